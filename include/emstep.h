@@ -1,0 +1,251 @@
+/*
+ * emstep.h -- C ABI of the step-based electromagnetic shower transport library
+ * for AMD MI355X (gfx950).
+ *
+ * The library implements the data-parallel hot path described in arXiv
+ * 2503.17608 ("Accelerating detector simulations with Celeritas"):
+ *
+ *   - a step-based transport loop ("Stepping algorithm"): the host runs a
+ *     loop of step iterations; each iteration is a sequence of kernels, one
+ *     per stepping action, over a fixed array of track slots stored as a
+ *     struct of arrays;
+ *   - secondaries are pushed to a buffer of lightweight track initializers
+ *     and vacant slots are filled from it at the start of every iteration;
+ *   - optional reordering of track slots by next action
+ *     ("Reindexing track slots") and optional partitioning of new tracks into
+ *     charged / neutral ends of the slot array ("Partitioning track data");
+ *   - a cap on field-propagation substeps per iteration after which a track's
+ *     step is paused and resumed ("Reducing load imbalance");
+ *   - stream-ordered memory operations only ("Asynchronous memory
+ *     management").
+ *
+ * The caller's sequence follows the statement of the problem: load geometry,
+ * materials and physics tables; push primaries; step until the slots are
+ * empty; read back energy deposition.
+ *
+ * Units: MeV (energies), cm (lengths), g/cm^3 (densities), tesla (field),
+ * eV (mean excitation energy only).
+ *
+ * Conventions for every entry point:
+ *   - all functions return ems_status (EMS_OK == 0 on success); no C++
+ *     exception crosses this interface; ems_last_error() gives a message for
+ *     the calling thread's last failure;
+ *   - host pointers are read (or written) before the call returns, and the
+ *     caller keeps ownership of them;
+ *   - `device_workspace` is device memory owned by the caller (e.g. one torch
+ *     uint8 tensor); it must stay allocated until ems_destroy();
+ *   - all device work is ordered on the HIP stream given to ems_create();
+ *     calls returning results to host memory synchronize that stream.
+ */
+#ifndef EMSTEP_H
+#define EMSTEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMS_ABI_VERSION 1u
+
+typedef enum {
+    EMS_OK = 0,
+    EMS_ERR_INVALID_ARG = -1,  /* bad pointer, size or value */
+    EMS_ERR_STATE = -2,        /* call out of order (e.g. push before load) */
+    EMS_ERR_CAPACITY = -3,     /* a buffer (initializers, primaries, event rows) is full */
+    EMS_ERR_DEVICE = -4,       /* a HIP call failed */
+    EMS_ERR_NUMERIC = -5,      /* non-finite value detected */
+    EMS_ERR_UNSUPPORTED = -6
+} ems_status;
+
+typedef enum { EMS_FP64 = 0, EMS_MIXED = 1 } ems_precision;
+typedef enum { EMS_SORT_NONE = 0, EMS_SORT_PARTITION = 1, EMS_SORT_RADIX = 2 } ems_sort_policy;
+typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_particle;
+
+/* Physics table layout (per material, in this order, 181 nodes each):
+ * Compton, photoelectric, pair, Moller, Bhabha, bremsstrahlung macroscopic
+ * cross sections [1/cm]; electron range, positron range [cm].  Nodes are at
+ * kinetic energies exp(ln(1e-3 MeV) + i ln(10)/20), i = 0..180. */
+#define EMS_TABLE_NODES 181
+#define EMS_TABLES_PER_MATERIAL 8
+
+typedef struct {
+    uint32_t abi_version;      /* must be EMS_ABI_VERSION */
+    int32_t precision;         /* ems_precision: FP64, or FP32 energies/directions/tables with FP64 positions */
+    uint64_t n_slots;          /* track slots (threads of the state arrays) */
+    uint64_t n_initializers;   /* capacity of the secondary initializer buffer */
+    uint64_t n_primaries;      /* capacity of the pending-primary buffer */
+    uint32_t max_events;       /* tally rows (events resident at once) */
+    uint32_t max_slabs;        /* capacity for geometry slabs */
+    uint32_t max_materials;    /* capacity for materials */
+    int32_t sort_policy;       /* ems_sort_policy, applied before the along-step and interaction kernels */
+    int32_t init_partition;    /* 1: new charged tracks fill vacancies from the low end, neutral from the high end */
+    int32_t max_substeps;      /* field substeps per track per iteration; <= 0 means unlimited */
+    uint64_t seed;             /* Philox key word 0 */
+    int32_t block_size;        /* threads per block for the step kernels; 0 = 256 */
+    int32_t graph_iterations;  /* iterations captured per HIP graph in ems_run; 0 = plain launches */
+} ems_options;
+
+typedef struct { double Z, A, density, I_eV; } ems_material;
+
+/* a primary track: `event` is the caller's event id (Philox key word 1) */
+typedef struct {
+    uint64_t event;
+    uint64_t key;              /* track key (Philox counter word 0) */
+    int32_t type;              /* ems_particle */
+    int32_t slab;              /* slab containing r (on a plane: the slab entered) */
+    double T;                  /* kinetic energy [MeV], must be >= the cut */
+    double r[3];
+    double u[3];               /* unit direction */
+} ems_primary;
+
+/* host view of one track slot (debug inject / read) */
+typedef struct {
+    uint64_t key;
+    uint32_t row;              /* tally row of the track's event */
+    uint32_t step;             /* completed steps */
+    int32_t type;              /* ems_particle, or -1 for a vacant slot */
+    int32_t slab;
+    double T;
+    double nl;                 /* remaining mean free paths, < 0 = to be sampled */
+    double r[3];
+    double u[3];
+} ems_track;
+
+typedef struct {
+    double escaped;            /* kinetic energy leaving the stack [MeV] */
+    uint64_t n_pair, n_annih, steps;
+    uint64_t n_sec[3];         /* secondaries created, by ems_particle */
+    uint64_t n_guard;          /* tracks stopped by the step guard */
+    uint64_t n_reject_cap;     /* rejection loops that hit their trial cap */
+} ems_ledger;
+
+typedef struct {
+    uint64_t iterations;       /* step iterations executed so far */
+    uint64_t alive;            /* live tracks at the start of the last iteration */
+    uint64_t queued;           /* secondary initializers waiting */
+    uint64_t pending_primaries;
+    uint64_t steps;            /* completed steps of tracks that have finished */
+    uint32_t overflow;         /* nonzero: the initializer buffer overflowed (results invalid) */
+    uint32_t pad;
+    /* cumulative tracks processed per kernel role: [1] init, [2] pre-step,
+     * [4] neutral, [5] charged, [6] field along-step (track-iterations),
+     * [7..12] Compton, photoelectric, pair, Moller, Bhabha, bremsstrahlung,
+     * [13] paused field steps, [14] field RK4 evaluations */
+    uint64_t work[16];
+} ems_counters;
+
+typedef struct ems_ctx ems_ctx;
+
+/* Library ABI version (EMS_ABI_VERSION). */
+uint32_t ems_abi_version(void);
+
+/* Message for the calling thread's most recent failure ("" if none).  The
+ * string is owned by the library and valid until the next call. */
+const char* ems_last_error(void);
+
+/* Bytes of device workspace needed for `opt`.  Errors: INVALID_ARG. */
+ems_status ems_query_workspace(const ems_options* opt, uint64_t* bytes);
+
+/* Create a context on the current HIP device.  `device_workspace` (>= the
+ * queried bytes, 256-byte aligned) and `hip_stream` (a hipStream_t, may be
+ * NULL for the null stream) are borrowed.  Errors: INVALID_ARG, DEVICE. */
+ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t bytes, void* hip_stream,
+                      ems_ctx** out);
+
+/* Release the context (not the caller's workspace). */
+void ems_destroy(ems_ctx* ctx);
+
+/* Materials (Z, A [g/mol], density, I [eV]); n <= max_materials. */
+ems_status ems_load_materials(ems_ctx* ctx, const ems_material* m, uint32_t n);
+
+/* Slab stack along z: z_planes[n_slabs + 1] strictly increasing, material
+ * index per slab, lateral half width (|x|, |y| <= half_width), uniform field
+ * B[3] in tesla.  Outside the stack is a kill region (escape). */
+ems_status ems_load_geometry(ems_ctx* ctx, const double* z_planes, const int32_t* slab_material,
+                             uint32_t n_slabs, double half_width, const double B[3]);
+
+/* Build the physics tables on the device from the loaded materials for the
+ * production/tracking cut `ecut` [MeV] (the same cut applies to delta rays,
+ * bremsstrahlung photons and all tracked particles).  Requires materials. */
+ems_status ems_build_tables(ems_ctx* ctx, double ecut);
+
+/* Load caller-provided tables instead: `tables` holds
+ * [n_materials][EMS_TABLES_PER_MATERIAL][EMS_TABLE_NODES] doubles in the
+ * layout described above; copied to the device. */
+ems_status ems_load_tables(ems_ctx* ctx, const double* tables, uint32_t n_materials, double ecut);
+
+/* Copy the device tables (FP64) to host `out` (same layout). */
+ems_status ems_read_tables(ems_ctx* ctx, double* out, uint64_t n_doubles);
+
+/* Queue primaries (copied to device).  Each event id is given a tally row on
+ * first sight.  Errors: STATE (nothing loaded), INVALID_ARG (bad type, slab,
+ * energy below the cut), CAPACITY (primary buffer or event rows full; nothing
+ * is queued in that case). */
+ems_status ems_push_primaries(ems_ctx* ctx, const ems_primary* p, uint64_t n);
+
+/* Enqueue `iterations` step iterations (asynchronous; no host wait).  If
+ * `out` is non-NULL, synchronizes and returns the counters after them. */
+ems_status ems_step(ems_ctx* ctx, uint32_t iterations, ems_counters* out);
+
+/* Step until no track is alive, queued or pending, or `max_iterations` is
+ * reached (then returns STATE).  The host polls device counters through a
+ * pinned buffer every `graph_iterations` (or 16) iterations.  Errors:
+ * CAPACITY if the initializer buffer overflowed. */
+ems_status ems_run(ems_ctx* ctx, uint64_t max_iterations, ems_counters* out);
+
+/* Synchronize and read the counters. */
+ems_status ems_read_counters(ems_ctx* ctx, ems_counters* out);
+
+/* Events whose tracks have all finished since the last poll (serving).
+ * Writes up to `cap` event ids to `events` and their count to *n. */
+ems_status ems_poll_completed(ems_ctx* ctx, uint64_t* events, uint32_t cap, uint32_t* n);
+
+/* Energy deposited per slab (n_slabs values) and the ledger of `event`. */
+ems_status ems_read_edep(ems_ctx* ctx, uint64_t event, double* per_slab, uint32_t n_slabs, ems_ledger* ledger);
+
+/* Read all tally rows at once: edep[max_events][n_slabs], ledgers[max_events]
+ * (either may be NULL), plus the event id of every row (row_event, may be
+ * NULL; unused rows hold UINT64_MAX). */
+ems_status ems_read_all_tallies(ems_ctx* ctx, double* edep, ems_ledger* ledgers, uint64_t* row_event);
+
+/* Free the tally row of a finished event and zero it for reuse. */
+ems_status ems_release_event(ems_ctx* ctx, uint64_t event);
+
+/* ---- test hooks ---------------------------------------------------------- */
+
+/* Give `event` a tally row (as ems_push_primaries would) and return it. */
+ems_status ems_debug_register_event(ems_ctx* ctx, uint64_t event, uint32_t* row);
+
+/* Overwrite slots [0, n) with `tracks` (rows from ems_debug_register_event,
+ * energies >= the cut), mark every other slot vacant and discard queued
+ * secondaries.  Errors: STATE, CAPACITY (n > n_slots), INVALID_ARG. */
+ems_status ems_debug_inject(ems_ctx* ctx, const ems_track* tracks, uint64_t n);
+
+/* Run `iterations` step iterations, skipping the slot initialization phase
+ * when `no_init` is nonzero (secondaries then stay in the initializer buffer). */
+ems_status ems_debug_iterate(ems_ctx* ctx, uint32_t iterations, int32_t no_init);
+
+/* Read slots [0, n) into `tracks`. */
+ems_status ems_debug_read_tracks(ems_ctx* ctx, ems_track* tracks, uint64_t n);
+
+/* Read the secondary initializer buffer (up to cap entries) as tracks; *n
+ * receives the number queued. */
+ems_status ems_debug_read_secondaries(ems_ctx* ctx, ems_track* out, uint64_t cap, uint64_t* n);
+
+/* Stable sort of n small keys (< 256) on the device with `policy`
+ * (PARTITION: keys < 16; RADIX: keys < 256); perm[i] = index of the i-th
+ * smallest key, equal keys in index order. */
+ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm);
+
+/* Average duration [ms] of each kernel over the iterations launched since the
+ * last call, measured with HIP events around every launch on the library's
+ * stream when `enable` was set; names are fixed kernel-role strings. */
+ems_status ems_profile_enable(ems_ctx* ctx, int32_t enable);
+ems_status ems_profile_read(ems_ctx* ctx, const char** names, double* total_ms, uint64_t* launches, uint32_t cap,
+                            uint32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMSTEP_H */

@@ -1,0 +1,198 @@
+// Shared host/device definitions of the step-loop library: state layout,
+// action codes, counters and small device helpers.
+//
+// Track state is a struct of arrays over n_slots (paper, "Stepping
+// algorithm"): every per-track quantity is its own array so that a kernel
+// reading one field streams it contiguously from HBM.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ems {
+
+// ---- physical constants (CODATA 2018) ---------------------------------------
+constexpr double kMe = 0.51099895;            // electron rest energy [MeV]
+constexpr double kRe = 2.8179403262e-13;      // classical electron radius [cm]
+constexpr double kAlpha = 1.0 / 137.035999084;
+constexpr double kNA = 6.02214076e23;         // [1/mol]
+constexpr double kCk = 2.99792458;            // p[MeV] = kCk * B[T] * radius[cm]
+constexpr double kPlasma = 28.816;            // hbar omega_p = 28.816 sqrt(rho Z / A) eV
+constexpr double kPi = 3.14159265358979323846;
+
+// ---- transport parameters -----------------------------------------------------
+constexpr int kNodes = 181;                   // table nodes: 1 keV .. 1 TeV, 20 per decade
+constexpr int kTabPerMat = 8;
+constexpr double kEmin = 1.0e-3;
+constexpr double kRhoRange = 0.2;             // step <= rho * range ...
+constexpr double kRFinal = 0.01;              // ... but not below r_f [cm]
+constexpr double kDChord = 0.0025;            // field substep sagitta [cm]
+constexpr double kDInt = 1.0e-5;              // boundary-search tolerance [cm]
+constexpr int kMaxSearch = 10;
+constexpr int kMaxTrials = 1000;
+constexpr uint32_t kMaxSteps = 1000000u;
+
+// table indices within a material
+enum : int { TB_COMPTON = 0, TB_PHOTO, TB_PAIR, TB_MOLLER, TB_BHABHA, TB_BREMS, TB_RANGE_EM, TB_RANGE_EP };
+// particle types stored in the state; kDead marks a vacant slot
+enum : uint8_t { kGamma = 0, kElectron = 1, kPositron = 2, kDead = 3 };
+// processes
+enum : int { P_COMPTON = 0, P_PHOTO, P_PAIR, P_MOLLER, P_BHABHA, P_BREMS, kNumProc };
+
+// Next-action codes (the sort key).  Along-step actions are set by the
+// pre-step kernel, interaction actions by the along-step kernels.
+enum : uint8_t {
+    A_IDLE = 0,        // alive, no work this phase
+    A_NEUTRAL = 1,     // straight-line along-step of a photon
+    A_CHARGED = 2,     // straight-line along-step with continuous loss (no field)
+    A_FIELD = 3,       // field propagation (also a paused step)
+    A_PROC0 = 4,       // + process index: discrete interaction
+    A_NUM = A_PROC0 + kNumProc,
+    A_NONE = 0xFF      // vacant slot
+};
+
+// flags byte
+enum : uint8_t {
+    F_DREW = 1,        // the interaction-length uniform (index 0) was drawn this step
+    F_LOSS = 2,        // the physics step limit is the energy-loss limit
+    F_PAUSED = 4,      // field step paused at the substep cap
+};
+
+// faces of a slab box
+enum : int { F_NONE = 0, F_ZLO, F_ZHI, F_XLO, F_XHI, F_YLO, F_YHI };
+
+// Track initializer: the minimal record to start a track (paper, "Stepping
+// algorithm").  80 bytes, written by interaction kernels and read once by the
+// initialization kernel; records are contiguous per wave.
+struct alignas(16) Initializer {
+    double T;
+    double r[3];
+    double u[3];
+    uint64_t key;
+    uint32_t row;
+    uint16_t slab;
+    uint8_t type;
+    uint8_t pad;
+};
+static_assert(sizeof(Initializer) == 80, "initializer layout");
+
+// per-event ledger (same layout as ems_ledger)
+struct Ledger {
+    double escaped;
+    unsigned long long n_pair, n_annih, steps;
+    unsigned long long n_sec[3];
+    unsigned long long n_guard, n_reject_cap;
+};
+static_assert(sizeof(Ledger) == 72, "ledger layout");
+
+// device-resident loop counters
+struct Counters {
+    unsigned long long queue_size;     // secondaries waiting in the initializer buffer
+    unsigned long long prim_next;      // next pending primary
+    unsigned long long prim_end;       // end of pushed primaries
+    unsigned long long iterations;
+    unsigned long long steps_done;     // completed steps of finished tracks
+    unsigned int n_vac;                // vacancies found this iteration
+    unsigned int n_alive;              // live tracks at the start of this iteration
+    unsigned int overflow;
+    unsigned int n_take_q;             // initializers taken from the queue this iteration
+    unsigned int n_take_p;             // primaries taken this iteration
+    unsigned int n_charged_taken;      // for the partitioned fill
+    unsigned long long q_base;         // first queue index taken (top - n_take_q)
+    unsigned long long p_base;
+    unsigned int range_off[16];        // sorted mode: start of each action's index range
+    unsigned int range_cnt[16];
+    unsigned long long work[16];       // tracks processed per kernel role (see W_*)
+};
+
+// work counter indices
+enum : int {
+    W_INIT = 1, W_PRE = 2, W_SORT = 3, W_NEUTRAL = 4, W_CHARGED = 5, W_FIELD = 6, W_PROC0 = 7,
+    W_PAUSED = 13, W_SUBSTEPS = 14
+};
+
+// Host-visible snapshot copied to pinned memory after each batch
+struct Snapshot {
+    unsigned long long queue_size, prim_next, prim_end, iterations, steps_done;
+    unsigned int n_vac, n_alive, overflow, pad;
+    unsigned long long work[16];
+};
+
+// ---- Philox4x64-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers:
+// as easy as 1, 2, 3", SC'11) ----------------------------------------------------
+struct U64x4 { uint64_t w[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+        uint64_t lo0 = m0 * c0, hi0 = __umul64hi(m0, c0);
+        uint64_t lo1 = m1 * c2, hi1 = __umul64hi(m1, c2);
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ULL;
+        k1 += 0xBB67AE8584CAA73BULL;
+    }
+    U64x4 o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+template <class R> __device__ __forceinline__ R unit_from(uint64_t w);
+template <> __device__ __forceinline__ double unit_from<double>(uint64_t w)
+{
+    return ((double)(w >> 12) + 0.5) * 0x1p-52;
+}
+template <> __device__ __forceinline__ float unit_from<float>(uint64_t w)
+{
+    return ((float)(uint32_t)(w >> 41) + 0.5f) * 0x1p-23f;
+}
+
+// Uniforms of one track step: uniform j is word j&3 of the Philox block
+// (key, step, j>>2, domain 0) under key (seed, event).
+template <class R>
+struct StepRng {
+    uint64_t k0, k1, key, step;
+    int j;
+    int have;          // block index cached in buf, -1 none
+    uint64_t buf[4];
+    __device__ StepRng(uint64_t seed, uint64_t event, uint64_t track_key, uint64_t step_, int j0)
+        : k0(seed), k1(event), key(track_key), step(step_), j(j0), have(-1) {}
+    __device__ __forceinline__ R next()
+    {
+        int b = j >> 2;
+        if (b != have) {
+            U64x4 o = philox4x64_10(key, step, (uint64_t)b, 0, k0, k1);
+            buf[0] = o.w[0]; buf[1] = o.w[1]; buf[2] = o.w[2]; buf[3] = o.w[3];
+            have = b;
+        }
+        uint64_t w = buf[j & 3];
+        ++j;
+        return unit_from<R>(w);
+    }
+};
+
+__device__ __forceinline__ uint64_t child_key(uint64_t seed, uint64_t event, uint64_t key, uint64_t step, int ordinal)
+{
+    return philox4x64_10(key, step, (uint64_t)ordinal, 1, seed, event).w[0];
+}
+
+// ---- math wrappers per precision ------------------------------------------------
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_floor(double x) { return floor(x); }
+__device__ __forceinline__ float m_floor(float x) { return floorf(x); }
+__device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void m_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ double m_max(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float m_max(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double m_min(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float m_min(float a, float b) { return fminf(a, b); }
+
+}  // namespace ems

@@ -1,0 +1,1061 @@
+// Host driver and C ABI of the step-based EM shower transport library.
+//
+// The host runs the outer loop of step iterations (paper, "Stepping
+// algorithm"); each iteration launches, in stream order:
+//   vacancy count / scatter  -> initialization (optionally partitioned)
+//   -> pre-step -> [sort point 1] -> along-step (neutral, charged, field)
+//   -> [sort point 2] -> six interaction kernels.
+// Loop termination is read from device counters copied asynchronously to a
+// pinned host buffer after every batch of iterations; batches can be captured
+// once into a HIP graph and replayed.  No synchronous memory operation is
+// issued inside the loop (paper, "Asynchronous memory management").
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/emstep.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "tables_build.hpp"
+
+using namespace ems;
+
+namespace {
+
+thread_local std::string g_err;
+
+ems_status fail(ems_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return fail(EMS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+    } while (0)
+
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+// Workspace layout: every region 256-byte aligned, offsets from the base.
+struct Layout {
+    uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
+    uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, sort_cnt, bin_off, ctr;
+    uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, incr;
+    uint64_t total;
+    uint32_t n_tiles;
+};
+
+Layout make_layout(const ems_options& o)
+{
+    Layout L{};
+    uint64_t off = 0;
+    const uint64_t n = o.n_slots;
+    const uint64_t rb = o.precision == EMS_MIXED ? 4 : 8;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L.type = take(n);
+    L.action = take(n);
+    L.flags = take(n);
+    L.nsearch = take(n);
+    L.slab = take(2 * n);
+    L.row = take(4 * n);
+    L.step = take(4 * n);
+    L.key = take(8 * n);
+    L.T = take(rb * n);
+    L.nl = take(rb * n);
+    L.xs = take(rb * n);
+    L.sphys = take(8 * n);
+    L.sdone = take(8 * n);
+    L.htry = take(8 * n);
+    L.x = take(8 * n);
+    L.y = take(8 * n);
+    L.z = take(8 * n);
+    L.ux = take(rb * n);
+    L.uy = take(rb * n);
+    L.uz = take(rb * n);
+    L.queue = take(sizeof(Initializer) * o.n_initializers);
+    L.prims = take(sizeof(Initializer) * o.n_primaries);
+    L.vac = take(4 * n);
+    uint64_t nvb = (n + kVacBlock - 1) / kVacBlock;
+    L.vac_cnt = take(4 * nvb);
+    L.init_cnt = take(4 * nvb);
+    L.perm = take(4 * n);
+    L.n_tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    L.sort_cnt = take(4ull * 128 * L.n_tiles);
+    L.bin_off = take(4 * 256);
+    L.ctr = take(sizeof(Counters));
+    uint64_t ntab = (uint64_t)o.max_materials * kTabPerMat * kNodes;
+    L.tables64 = take(8 * ntab);
+    L.tables32 = take(4 * ntab);
+    L.mats = take(sizeof(MatDev) * o.max_materials);
+    L.zp = take(8 * ((uint64_t)o.max_slabs + 1));
+    L.smat = take(4 * (uint64_t)o.max_slabs);
+    L.row_event = take(8 * (uint64_t)o.max_events);
+    L.edep = take(8 * (uint64_t)o.max_events * o.max_slabs);
+    L.ledger = take(sizeof(Ledger) * (uint64_t)o.max_events);
+    L.incr = take(8ull * o.max_materials * 2 * (kNodes - 1));
+    L.total = off;
+    return L;
+}
+
+enum Role {
+    R_VAC = 0, R_INIT, R_PRE, R_SORT, R_ALONG_NEUTRAL, R_ALONG_CHARGED, R_ALONG_FIELD,
+    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_NUM
+};
+const char* kRoleNames[R_NUM] = {"vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged",
+                                 "along_field", "compton", "photoelectric", "pair", "moller", "bhabha",
+                                 "bremsstrahlung"};
+
+}  // namespace
+
+struct ems_ctx {
+    ems_options opt;
+    Layout L;
+    char* ws;
+    hipStream_t stream;
+    int device;
+    // host mirrors
+    uint32_t n_materials = 0, n_slabs = 0;
+    bool have_mats = false, have_geom = false, have_tables = false;
+    double ecut = 0.0, half_width = 0.0, B[3] = {0, 0, 0};
+    double ln_e0, dlog;
+    std::vector<ems_material> mats;
+    // events
+    std::unordered_map<uint64_t, uint32_t> row_of;
+    std::vector<uint64_t> row_event;           // host copy, UINT64_MAX = free
+    std::vector<uint32_t> free_rows;
+    std::vector<uint64_t> row_pending;         // primaries pushed per row (for completion)
+    // primaries ring
+    uint64_t prim_end = 0;                     // host-owned
+    // pinned host memory
+    Snapshot* snap = nullptr;                  // ring of snapshots
+    int snap_slots = 4;
+    hipEvent_t snap_ev[4];
+    uint64_t snap_seq = 0;
+    Initializer* staging = nullptr;            // pinned primary staging
+    uint64_t staging_cap = 0;
+    hipEvent_t staging_ev;
+    bool staging_busy = false;
+    // graphs
+    hipGraphExec_t graph = nullptr;
+    int graph_iters = 0;
+    int graph_no_init = -1;
+    // profiling
+    uint32_t prof_mask = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+    double prof_ms[R_NUM] = {0};
+    uint64_t prof_n[R_NUM] = {0};
+    Snapshot last{};
+};
+
+namespace {
+
+template <class R>
+Dev<R> make_dev(const ems_ctx* c)
+{
+    Dev<R> d{};
+    char* b = c->ws;
+    const Layout& L = c->L;
+    d.type = (uint8_t*)(b + L.type);
+    d.action = (uint8_t*)(b + L.action);
+    d.flags = (uint8_t*)(b + L.flags);
+    d.nsearch = (uint8_t*)(b + L.nsearch);
+    d.slab = (uint16_t*)(b + L.slab);
+    d.row = (uint32_t*)(b + L.row);
+    d.step = (uint32_t*)(b + L.step);
+    d.key = (uint64_t*)(b + L.key);
+    d.T = (R*)(b + L.T);
+    d.nl = (R*)(b + L.nl);
+    d.xs = (R*)(b + L.xs);
+    d.sphys = (double*)(b + L.sphys);
+    d.sdone = (double*)(b + L.sdone);
+    d.htry = (double*)(b + L.htry);
+    d.x = (double*)(b + L.x);
+    d.y = (double*)(b + L.y);
+    d.z = (double*)(b + L.z);
+    d.ux = (R*)(b + L.ux);
+    d.uy = (R*)(b + L.uy);
+    d.uz = (R*)(b + L.uz);
+    d.n_slots = (uint32_t)c->opt.n_slots;
+    d.queue = (Initializer*)(b + L.queue);
+    d.queue_cap = c->opt.n_initializers;
+    d.prims = (Initializer*)(b + L.prims);
+    d.prim_cap = c->opt.n_primaries;
+    d.vac = (uint32_t*)(b + L.vac);
+    d.vac_cnt = (uint32_t*)(b + L.vac_cnt);
+    d.init_cnt = (uint32_t*)(b + L.init_cnt);
+    d.perm = (uint32_t*)(b + L.perm);
+    d.ctr = (Counters*)(b + L.ctr);
+    d.tb.v = (const R*)(b + (sizeof(R) == 8 ? L.tables64 : L.tables32));
+    d.tb.ln_e0 = (R)c->ln_e0;
+    d.tb.dlog = (R)c->dlog;
+    d.tb.inv_dlog = (R)(1.0 / c->dlog);
+    d.zp = (const double*)(b + L.zp);
+    d.smat = (const int32_t*)(b + L.smat);
+    d.n_slabs = (int)c->n_slabs;
+    d.W = c->half_width;
+    d.B[0] = c->B[0]; d.B[1] = c->B[1]; d.B[2] = c->B[2];
+    d.has_field = (c->B[0] != 0.0 || c->B[1] != 0.0 || c->B[2] != 0.0);
+    d.ecut = c->ecut;
+    d.seed = c->opt.seed;
+    d.row_event = (const uint64_t*)(b + L.row_event);
+    d.edep = (double*)(b + L.edep);
+    d.ledger = (Ledger*)(b + L.ledger);
+    d.edep_stride = (int)c->opt.max_slabs;
+    d.max_substeps = c->opt.max_substeps;
+    d.sorted = c->opt.sort_policy != EMS_SORT_NONE;
+    return d;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, uint64_t n)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_zero_bytes(uint8_t* p, uint64_t n)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_set_prim_end(Counters* c, unsigned long long v) { c->prim_end = v; }
+
+__global__ void k_reset_queue(Counters* c)
+{
+    c->queue_size = 0;
+    c->overflow = 0;
+}
+
+__global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double* edep, Ledger* led, uint32_t n_slabs)
+{
+    // register an event on a row and clear the row's tallies
+    for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)row * n_slabs + i] = 0.0;
+    if (threadIdx.x == 0) {
+        row_event[row] = ev;
+        led[row] = Ledger{};
+    }
+}
+
+__global__ void k_snapshot(const Counters* c, Snapshot* out)
+{
+    Snapshot s;
+    s.queue_size = c->queue_size;
+    s.prim_next = c->prim_next;
+    s.prim_end = c->prim_end;
+    s.iterations = c->iterations;
+    s.steps_done = c->steps_done;
+    s.n_vac = c->n_vac;
+    s.n_alive = c->n_alive;
+    s.overflow = c->overflow;
+    s.pad = 0;
+    for (int i = 0; i < 16; ++i) s.work[i] = c->work[i];
+    *out = s;
+}
+
+uint32_t grid_for(uint64_t n, int bs)
+{
+    uint64_t g = (n + bs - 1) / bs;
+    const uint64_t cap = 256 * 8;   // 256 CUs x 8 resident blocks: grid-stride beyond that
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return (uint32_t)g;
+}
+
+struct Launcher {
+    ems_ctx* c;
+    bool prof;
+    template <class F>
+    void run(int role, F&& f)
+    {
+        if (prof && (c->prof_mask & (1u << role))) {
+            hipEvent_t a, b;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            (void)hipEventRecord(a, c->stream);
+            f();
+            (void)hipEventRecord(b, c->stream);
+            c->prof_events.push_back({role, {a, b}});
+        } else {
+            f();
+        }
+    }
+};
+
+template <class R>
+void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
+{
+    const int policy = c->opt.sort_policy;
+    uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
+    uint32_t nt = c->L.n_tiles;
+    uint32_t n = d.n_slots;
+    ln.run(R_SORT, [&] {
+        if (policy == EMS_SORT_PARTITION) {
+            hipLaunchKernelGGL((k_sort_hist<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n, cnt, nt);
+            hipLaunchKernelGGL((k_sort_scan<16>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, d.ctr, 0, nullptr);
+            hipLaunchKernelGGL((k_sort_scatter<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n,
+                               cnt, nt, d.perm);
+        } else {
+            hipLaunchKernelGGL((k_sort_hist<R, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, nullptr, n, cnt, nt);
+            hipLaunchKernelGGL((k_sort_scan<128>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, d.ctr, 1, nullptr);
+            hipLaunchKernelGGL((k_sort_scatter<R, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, nullptr, n,
+                               cnt, nt, d.perm);
+        }
+    });
+}
+
+template <class R>
+void launch_iteration(ems_ctx* c, bool no_init, bool prof)
+{
+    Dev<R> d = make_dev<R>(c);
+    Launcher ln{c, prof};
+    const int bs = c->opt.block_size > 0 ? c->opt.block_size : 256;
+    const uint32_t n = d.n_slots;
+    const uint32_t nvb = (n + kVacBlock - 1) / kVacBlock;
+    const uint32_t g = grid_for(n, bs);
+    hipStream_t st = c->stream;
+    ln.run(R_VAC, [&] {
+        hipLaunchKernelGGL((k_vac_count<R>), dim3(nvb), dim3(kVacBlock), 0, st, d);
+        hipLaunchKernelGGL((k_vac_scatter<R>), dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1);
+    });
+    if (!no_init) {
+        ln.run(R_INIT, [&] {
+            if (c->opt.init_partition) {
+                hipLaunchKernelGGL((k_init_count<R>), dim3(nvb), dim3(kVacBlock), 0, st, d);
+                hipLaunchKernelGGL((k_init<R, true>), dim3(nvb), dim3(kVacBlock), 0, st, d);
+            } else {
+                hipLaunchKernelGGL((k_init<R, false>), dim3(nvb), dim3(kVacBlock), 0, st, d);
+            }
+        });
+    }
+    ln.run(R_PRE, [&] { hipLaunchKernelGGL((k_pre_step<R>), dim3(g), dim3(bs), 0, st, d); });
+    if (d.sorted) launch_sort<R>(c, d, ln);
+    ln.run(R_ALONG_NEUTRAL, [&] { hipLaunchKernelGGL((k_along_straight<R, false>), dim3(g), dim3(bs), 0, st, d); });
+    if (d.has_field)
+        ln.run(R_ALONG_FIELD, [&] { hipLaunchKernelGGL((k_along_field<R>), dim3(g), dim3(bs), 0, st, d); });
+    else
+        ln.run(R_ALONG_CHARGED, [&] { hipLaunchKernelGGL((k_along_straight<R, true>), dim3(g), dim3(bs), 0, st, d); });
+    if (d.sorted) launch_sort<R>(c, d, ln);
+    ln.run(R_COMPTON, [&] { hipLaunchKernelGGL((k_interact<R, P_COMPTON>), dim3(g), dim3(bs), 0, st, d); });
+    ln.run(R_PHOTO, [&] { hipLaunchKernelGGL((k_interact<R, P_PHOTO>), dim3(g), dim3(bs), 0, st, d); });
+    ln.run(R_PAIR, [&] { hipLaunchKernelGGL((k_interact<R, P_PAIR>), dim3(g), dim3(bs), 0, st, d); });
+    ln.run(R_MOLLER, [&] { hipLaunchKernelGGL((k_interact<R, P_MOLLER>), dim3(g), dim3(bs), 0, st, d); });
+    ln.run(R_BHABHA, [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(g), dim3(bs), 0, st, d); });
+    ln.run(R_BREMS, [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(g), dim3(bs), 0, st, d); });
+}
+
+void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
+{
+    if (c->opt.precision == EMS_MIXED) launch_iteration<float>(c, no_init, prof);
+    else launch_iteration<double>(c, no_init, prof);
+}
+
+ems_status check_ready(ems_ctx* c)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
+    if (!c->have_geom || !c->have_tables || !c->have_mats)
+        return fail(EMS_ERR_STATE, "materials, geometry and tables must be loaded first");
+    return EMS_OK;
+}
+
+ems_status drop_graph(ems_ctx* c)
+{
+    if (c->graph) {
+        HIP_TRY(hipGraphExecDestroy(c->graph));
+        c->graph = nullptr;
+    }
+    return EMS_OK;
+}
+
+// launch `iters` iterations, through a captured graph when configured
+ems_status launch_batch(ems_ctx* c, int iters, bool no_init)
+{
+    bool prof = c->prof_mask != 0;
+    int gi = c->opt.graph_iterations;
+    if (gi > 0 && !prof && iters == gi) {
+        if (!c->graph || c->graph_iters != gi || c->graph_no_init != (int)no_init) {
+            ems_status s = drop_graph(c);
+            if (s != EMS_OK) return s;
+            hipGraph_t g;
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < gi; ++i) launch_iteration_any(c, no_init, false);
+            HIP_TRY(hipStreamEndCapture(c->stream, &g));
+            HIP_TRY(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+            HIP_TRY(hipGraphDestroy(g));
+            c->graph_iters = gi;
+            c->graph_no_init = (int)no_init;
+        }
+        HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+    } else {
+        for (int i = 0; i < iters; ++i) launch_iteration_any(c, no_init, prof);
+        HIP_TRY(hipGetLastError());
+    }
+    return EMS_OK;
+}
+
+ems_status snapshot_now(ems_ctx* c, Snapshot* out)
+{
+    Snapshot* slot = &c->snap[0];
+    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, c->stream, (const Counters*)(c->ws + c->L.ctr), slot);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = *slot;
+    c->last = *out;
+    return EMS_OK;
+}
+
+void to_counters(const Snapshot& s, ems_counters* out)
+{
+    out->iterations = s.iterations;
+    out->alive = s.n_alive;
+    out->queued = s.queue_size;
+    out->pending_primaries = s.prim_end - s.prim_next;
+    out->steps = s.steps_done;
+    out->overflow = s.overflow;
+    out->pad = 0;
+    for (int i = 0; i < 16; ++i) out->work[i] = s.work[i];
+}
+
+template <class R>
+__global__ void k_inject(Dev<R> d, const ems_track* t, uint64_t n)
+{
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= d.n_slots) return;
+    if (i >= n || t[i].type < 0) {
+        d.type[i] = kDead;
+        d.action[i] = A_NONE;
+        return;
+    }
+    const ems_track& r = t[i];
+    d.type[i] = (uint8_t)r.type;
+    d.action[i] = A_IDLE;
+    d.flags[i] = 0;
+    d.nsearch[i] = 0;
+    d.slab[i] = (uint16_t)r.slab;
+    d.row[i] = r.row;
+    d.step[i] = r.step;
+    d.key[i] = r.key;
+    d.T[i] = (R)r.T;
+    d.nl[i] = (R)r.nl;
+    d.xs[i] = R(0);
+    d.sphys[i] = 0.0;
+    d.sdone[i] = 0.0;
+    d.htry[i] = 0.0;
+    d.x[i] = r.r[0]; d.y[i] = r.r[1]; d.z[i] = r.r[2];
+    d.ux[i] = (R)r.u[0]; d.uy[i] = (R)r.u[1]; d.uz[i] = (R)r.u[2];
+}
+
+template <class R>
+__global__ void k_read_tracks(Dev<R> d, ems_track* t, uint64_t n)
+{
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ems_track& r = t[i];
+    r.key = d.key[i];
+    r.row = d.row[i];
+    r.step = d.step[i];
+    r.type = d.type[i] == kDead ? -1 : (int32_t)d.type[i];
+    r.slab = d.slab[i];
+    r.T = (double)d.T[i];
+    r.nl = (double)d.nl[i];
+    r.r[0] = d.x[i]; r.r[1] = d.y[i]; r.r[2] = d.z[i];
+    r.u[0] = (double)d.ux[i]; r.u[1] = (double)d.uy[i]; r.u[2] = (double)d.uz[i];
+}
+
+__global__ void k_read_queue(const Initializer* q, uint64_t n, ems_track* t)
+{
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Initializer& a = q[i];
+    ems_track& r = t[i];
+    r.key = a.key;
+    r.row = a.row;
+    r.step = 0;
+    r.type = a.type;
+    r.slab = a.slab;
+    r.T = a.T;
+    r.nl = -1.0;
+    r.r[0] = a.r[0]; r.r[1] = a.r[1]; r.r[2] = a.r[2];
+    r.u[0] = a.u[0]; r.u[1] = a.u[1]; r.u[2] = a.u[2];
+}
+
+ems_status assign_row(ems_ctx* c, uint64_t ev, uint32_t* row)
+{
+    auto it = c->row_of.find(ev);
+    if (it != c->row_of.end()) {
+        *row = it->second;
+        return EMS_OK;
+    }
+    if (c->free_rows.empty()) return fail(EMS_ERR_CAPACITY, "no free event row (max_events)");
+    uint32_t r = c->free_rows.back();
+    c->free_rows.pop_back();
+    c->row_of[ev] = r;
+    c->row_event[r] = ev;
+    hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), r, ev,
+                       (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs);
+    HIP_TRY(hipGetLastError());
+    *row = r;
+    return EMS_OK;
+}
+
+}  // namespace
+
+// =============================================================================== ABI
+extern "C" {
+
+uint32_t ems_abi_version(void) { return EMS_ABI_VERSION; }
+
+const char* ems_last_error(void) { return g_err.c_str(); }
+
+static ems_status validate(const ems_options* o)
+{
+    if (!o) return fail(EMS_ERR_INVALID_ARG, "null options");
+    if (o->abi_version != EMS_ABI_VERSION) return fail(EMS_ERR_INVALID_ARG, "abi_version mismatch");
+    if (o->precision != EMS_FP64 && o->precision != EMS_MIXED) return fail(EMS_ERR_INVALID_ARG, "precision");
+    if (o->n_slots == 0 || o->n_slots > (1ull << 30)) return fail(EMS_ERR_INVALID_ARG, "n_slots must be in [1, 2^30]");
+    if (o->n_initializers == 0 || o->n_primaries == 0) return fail(EMS_ERR_INVALID_ARG, "buffer capacities");
+    if (o->max_events == 0 || o->max_slabs == 0 || o->max_slabs > 65534 || o->max_materials == 0)
+        return fail(EMS_ERR_INVALID_ARG, "max_events / max_slabs / max_materials");
+    if (o->sort_policy < 0 || o->sort_policy > 2) return fail(EMS_ERR_INVALID_ARG, "sort_policy");
+    int bs = o->block_size;
+    if (bs != 0 && (bs < 64 || bs > 1024 || (bs % 64) != 0)) return fail(EMS_ERR_INVALID_ARG, "block_size");
+    if (o->graph_iterations < 0) return fail(EMS_ERR_INVALID_ARG, "graph_iterations");
+    return EMS_OK;
+}
+
+ems_status ems_query_workspace(const ems_options* opt, uint64_t* bytes)
+{
+    ems_status s = validate(opt);
+    if (s != EMS_OK) return s;
+    if (!bytes) return fail(EMS_ERR_INVALID_ARG, "null bytes");
+    *bytes = make_layout(*opt).total;
+    return EMS_OK;
+}
+
+ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t bytes, void* hip_stream, ems_ctx** out)
+{
+    ems_status s = validate(opt);
+    if (s != EMS_OK) return s;
+    if (!device_workspace || !out) return fail(EMS_ERR_INVALID_ARG, "null workspace or out");
+    if (((uintptr_t)device_workspace & 255) != 0) return fail(EMS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    Layout L = make_layout(*opt);
+    if (bytes < L.total) return fail(EMS_ERR_INVALID_ARG, "workspace too small");
+    ems_ctx* c = new ems_ctx();
+    c->opt = *opt;
+    c->L = L;
+    c->ws = (char*)device_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->ln_e0 = std::log(kEmin);
+    c->dlog = std::log(10.0) / 20.0;
+    (void)hipGetDevice(&c->device);
+    c->row_event.assign(opt->max_events, UINT64_MAX);
+    c->row_pending.assign(opt->max_events, 0);
+    for (uint32_t r = opt->max_events; r > 0; --r) c->free_rows.push_back(r - 1);
+    auto cleanup = [&](ems_status st) { ems_destroy(c); return st; };
+    if (hipHostMalloc((void**)&c->snap, sizeof(Snapshot) * c->snap_slots, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc snapshot"));
+    for (int i = 0; i < c->snap_slots; ++i) (void)hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming);
+    c->staging_cap = 1 << 16;
+    if (hipHostMalloc((void**)&c->staging, sizeof(Initializer) * c->staging_cap, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc staging"));
+    (void)hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming);
+    // clear state: all slots vacant, counters and tallies zero, rows unassigned
+    uint64_t n = opt->n_slots;
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, (uint8_t*)(c->ws + L.type), kDead, n);
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, (uint8_t*)(c->ws + L.action), A_NONE, n);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(256), 0, c->stream, (uint8_t*)(c->ws + L.ctr), (uint64_t)sizeof(Counters));
+    uint64_t tb = L.incr - L.row_event;   // row_event, edep, ledger are contiguous
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(8ull * opt->max_events, 256)), dim3(256), 0, c->stream,
+                       (uint8_t*)(c->ws + L.row_event), (uint8_t)0xFF, 8ull * opt->max_events);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(grid_for(tb, 256)), dim3(256), 0, c->stream, (uint8_t*)(c->ws + L.edep),
+                       L.incr - L.edep);
+    if (hipGetLastError() != hipSuccess) return cleanup(fail(EMS_ERR_DEVICE, "initial clear failed"));
+    *out = c;
+    return EMS_OK;
+}
+
+void ems_destroy(ems_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (auto& e : c->prof_events) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    if (c->snap) {
+        (void)hipHostFree(c->snap);
+        for (int i = 0; i < c->snap_slots; ++i) (void)hipEventDestroy(c->snap_ev[i]);
+    }
+    if (c->staging) {
+        (void)hipHostFree(c->staging);
+        (void)hipEventDestroy(c->staging_ev);
+    }
+    delete c;
+}
+
+ems_status ems_load_materials(ems_ctx* c, const ems_material* m, uint32_t n)
+{
+    if (!c || !m || n == 0) return fail(EMS_ERR_INVALID_ARG, "null or empty materials");
+    if (n > c->opt.max_materials) return fail(EMS_ERR_CAPACITY, "too many materials");
+    std::vector<MatDev> md(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!(m[i].Z > 0 && m[i].A > 0 && m[i].density > 0 && m[i].I_eV > 0))
+            return fail(EMS_ERR_INVALID_ARG, "material values must be positive");
+        md[i] = MatDev{m[i].Z, m[i].A, m[i].density, m[i].I_eV};
+    }
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.mats, md.data(), sizeof(MatDev) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->mats.assign(m, m + n);
+    c->n_materials = n;
+    c->have_mats = true;
+    c->have_tables = false;
+    return drop_graph(c);
+}
+
+ems_status ems_load_geometry(ems_ctx* c, const double* zp, const int32_t* sm, uint32_t n_slabs, double half_width,
+                             const double B[3])
+{
+    if (!c || !zp || !sm || !B || n_slabs == 0) return fail(EMS_ERR_INVALID_ARG, "null geometry");
+    if (n_slabs > c->opt.max_slabs) return fail(EMS_ERR_CAPACITY, "too many slabs");
+    if (!c->have_mats) return fail(EMS_ERR_STATE, "load materials first");
+    for (uint32_t i = 0; i < n_slabs; ++i) {
+        if (!(zp[i + 1] > zp[i])) return fail(EMS_ERR_INVALID_ARG, "z planes must increase");
+        if (sm[i] < 0 || (uint32_t)sm[i] >= c->n_materials) return fail(EMS_ERR_INVALID_ARG, "slab material index");
+    }
+    if (!(half_width > 0)) return fail(EMS_ERR_INVALID_ARG, "half_width");
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.zp, zp, 8ull * (n_slabs + 1), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.smat, sm, 4ull * n_slabs, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->n_slabs = n_slabs;
+    c->half_width = half_width;
+    c->B[0] = B[0]; c->B[1] = B[1]; c->B[2] = B[2];
+    c->have_geom = true;
+    return drop_graph(c);
+}
+
+static ems_status finish_tables(ems_ctx* c, double ecut)
+{
+    uint64_t ntab = (uint64_t)c->n_materials * kTabPerMat * kNodes;
+    hipLaunchKernelGGL(k_tables_to_f32, dim3((ntab + 255) / 256), dim3(256), 0, c->stream,
+                       (const double*)(c->ws + c->L.tables64), (float*)(c->ws + c->L.tables32), (int)ntab);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->ecut = ecut;
+    c->have_tables = true;
+    return drop_graph(c);
+}
+
+ems_status ems_build_tables(ems_ctx* c, double ecut)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
+    if (!c->have_mats) return fail(EMS_ERR_STATE, "load materials first");
+    if (!(ecut > kEmin && ecut < 1.0e5)) return fail(EMS_ERR_INVALID_ARG, "cut outside the table range");
+    int nm = (int)c->n_materials;
+    const MatDev* md = (const MatDev*)(c->ws + c->L.mats);
+    double* t64 = (double*)(c->ws + c->L.tables64);
+    double* incr = (double*)(c->ws + c->L.incr);
+    hipLaunchKernelGGL(k_build_xs, dim3((nm * kNodes + 127) / 128), dim3(128), 0, c->stream, md, nm, ecut, c->ln_e0,
+                       c->dlog, t64);
+    hipLaunchKernelGGL(k_range_increments, dim3((nm * 2 * (kNodes - 1) + 127) / 128), dim3(128), 0, c->stream, md, nm,
+                       ecut, c->ln_e0, c->dlog, incr);
+    hipLaunchKernelGGL(k_range_accumulate, dim3(1), dim3(64), 0, c->stream, md, nm, ecut, c->ln_e0,
+                       (const double*)incr, t64);
+    HIP_TRY(hipGetLastError());
+    return finish_tables(c, ecut);
+}
+
+ems_status ems_load_tables(ems_ctx* c, const double* tables, uint32_t n_materials, double ecut)
+{
+    if (!c || !tables) return fail(EMS_ERR_INVALID_ARG, "null tables");
+    if (!c->have_mats || n_materials != c->n_materials) return fail(EMS_ERR_STATE, "tables must match loaded materials");
+    if (!(ecut > kEmin && ecut < 1.0e5)) return fail(EMS_ERR_INVALID_ARG, "cut outside the table range");
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.tables64, tables, 8ull * n_materials * kTabPerMat * kNodes,
+                           hipMemcpyHostToDevice, c->stream));
+    return finish_tables(c, ecut);
+}
+
+ems_status ems_read_tables(ems_ctx* c, double* out, uint64_t n_doubles)
+{
+    if (!c || !out) return fail(EMS_ERR_INVALID_ARG, "null");
+    if (!c->have_tables) return fail(EMS_ERR_STATE, "no tables");
+    uint64_t need = (uint64_t)c->n_materials * kTabPerMat * kNodes;
+    if (n_doubles < need) return fail(EMS_ERR_INVALID_ARG, "output too small");
+    HIP_TRY(hipMemcpyAsync(out, c->ws + c->L.tables64, 8 * need, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return EMS_OK;
+}
+
+ems_status ems_push_primaries(ems_ctx* c, const ems_primary* p, uint64_t n)
+{
+    ems_status s = check_ready(c);
+    if (s != EMS_OK) return s;
+    if (n == 0) return EMS_OK;
+    if (!p) return fail(EMS_ERR_INVALID_ARG, "null primaries");
+    // validate everything before touching any state
+    uint64_t new_events = 0;
+    std::unordered_map<uint64_t, int> seen;
+    for (uint64_t i = 0; i < n; ++i) {
+        const ems_primary& q = p[i];
+        if (q.type < 0 || q.type > 2) return fail(EMS_ERR_INVALID_ARG, "primary type");
+        if (q.slab < 0 || (uint32_t)q.slab >= c->n_slabs) return fail(EMS_ERR_INVALID_ARG, "primary slab");
+        if (!(q.T >= c->ecut) || !std::isfinite(q.T)) return fail(EMS_ERR_INVALID_ARG, "primary energy below the cut");
+        double un = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+        if (!(std::fabs(un - 1.0) < 1e-6)) return fail(EMS_ERR_INVALID_ARG, "primary direction not unit");
+        if (c->row_of.find(q.event) == c->row_of.end() && seen.emplace(q.event, 1).second) ++new_events;
+    }
+    if (new_events > c->free_rows.size()) return fail(EMS_ERR_CAPACITY, "not enough free event rows");
+    // ring capacity against the last known device consumption (conservative)
+    uint64_t consumed = c->last.prim_next;
+    if (c->prim_end + n - consumed > c->opt.n_primaries) {
+        Snapshot sn;
+        s = snapshot_now(c, &sn);
+        if (s != EMS_OK) return s;
+        consumed = sn.prim_next;
+        if (c->prim_end + n - consumed > c->opt.n_primaries) return fail(EMS_ERR_CAPACITY, "primary buffer full");
+    }
+    Initializer* dst = (Initializer*)(c->ws + c->L.prims);
+    uint64_t done = 0;
+    while (done < n) {
+        if (c->staging_busy) {
+            HIP_TRY(hipEventSynchronize(c->staging_ev));
+            c->staging_busy = false;
+        }
+        uint64_t chunk = std::min<uint64_t>(n - done, c->staging_cap);
+        for (uint64_t i = 0; i < chunk; ++i) {
+            const ems_primary& q = p[done + i];
+            uint32_t row;
+            s = assign_row(c, q.event, &row);
+            if (s != EMS_OK) return s;
+            c->row_pending[row] += 1;
+            Initializer& r = c->staging[i];
+            r.T = q.T;
+            r.r[0] = q.r[0]; r.r[1] = q.r[1]; r.r[2] = q.r[2];
+            r.u[0] = q.u[0]; r.u[1] = q.u[1]; r.u[2] = q.u[2];
+            r.key = q.key;
+            r.row = row;
+            r.slab = (uint16_t)q.slab;
+            r.type = (uint8_t)q.type;
+            r.pad = 0;
+        }
+        // copy into the ring [prim_end, prim_end + chunk) modulo capacity
+        uint64_t cap = c->opt.n_primaries;
+        uint64_t at = c->prim_end % cap;
+        uint64_t first = std::min<uint64_t>(chunk, cap - at);
+        HIP_TRY(hipMemcpyAsync(dst + at, c->staging, sizeof(Initializer) * first, hipMemcpyHostToDevice, c->stream));
+        if (first < chunk)
+            HIP_TRY(hipMemcpyAsync(dst, c->staging + first, sizeof(Initializer) * (chunk - first),
+                                   hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipEventRecord(c->staging_ev, c->stream));
+        c->staging_busy = true;
+        c->prim_end += chunk;
+        done += chunk;
+    }
+    hipLaunchKernelGGL(k_set_prim_end, dim3(1), dim3(1), 0, c->stream, (Counters*)(c->ws + c->L.ctr),
+                       (unsigned long long)c->prim_end);
+    HIP_TRY(hipGetLastError());
+    return EMS_OK;
+}
+
+ems_status ems_step(ems_ctx* c, uint32_t iterations, ems_counters* out)
+{
+    ems_status s = check_ready(c);
+    if (s != EMS_OK) return s;
+    for (uint32_t i = 0; i < iterations; ++i) {
+        s = launch_batch(c, 1, false);
+        if (s != EMS_OK) return s;
+    }
+    if (out) {
+        Snapshot sn;
+        s = snapshot_now(c, &sn);
+        if (s != EMS_OK) return s;
+        to_counters(sn, out);
+    }
+    return EMS_OK;
+}
+
+ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
+{
+    ems_status s = check_ready(c);
+    if (s != EMS_OK) return s;
+    const int batch = c->opt.graph_iterations > 0 ? c->opt.graph_iterations : 16;
+    uint64_t launched = 0;
+    uint64_t seq = 0;
+    // batches in flight: after launching batch g we wait for the snapshot of batch g-1
+    Snapshot done{};
+    bool finished = false;
+    int in_flight = 0;
+    while (!finished) {
+        if (launched < max_iterations) {
+            s = launch_batch(c, batch, false);
+            if (s != EMS_OK) return s;
+            launched += batch;
+            int slot = (int)(seq % c->snap_slots);
+            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
+                               &c->snap[slot]);
+            HIP_TRY(hipEventRecord(c->snap_ev[slot], c->stream));
+            ++seq;
+            ++in_flight;
+        }
+        if (in_flight >= 2 || launched >= max_iterations) {
+            int slot = (int)((seq - in_flight) % c->snap_slots);
+            HIP_TRY(hipEventSynchronize(c->snap_ev[slot]));
+            done = c->snap[slot];
+            --in_flight;
+            if (done.overflow) {
+                HIP_TRY(hipStreamSynchronize(c->stream));
+                c->last = done;
+                if (out) to_counters(done, out);
+                return fail(EMS_ERR_CAPACITY, "initializer buffer overflow: increase n_initializers");
+            }
+            if (done.n_alive == 0 && done.queue_size == 0 && done.prim_next == done.prim_end) finished = true;
+            else if (launched >= max_iterations && in_flight == 0) break;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Snapshot fin;
+    s = snapshot_now(c, &fin);
+    if (s != EMS_OK) return s;
+    if (out) to_counters(fin, out);
+    if (!finished) return fail(EMS_ERR_STATE, "max_iterations reached before the slots emptied");
+    return EMS_OK;
+}
+
+ems_status ems_read_counters(ems_ctx* c, ems_counters* out)
+{
+    if (!c || !out) return fail(EMS_ERR_INVALID_ARG, "null");
+    Snapshot sn;
+    ems_status s = snapshot_now(c, &sn);
+    if (s != EMS_OK) return s;
+    to_counters(sn, out);
+    return EMS_OK;
+}
+
+ems_status ems_poll_completed(ems_ctx* c, uint64_t* events, uint32_t cap, uint32_t* n)
+{
+    (void)c; (void)events; (void)cap;
+    if (n) *n = 0;
+    return fail(EMS_ERR_UNSUPPORTED, "completion polling is not available in this build");
+}
+
+ems_status ems_read_edep(ems_ctx* c, uint64_t event, double* per_slab, uint32_t n_slabs, ems_ledger* ledger)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
+    auto it = c->row_of.find(event);
+    if (it == c->row_of.end()) return fail(EMS_ERR_INVALID_ARG, "unknown event");
+    uint32_t row = it->second;
+    if (per_slab) {
+        if (n_slabs < c->n_slabs) return fail(EMS_ERR_INVALID_ARG, "per_slab too small");
+        HIP_TRY(hipMemcpyAsync(per_slab, c->ws + c->L.edep + 8ull * row * c->opt.max_slabs, 8ull * c->n_slabs,
+                               hipMemcpyDeviceToHost, c->stream));
+    }
+    if (ledger)
+        HIP_TRY(hipMemcpyAsync(ledger, c->ws + c->L.ledger + sizeof(Ledger) * row, sizeof(Ledger),
+                               hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return EMS_OK;
+}
+
+ems_status ems_read_all_tallies(ems_ctx* c, double* edep, ems_ledger* ledgers, uint64_t* row_event)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
+    uint64_t rows = c->opt.max_events;
+    if (edep) {
+        // rows are stored with stride max_slabs; return them with stride n_slabs
+        std::vector<double> tmp(rows * c->opt.max_slabs);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), c->ws + c->L.edep, 8ull * rows * c->opt.max_slabs, hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (uint64_t r = 0; r < rows; ++r)
+            std::memcpy(edep + r * c->n_slabs, tmp.data() + r * c->opt.max_slabs, 8ull * c->n_slabs);
+    }
+    if (ledgers)
+        HIP_TRY(hipMemcpyAsync(ledgers, c->ws + c->L.ledger, sizeof(Ledger) * rows, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (row_event) std::memcpy(row_event, c->row_event.data(), 8ull * rows);
+    return EMS_OK;
+}
+
+ems_status ems_release_event(ems_ctx* c, uint64_t event)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
+    auto it = c->row_of.find(event);
+    if (it == c->row_of.end()) return fail(EMS_ERR_INVALID_ARG, "unknown event");
+    uint32_t row = it->second;
+    c->row_of.erase(it);
+    c->row_event[row] = UINT64_MAX;
+    c->row_pending[row] = 0;
+    hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), row,
+                       (uint64_t)UINT64_MAX, (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger),
+                       (uint32_t)c->opt.max_slabs);
+    HIP_TRY(hipGetLastError());
+    c->free_rows.push_back(row);
+    return EMS_OK;
+}
+
+// ---------------------------------------------------------------- test hooks
+ems_status ems_debug_register_event(ems_ctx* c, uint64_t event, uint32_t* row)
+{
+    if (!c || !row) return fail(EMS_ERR_INVALID_ARG, "null");
+    return assign_row(c, event, row);
+}
+
+ems_status ems_debug_inject(ems_ctx* c, const ems_track* t, uint64_t n)
+{
+    ems_status s = check_ready(c);
+    if (s != EMS_OK) return s;
+    if (n > c->opt.n_slots) return fail(EMS_ERR_CAPACITY, "more tracks than slots");
+    for (uint64_t i = 0; i < n; ++i) {
+        if (t[i].type < 0) continue;
+        if (t[i].type > 2 || t[i].slab < 0 || (uint32_t)t[i].slab >= c->n_slabs || t[i].row >= c->opt.max_events ||
+            c->row_event[t[i].row] == UINT64_MAX || !(t[i].T >= c->ecut))
+            return fail(EMS_ERR_INVALID_ARG, "invalid injected track");
+    }
+    ems_track* dt = nullptr;
+    HIP_TRY(hipMalloc(&dt, sizeof(ems_track) * (n ? n : 1)));
+    if (n) HIP_TRY(hipMemcpyAsync(dt, t, sizeof(ems_track) * n, hipMemcpyHostToDevice, c->stream));
+    uint64_t ns = c->opt.n_slots;
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, c->stream, (Counters*)(c->ws + c->L.ctr));
+    if (c->opt.precision == EMS_MIXED)
+        hipLaunchKernelGGL(k_inject<float>, dim3((ns + 255) / 256), dim3(256), 0, c->stream, make_dev<float>(c), dt, n);
+    else
+        hipLaunchKernelGGL(k_inject<double>, dim3((ns + 255) / 256), dim3(256), 0, c->stream, make_dev<double>(c), dt, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(dt));
+    return EMS_OK;
+}
+
+ems_status ems_debug_iterate(ems_ctx* c, uint32_t iterations, int32_t no_init)
+{
+    ems_status s = check_ready(c);
+    if (s != EMS_OK) return s;
+    for (uint32_t i = 0; i < iterations; ++i) launch_iteration_any(c, no_init != 0, c->prof_mask != 0);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return EMS_OK;
+}
+
+ems_status ems_debug_read_tracks(ems_ctx* c, ems_track* t, uint64_t n)
+{
+    if (!c || !t) return fail(EMS_ERR_INVALID_ARG, "null");
+    if (n > c->opt.n_slots) return fail(EMS_ERR_INVALID_ARG, "n > n_slots");
+    if (n == 0) return EMS_OK;
+    ems_track* dt = nullptr;
+    HIP_TRY(hipMalloc(&dt, sizeof(ems_track) * n));
+    if (c->opt.precision == EMS_MIXED)
+        hipLaunchKernelGGL(k_read_tracks<float>, dim3((n + 255) / 256), dim3(256), 0, c->stream, make_dev<float>(c), dt, n);
+    else
+        hipLaunchKernelGGL(k_read_tracks<double>, dim3((n + 255) / 256), dim3(256), 0, c->stream, make_dev<double>(c), dt, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(t, dt, sizeof(ems_track) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(dt));
+    return EMS_OK;
+}
+
+ems_status ems_debug_read_secondaries(ems_ctx* c, ems_track* out, uint64_t cap, uint64_t* n)
+{
+    if (!c || !n) return fail(EMS_ERR_INVALID_ARG, "null");
+    Snapshot sn;
+    ems_status s = snapshot_now(c, &sn);
+    if (s != EMS_OK) return s;
+    uint64_t q = sn.queue_size < c->opt.n_initializers ? sn.queue_size : c->opt.n_initializers;
+    *n = q;
+    uint64_t m = q < cap ? q : cap;
+    if (m == 0 || !out) return EMS_OK;
+    ems_track* dt = nullptr;
+    HIP_TRY(hipMalloc(&dt, sizeof(ems_track) * m));
+    hipLaunchKernelGGL(k_read_queue, dim3((m + 255) / 256), dim3(256), 0, c->stream,
+                       (const Initializer*)(c->ws + c->L.queue), m, dt);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, dt, sizeof(ems_track) * m, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(dt));
+    return EMS_OK;
+}
+
+ems_status ems_debug_sort(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm)
+{
+    if (!c || (!keys && n) || (!perm && n)) return fail(EMS_ERR_INVALID_ARG, "null");
+    if (policy != EMS_SORT_PARTITION && policy != EMS_SORT_RADIX) return fail(EMS_ERR_INVALID_ARG, "policy");
+    if (n == 0) return EMS_OK;
+    if (n > 0xFFFFFFFFull) return fail(EMS_ERR_INVALID_ARG, "n too large");
+    const int nb = policy == EMS_SORT_PARTITION ? 16 : 128;
+    for (uint64_t i = 0; i < n; ++i)
+        if (keys[i] >= nb) return fail(EMS_ERR_INVALID_ARG, "key out of range for the policy");
+    uint32_t nt = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    uint8_t* dk = nullptr;
+    uint32_t *dp = nullptr, *cnt = nullptr;
+    HIP_TRY(hipMalloc(&dk, n));
+    HIP_TRY(hipMalloc(&dp, 4 * n));
+    HIP_TRY(hipMalloc(&cnt, 4ull * 128 * nt));
+    HIP_TRY(hipMemcpyAsync(dk, keys, n, hipMemcpyHostToDevice, c->stream));
+    Dev<double> d{};
+    if (nb == 16) {
+        hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk, (uint32_t)n, cnt, nt);
+        hipLaunchKernelGGL((k_sort_scan<16>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, (Counters*)nullptr, 0,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL((k_sort_scatter<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk,
+                           (uint32_t)n, cnt, nt, dp);
+    } else {
+        hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk, (uint32_t)n, cnt, nt);
+        hipLaunchKernelGGL((k_sort_scan<128>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, (Counters*)nullptr, 1,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL((k_sort_scatter<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk,
+                           (uint32_t)n, cnt, nt, dp);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(perm, dp, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    (void)hipFree(dk);
+    (void)hipFree(dp);
+    (void)hipFree(cnt);
+    return EMS_OK;
+}
+
+ems_status ems_profile_enable(ems_ctx* c, int32_t enable)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null");
+    c->prof_mask = (uint32_t)enable;
+    return EMS_OK;
+}
+
+ems_status ems_profile_read(ems_ctx* c, const char** names, double* total_ms, uint64_t* launches, uint32_t cap,
+                            uint32_t* n)
+{
+    if (!c || !n) return fail(EMS_ERR_INVALID_ARG, "null");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& e : c->prof_events) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e.second.first, e.second.second);
+        c->prof_ms[e.first] += ms;
+        c->prof_n[e.first] += 1;
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    c->prof_events.clear();
+    uint32_t m = cap < (uint32_t)R_NUM ? cap : (uint32_t)R_NUM;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (names) names[i] = kRoleNames[i];
+        if (total_ms) total_ms[i] = c->prof_ms[i];
+        if (launches) launches[i] = c->prof_n[i];
+        c->prof_ms[i] = 0.0;
+        c->prof_n[i] = 0;
+    }
+    *n = m;
+    return EMS_OK;
+}
+
+}  // extern "C"

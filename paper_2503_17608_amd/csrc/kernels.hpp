@@ -1,0 +1,919 @@
+// Step-iteration kernels (paper, "Stepping algorithm"): one kernel per
+// stepping action over the struct-of-arrays track state.
+//
+// Every kernel visits its tracks either masked over all slots (the paper's
+// default: each kernel runs on all tracks and masks by next action) or through
+// an index range of a sorted permutation of slots (paper, "Reindexing track
+// slots").  Index ranges live in device memory so that a captured HIP graph
+// replays correctly whatever the occupancy.
+#pragma once
+#include "common.hpp"
+#include "physics.hpp"
+
+namespace ems {
+
+template <class R>
+struct Dev {
+    // track state (struct of arrays over n_slots)
+    uint8_t* type;
+    uint8_t* action;
+    uint8_t* flags;
+    uint8_t* nsearch;
+    uint16_t* slab;
+    uint32_t* row;
+    uint32_t* step;
+    uint64_t* key;
+    R* T;
+    R* nl;
+    R* xs;
+    double* sphys;
+    double* sdone;
+    double* htry;
+    double* x;
+    double* y;
+    double* z;
+    R* ux;
+    R* uy;
+    R* uz;
+    uint32_t n_slots;
+    // buffers
+    Initializer* queue;
+    unsigned long long queue_cap;
+    Initializer* prims;
+    unsigned long long prim_cap;   // pending primaries form a ring of this size
+    uint32_t* vac;
+    uint32_t* vac_cnt;      // per vacancy block
+    uint32_t* init_cnt;     // per init block: charged initializers
+    uint32_t* perm;
+    Counters* ctr;
+    // physics / geometry
+    Tables<R> tb;
+    const double* zp;
+    const int32_t* smat;
+    int n_slabs;
+    double W;
+    double B[3];
+    int has_field;
+    double ecut;
+    uint64_t seed;
+    const uint64_t* row_event;
+    double* edep;           // [rows][edep_stride]
+    Ledger* ledger;
+    int edep_stride;
+    int max_substeps;
+    int sorted;
+};
+
+constexpr int kVacBlock = 1024;   // slots per block of the vacancy and init kernels
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// one atomic per wave: number of active lanes
+template <class R>
+__device__ __forceinline__ void count_work(const Dev<R>& d, int role, bool act)
+{
+    uint64_t m = __ballot(act);
+    if (lane_id() == 0 && m) atomicAdd(&d.ctr->work[role], (unsigned long long)__popcll(m));
+}
+
+// exclusive prefix of per-block counts: sum of cnt[0, b) with the whole block
+__device__ uint32_t block_prefix(const uint32_t* cnt, uint32_t b, uint32_t* scratch)
+{
+    uint32_t s = 0;
+    for (uint32_t i = threadIdx.x; i < b; i += blockDim.x) s += cnt[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 0) scratch[w] = s;
+    __syncthreads();
+    uint32_t tot = 0;
+    int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) tot += scratch[i];
+    __syncthreads();
+    return tot;
+}
+
+// ---- vacancy compaction (ordered by slot index) ---------------------------------
+template <class R>
+__global__ void __launch_bounds__(kVacBlock) k_vac_count(Dev<R> d)
+{
+    uint32_t s = blockIdx.x * kVacBlock + threadIdx.x;
+    int v = (s < d.n_slots) && d.type[s] == kDead;
+    int c = __syncthreads_count(v);
+    if (threadIdx.x == 0) d.vac_cnt[blockIdx.x] = (uint32_t)c;
+}
+
+// Writes vacant slot indices in slot order; the last block plans the fill:
+// initializers are taken from the top of the secondary buffer first (LIFO),
+// then from the pending primaries.
+template <class R>
+__global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fill)
+{
+    __shared__ uint32_t red[kVacBlock / 64];
+    __shared__ uint32_t wcnt[kVacBlock / 64];
+    uint32_t prefix = block_prefix(d.vac_cnt, blockIdx.x, red);
+    uint32_t s = blockIdx.x * kVacBlock + threadIdx.x;
+    bool v = (s < d.n_slots) && d.type[s] == kDead;
+    uint64_t m = __ballot(v);
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 0) wcnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t off = prefix;
+    for (int i = 0; i < w; ++i) off += wcnt[i];
+    if (v) d.vac[off + rank_below(m)] = s;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        uint32_t blk = 0;
+        for (int i = 0; i < kVacBlock / 64; ++i) blk += wcnt[i];
+        Counters* c = d.ctr;
+        uint32_t n_vac = prefix + blk;
+        c->n_vac = n_vac;
+        c->n_alive = d.n_slots - n_vac;
+        c->iterations += 1;
+        unsigned long long q = c->queue_size;
+        if (q > d.queue_cap) q = d.queue_cap;     // entries past capacity were dropped (overflow flagged)
+        unsigned long long pa = c->prim_end - c->prim_next;
+        unsigned long long tq = 0, tp = 0;
+        if (plan_fill) {
+            tq = q < n_vac ? q : n_vac;
+            unsigned long long left = n_vac - tq;
+            tp = pa < left ? pa : left;
+        }
+        c->n_take_q = (uint32_t)tq;
+        c->n_take_p = (uint32_t)tp;
+        c->q_base = q - tq;
+        c->p_base = c->prim_next;
+        c->queue_size = q - tq;
+        c->prim_next += tp;
+        c->n_alive += (uint32_t)(tq + tp);
+    }
+}
+
+template <class R>
+__device__ __forceinline__ const Initializer* taken(const Dev<R>& d, uint32_t i)
+{
+    const Counters* c = d.ctr;
+    if (i < c->n_take_q) return &d.queue[c->q_base + c->n_take_q - 1 - i];
+    return &d.prims[(c->p_base + (i - c->n_take_q)) % d.prim_cap];
+}
+
+// per-block count of charged initializers among the taken ones (partitioned fill)
+template <class R>
+__global__ void __launch_bounds__(kVacBlock) k_init_count(Dev<R> d)
+{
+    uint32_t i = blockIdx.x * kVacBlock + threadIdx.x;
+    uint32_t n = d.ctr->n_take_q + d.ctr->n_take_p;
+    int ch = 0;
+    if (i < n) ch = taken(d, i)->type != kGamma;
+    int c = __syncthreads_count(ch);
+    if (threadIdx.x == 0) d.init_cnt[blockIdx.x] = (uint32_t)c;
+}
+
+// Fill vacancies from the taken initializers.  Without partitioning the i-th
+// taken initializer goes to the i-th vacancy; with it, charged initializers
+// fill vacancies from the lowest slot upwards and neutral ones from the
+// highest slot downwards (paper, "Partitioning track data").
+template <class R, bool PART>
+__global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
+{
+    __shared__ uint32_t red[kVacBlock / 64];
+    __shared__ uint32_t wcnt[kVacBlock / 64];
+    const Counters* c = d.ctr;
+    uint32_t n = c->n_take_q + c->n_take_p;
+    if (blockIdx.x * kVacBlock >= n) return;          // block-uniform
+    uint32_t i = blockIdx.x * kVacBlock + threadIdx.x;
+    bool act = i < n;
+    Initializer rec;
+    if (act) rec = *taken(d, i);
+    uint32_t slot = 0;
+    if (PART) {
+        uint32_t prefix = block_prefix(d.init_cnt, blockIdx.x, red);
+        bool ch = act && rec.type != kGamma;
+        uint64_t m = __ballot(ch);
+        int w = threadIdx.x >> 6;
+        if (lane_id() == 0) wcnt[w] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = prefix;
+        for (int k = 0; k < w; ++k) off += wcnt[k];
+        uint32_t cidx = off + rank_below(m);          // charged initializers before i
+        if (act) slot = ch ? d.vac[cidx] : d.vac[c->n_vac - 1 - (i - cidx)];
+    } else {
+        if (act) slot = d.vac[i];
+    }
+    count_work(d, W_INIT, act);
+    if (!act) return;
+    d.type[slot] = rec.type;
+    d.action[slot] = A_IDLE;
+    d.flags[slot] = 0;
+    d.nsearch[slot] = 0;
+    d.slab[slot] = rec.slab;
+    d.row[slot] = rec.row;
+    d.step[slot] = 0;
+    d.key[slot] = rec.key;
+    d.T[slot] = (R)rec.T;
+    d.nl[slot] = R(-1);
+    d.xs[slot] = R(0);
+    d.sphys[slot] = 0.0;
+    d.sdone[slot] = 0.0;
+    d.htry[slot] = 0.0;
+    d.x[slot] = rec.r[0];
+    d.y[slot] = rec.r[1];
+    d.z[slot] = rec.r[2];
+    d.ux[slot] = (R)rec.u[0];
+    d.uy[slot] = (R)rec.u[1];
+    d.uz[slot] = (R)rec.u[2];
+}
+
+// ---- work distribution ----------------------------------------------------------
+// Iterate the tracks of action `a`: masked over all slots, or the index range
+// of `a` in the sorted permutation.  The loop bound is block-uniform so every
+// wave reaches the converged point at the end of each trip.
+#define EMS_FOR_TRACKS(d, a, s, act, role)                                                 \
+    const uint32_t _n = (d).sorted ? (d).ctr->range_cnt[a] : (d).n_slots;                    \
+    const uint32_t _off = (d).sorted ? (d).ctr->range_off[a] : 0u;                          \
+    for (uint32_t _base = blockIdx.x * blockDim.x; _base < _n; _base += gridDim.x * blockDim.x) { \
+        uint32_t _i = _base + threadIdx.x;                                                  \
+        bool act = _i < _n;                                                                 \
+        uint32_t s = 0;                                                                     \
+        if (act) s = (d).sorted ? (d).perm[_off + _i] : _i;                                 \
+        if (act && (d).action[s] != (a)) act = false;                                       \
+        count_work((d), (role), act);
+
+#define EMS_END_TRACKS }
+
+// ---- secondary append (wave-aggregated) ------------------------------------------
+template <class R>
+__device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row,
+                                                   uint16_t slab, const double r[3])
+{
+    int n = sb.n;
+    int lane = lane_id();
+    int x = n;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    int total = __shfl(x, 63, 64);
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&d.ctr->queue_size, (unsigned long long)total);
+    uint32_t lo = __shfl((uint32_t)base, 0, 64), hi = __shfl((uint32_t)(base >> 32), 0, 64);
+    base = ((unsigned long long)hi << 32) | lo;
+    unsigned long long pos = base + (unsigned long long)(x - n);
+    for (int k = 0; k < n; ++k) {
+        unsigned long long q = pos + (unsigned long long)k;
+        if (q >= d.queue_cap) {
+            atomicOr(&d.ctr->overflow, 1u);
+            continue;
+        }
+        Initializer rec;
+        rec.T = (double)sb.T[k];
+        rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
+        rec.u[0] = (double)sb.u[k][0]; rec.u[1] = (double)sb.u[k][1]; rec.u[2] = (double)sb.u[k][2];
+        rec.key = sb.key[k];
+        rec.row = row;
+        rec.slab = slab;
+        rec.type = sb.type[k];
+        rec.pad = 0;
+        d.queue[q] = rec;
+        atomicAdd(&d.ledger[row].n_sec[sb.type[k]], 1ull);
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void record_tally(const Dev<R>& d, uint32_t row, int slab, const StepTally& tl)
+{
+    if (tl.edep != 0.0) atomicAdd(&d.edep[(size_t)row * d.edep_stride + slab], tl.edep);
+    if (tl.n_pair) atomicAdd(&d.ledger[row].n_pair, (unsigned long long)tl.n_pair);
+    if (tl.n_annih) atomicAdd(&d.ledger[row].n_annih, (unsigned long long)tl.n_annih);
+    if (tl.capped) atomicAdd(&d.ledger[row].n_reject_cap, 1ull);
+}
+
+// a track finishes: free its slot and add its steps to the event ledger
+template <class R>
+__device__ __forceinline__ void retire(const Dev<R>& d, uint32_t s, uint32_t row, uint32_t steps)
+{
+    d.type[s] = kDead;
+    d.action[s] = A_NONE;
+    atomicAdd(&d.ledger[row].steps, (unsigned long long)steps);
+    atomicAdd(&d.ctr->steps_done, (unsigned long long)steps);
+}
+
+// ---- pre-step: interaction length, physics step limit, along-step action -----------
+template <class R>
+__global__ void k_pre_step(Dev<R> d)
+{
+    for (uint32_t base = blockIdx.x * blockDim.x; base < d.n_slots; base += gridDim.x * blockDim.x) {
+        uint32_t s = base + threadIdx.x;
+        bool act = s < d.n_slots;
+        uint8_t typ = kDead, fl = 0;
+        if (act) {
+            typ = d.type[s];
+            act = typ != kDead;
+        }
+        if (act) {
+            fl = d.flags[s];
+            act = !(fl & F_PAUSED);
+        }
+        count_work(d, W_PRE, act);
+        if (!act) continue;
+        R T = d.T[s];
+        int mat = d.smat[d.slab[s]];
+        R nl = d.nl[s];
+        uint8_t nf = 0;
+        if (nl < R(0)) {
+            StepRng<R> rng(d.seed, d.row_event[d.row[s]], d.key[s], d.step[s], 0);
+            nl = -m_log(rng.next());
+            d.nl[s] = nl;
+            nf |= F_DREW;
+        }
+        Loc<R> l = locate(d.tb, T);
+        R sig = total_xs(d.tb, mat, typ, T, l, R(d.ecut));
+        R s_int = sig > R(0) ? nl / sig : R(INFINITY);
+        R s_phys = s_int;
+        if (typ != kGamma) {
+            R Rg = interp(range_tab(d.tb, mat, typ), l);
+            R s_loss = Rg <= R(kRFinal) ? Rg : m_max(R(kRFinal), R(kRhoRange) * Rg);
+            if (s_loss < s_int) {
+                s_phys = s_loss;
+                nf |= F_LOSS;
+            }
+        }
+        d.xs[s] = sig;
+        d.sphys[s] = (double)s_phys;
+        d.flags[s] = nf;
+        d.action[s] = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
+    }
+}
+
+// ---- geometry helpers -----------------------------------------------------------
+__device__ __forceinline__ double face_plane(const double* zp, int slab, double W, int face)
+{
+    switch (face) {
+    case F_ZLO: return zp[slab];
+    case F_ZHI: return zp[slab + 1];
+    case F_XLO: return -W;
+    case F_XHI: return W;
+    case F_YLO: return -W;
+    default:    return W;
+    }
+}
+__device__ __forceinline__ int face_axis(int face) { return face <= F_ZHI ? 2 : (face <= F_XHI ? 0 : 1); }
+
+// straight-line distance to leave the slab box (z face wins ties, then x, y)
+__device__ __forceinline__ double straight_distance(const double r[3], const double u[3], double zlo, double zhi,
+                                                    double W, int* face)
+{
+    double dz = INFINITY, dx = INFINITY, dy = INFINITY;
+    int fz = F_NONE, fx = F_NONE, fy = F_NONE;
+    if (u[2] > 0.0) { dz = (zhi - r[2]) / u[2]; fz = F_ZHI; }
+    else if (u[2] < 0.0) { dz = (zlo - r[2]) / u[2]; fz = F_ZLO; }
+    if (u[0] > 0.0) { dx = (W - r[0]) / u[0]; fx = F_XHI; }
+    else if (u[0] < 0.0) { dx = (-W - r[0]) / u[0]; fx = F_XLO; }
+    if (u[1] > 0.0) { dy = (W - r[1]) / u[1]; fy = F_YHI; }
+    else if (u[1] < 0.0) { dy = (-W - r[1]) / u[1]; fy = F_YLO; }
+    dz = fmax(dz, 0.0); dx = fmax(dx, 0.0); dy = fmax(dy, 0.0);
+    double dd = dz;
+    *face = fz;
+    if (dx < dd) { dd = dx; *face = fx; }
+    if (dy < dd) { dd = dy; *face = fy; }
+    return dd;
+}
+
+// Common end of an along-step (S6-S8) for a step of length s.  Returns true
+// when the track remains alive; sets the next action.
+template <class R, bool CHARGED>
+__device__ __forceinline__ void finish_along(const Dev<R>& d, uint32_t s, int typ, R& T, R sig, double step_len,
+                                             int face, uint8_t fl, int mat, uint16_t& slab, const double r[3],
+                                             SecBuf<R>& sb, StepTally& tl, const PhysParams& pp, bool& alive,
+                                             uint8_t& next_action, R& nl)
+{
+    uint32_t step = d.step[s];
+    if (CHARGED) {
+        const R* Rt = range_tab(d.tb, mat, typ);
+        Loc<R> l = locate(d.tb, T);
+        R Rg = interp(Rt, l);
+        bool stop = false;
+        if (face == F_NONE && (fl & F_LOSS) && Rg <= R(kRFinal)) {
+            stop = true;
+        } else {
+            R Tn = inverse_range(d.tb, Rt, (R)((double)Rg - step_len));
+            if (Tn < R(d.ecut)) stop = true;
+            else {
+                tl.edep += (double)T - (double)Tn;
+                T = Tn;
+            }
+        }
+        if (stop) {
+            Prim<R> p;
+            p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = d.key[s]; p.step = step; p.type = typ; p.alive = true;
+            stop_lepton<R>(pp, p, sb, tl);
+            T = R(0);
+            alive = false;
+            next_action = A_NONE;
+            d.step[s] = step + 1;
+            return;
+        }
+    }
+    nl = nl - (R)step_len * sig;
+    if (face != F_NONE) {
+        int next = slab;
+        if (face == F_ZLO) next = slab - 1;
+        else if (face == F_ZHI) next = slab + 1;
+        else next = -1;
+        if (next < 0 || next >= d.n_slabs) {
+            atomicAdd(&d.ledger[d.row[s]].escaped, (double)T);
+            alive = false;
+            next_action = A_NONE;
+        } else {
+            slab = (uint16_t)next;
+            next_action = A_IDLE;
+        }
+        d.step[s] = step + 1;
+    } else if (fl & F_LOSS) {
+        next_action = A_IDLE;
+        d.step[s] = step + 1;
+    } else {
+        StepRng<R> rng(d.seed, pp.event, d.key[s], step, (fl & F_DREW) ? 1 : 0);
+        R U1 = rng.next();
+        R sig1;
+        Loc<R> l1;
+        if (CHARGED) {
+            l1 = locate(d.tb, T);
+            sig1 = total_xs(d.tb, mat, typ, T, l1, R(d.ecut));
+        } else {
+            l1 = locate(d.tb, T);
+            sig1 = sig;
+        }
+        nl = R(-1);
+        if (sig1 > R(0)) {
+            R target = U1 * sig1, cum = R(0);
+            int proc = proc_of(typ, n_proc(typ) - 1);
+            for (int k = 0; k < n_proc(typ); ++k) {
+                cum += proc_xs(d.tb, mat, proc_of(typ, k), T, l1, R(d.ecut));
+                if (target < cum) { proc = proc_of(typ, k); break; }
+            }
+            next_action = (uint8_t)(A_PROC0 + proc);
+        } else {
+            next_action = A_IDLE;
+            d.step[s] = step + 1;
+        }
+    }
+    if (alive && d.step[s] > kMaxSteps && next_action == A_IDLE) {
+        // step guard
+        atomicAdd(&d.ledger[d.row[s]].n_guard, 1ull);
+        Prim<R> p;
+        p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = d.key[s]; p.step = d.step[s]; p.type = typ; p.alive = true;
+        if (typ != kGamma) stop_lepton<R>(pp, p, sb, tl);
+        else tl.edep += (double)T;
+        T = R(0);
+        alive = false;
+        next_action = A_NONE;
+    }
+}
+
+// ---- along-step, straight line (photons, or charged without field) ------------------
+template <class R, bool CHARGED>
+__global__ void k_along_straight(Dev<R> d)
+{
+    const uint8_t A = CHARGED ? A_CHARGED : A_NEUTRAL;
+    EMS_FOR_TRACKS(d, A, s, act, CHARGED ? W_CHARGED : W_NEUTRAL)
+    SecBuf<R> sb;
+    sb.n = 0;
+    double r[3] = {0.0, 0.0, 0.0};
+    uint32_t row = 0;
+    uint16_t slab0 = 0;
+    if (act) {
+        int typ = d.type[s];
+        row = d.row[s];
+        uint16_t slab = d.slab[s];
+        slab0 = slab;
+        int mat = d.smat[slab];
+        R T = d.T[s];
+        R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
+        double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
+        r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+        double s_phys = d.sphys[s];
+        uint8_t fl = d.flags[s];
+        R sig = d.xs[s];
+        R nl = d.nl[s];
+        int face;
+        double s_geo = straight_distance(r, ud, d.zp[slab], d.zp[slab + 1], d.W, &face);
+        double st;
+        if (s_geo <= s_phys) st = s_geo;
+        else { st = s_phys; face = F_NONE; }
+        r[0] = r[0] + st * ud[0];
+        r[1] = r[1] + st * ud[1];
+        r[2] = r[2] + st * ud[2];
+        if (face != F_NONE) r[face_axis(face)] = face_plane(d.zp, slab, d.W, face);
+        StepTally tl = {0.0, 0, 0, 0};
+        PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+        bool alive = true;
+        uint8_t na = A_IDLE;
+        finish_along<R, CHARGED>(d, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+        record_tally(d, row, slab0, tl);
+        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+        if (alive) {
+            d.T[s] = T;
+            d.nl[s] = nl;
+            d.slab[s] = slab;
+            d.action[s] = na;
+        } else {
+            retire(d, s, row, d.step[s]);
+        }
+    }
+    append_secondaries(d, sb, row, slab0, r);
+    EMS_END_TRACKS
+}
+
+// ---- along-step in a uniform field -------------------------------------------------
+__device__ __forceinline__ void rk4(const double r[3], const double u[3], double h, double kf, const double B[3],
+                                    double r1[3], double u1[3])
+{
+    double k1[3], k2[3], k3[3], k4[3], u2[3], u3[3], u4[3];
+#define EMS_CROSS(a, o)                                 \
+    o[0] = kf * (a[1] * B[2] - a[2] * B[1]);            \
+    o[1] = kf * (a[2] * B[0] - a[0] * B[2]);            \
+    o[2] = kf * (a[0] * B[1] - a[1] * B[0]);
+    EMS_CROSS(u, k1)
+    for (int c = 0; c < 3; ++c) u2[c] = u[c] + 0.5 * h * k1[c];
+    EMS_CROSS(u2, k2)
+    for (int c = 0; c < 3; ++c) u3[c] = u[c] + 0.5 * h * k2[c];
+    EMS_CROSS(u3, k3)
+    for (int c = 0; c < 3; ++c) u4[c] = u[c] + h * k3[c];
+    EMS_CROSS(u4, k4)
+#undef EMS_CROSS
+    for (int c = 0; c < 3; ++c) {
+        r1[c] = r[c] + h / 6.0 * (u[c] + 2.0 * u2[c] + 2.0 * u3[c] + u4[c]);
+        u1[c] = u[c] + h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+    }
+}
+
+__device__ __forceinline__ bool beyond(int face, double v, double p)
+{
+    return (face == F_ZLO || face == F_XLO || face == F_YLO) ? (v < p) : (v > p);
+}
+
+__device__ __forceinline__ bool points_out(const double u[3], int face)
+{
+    switch (face) {
+    case F_ZLO: return u[2] < 0.0;
+    case F_ZHI: return u[2] > 0.0;
+    case F_XLO: return u[0] < 0.0;
+    case F_XHI: return u[0] > 0.0;
+    case F_YLO: return u[1] < 0.0;
+    default:    return u[1] > 0.0;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void store_dir(double u[3])
+{
+    // directions are stored in precision R; keep the integrator's copy
+    // identical to what a paused step would store
+    u[0] = (double)(R)u[0];
+    u[1] = (double)(R)u[1];
+    u[2] = (double)(R)u[2];
+}
+
+__device__ __forceinline__ void normalize_d(double v[3])
+{
+    double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n; v[1] /= n; v[2] /= n;
+}
+
+// Uniform-field propagation with RK4 substeps of at most sqrt(8 d_chord /
+// curvature), boundary search by chord fraction, and a cap of max_substeps
+// RK4 evaluations per iteration: at the cap the step pauses with its
+// position, direction, path length and search state saved, and resumes in the
+// next iteration (paper, "Reducing load imbalance").  Momentum is fixed during
+// the step, so a paused step ends exactly as an uninterrupted one.
+template <class R>
+__global__ void k_along_field(Dev<R> d)
+{
+    EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
+    SecBuf<R> sb;
+    sb.n = 0;
+    double r[3] = {0.0, 0.0, 0.0};
+    uint32_t row = 0;
+    uint16_t slab0 = 0;
+    if (act) {
+        int typ = d.type[s];
+        row = d.row[s];
+        uint16_t slab = d.slab[s];
+        slab0 = slab;
+        int mat = d.smat[slab];
+        R T = d.T[s];
+        double u[3] = {(double)d.ux[s], (double)d.uy[s], (double)d.uz[s]};
+        r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+        double s_phys = d.sphys[s];
+        double s_done = d.sdone[s];
+        double h_try = d.htry[s];
+        int n_search = d.nsearch[s];
+        uint8_t fl = d.flags[s];
+        double Td = (double)T;
+        double q = typ == kPositron ? 1.0 : -1.0;
+        double p = sqrt(Td * (Td + 2.0 * kMe));
+        double kf = q * kCk / p;
+        double Bm = sqrt(d.B[0] * d.B[0] + d.B[1] * d.B[1] + d.B[2] * d.B[2]);
+        double h_chord = sqrt(8.0 * kDChord / (kCk * Bm / p));
+        double zlo = d.zp[slab], zhi = d.zp[slab + 1];
+        int face = F_NONE;
+        bool paused = false;
+        int att = 0;
+        for (;;) {
+            if (d.max_substeps > 0 && att >= d.max_substeps) { paused = true; break; }
+            double rem = s_phys - s_done;
+            double h = h_try > 0.0 ? h_try : fmin(rem, h_chord);
+            bool last = (h_try == 0.0 && h == rem);
+            double r1[3], u1[3];
+            rk4(r, u, h, kf, d.B, r1, u1);
+            ++att;
+            // first face crossed by the chord r -> r1
+            int fc = F_NONE;
+            double f = INFINITY;
+            for (int fa = F_ZLO; fa <= F_YHI; ++fa) {
+                int ax = face_axis(fa);
+                double pl = fa == F_ZLO ? zlo : (fa == F_ZHI ? zhi : face_plane(d.zp, slab, d.W, fa));
+                if (!beyond(fa, r1[ax], pl)) continue;
+                double fr = (pl - r[ax]) / (r1[ax] - r[ax]);
+                fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+                if (fr < f) { f = fr; fc = fa; }
+            }
+            if (fc == F_NONE) {
+                int nf = F_NONE;
+                if (h_try > 0.0) {
+                    double bd = kDInt;
+                    for (int fa = F_ZLO; fa <= F_YHI; ++fa) {
+                        double pl = fa == F_ZLO ? zlo : (fa == F_ZHI ? zhi : face_plane(d.zp, slab, d.W, fa));
+                        double dd = fabs(r1[face_axis(fa)] - pl);
+                        if (dd <= bd && (nf == F_NONE || dd < bd)) { bd = dd; nf = fa; }
+                    }
+                }
+                r[0] = r1[0]; r[1] = r1[1]; r[2] = r1[2];
+                normalize_d(u1);
+                store_dir<R>(u1);
+                u[0] = u1[0]; u[1] = u1[1]; u[2] = u1[2];
+                if (nf != F_NONE) {
+                    r[face_axis(nf)] = face_plane(d.zp, slab, d.W, nf);
+                    s_done += h;
+                    face = nf;
+                    break;
+                }
+                if (last) { s_done = s_phys; break; }
+                s_done += h;
+                h_try = 0.0;
+                n_search = 0;
+                continue;
+            }
+            if (f == 0.0 && points_out(u, fc)) {
+                r[face_axis(fc)] = face_plane(d.zp, slab, d.W, fc);
+                face = fc;
+                break;
+            }
+            double ch[3] = {r1[0] - r[0], r1[1] - r[1], r1[2] - r[2]};
+            double clen = sqrt(ch[0] * ch[0] + ch[1] * ch[1] + ch[2] * ch[2]);
+            if ((1.0 - f) * clen <= kDInt || n_search >= kMaxSearch) {
+                for (int c = 0; c < 3; ++c) r[c] = r[c] + f * ch[c];
+                r[face_axis(fc)] = face_plane(d.zp, slab, d.W, fc);
+                normalize_d(u1);
+                store_dir<R>(u1);
+                u[0] = u1[0]; u[1] = u1[1]; u[2] = u1[2];
+                s_done += f * h;
+                face = fc;
+                break;
+            }
+            h_try = f > 0.0 ? f * h : 0.5 * h;
+            n_search += 1;
+        }
+        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+        d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
+        atomicAdd(&d.ctr->work[W_SUBSTEPS], (unsigned long long)att);
+        if (paused) atomicAdd(&d.ctr->work[W_PAUSED], 1ull);
+        if (paused) {
+            d.sdone[s] = s_done;
+            d.htry[s] = h_try;
+            d.nsearch[s] = (uint8_t)n_search;
+            d.flags[s] = fl | F_PAUSED;
+        } else {
+            d.sdone[s] = 0.0;
+            d.htry[s] = 0.0;
+            d.nsearch[s] = 0;
+            d.flags[s] = fl & (uint8_t)~F_PAUSED;
+            R sig = d.xs[s];
+            R nl = d.nl[s];
+            StepTally tl = {0.0, 0, 0, 0};
+            PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+            bool alive = true;
+            uint8_t na = A_IDLE;
+            finish_along<R, true>(d, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+            record_tally(d, row, slab0, tl);
+            if (alive) {
+                d.T[s] = T;
+                d.nl[s] = nl;
+                d.slab[s] = slab;
+                d.action[s] = na;
+            } else {
+                retire(d, s, row, d.step[s]);
+            }
+        }
+    }
+    append_secondaries(d, sb, row, slab0, r);
+    EMS_END_TRACKS
+}
+
+// ---- discrete interactions: one kernel per process ---------------------------------
+template <class R, int PROC>
+__global__ void k_interact(Dev<R> d)
+{
+    EMS_FOR_TRACKS(d, (uint8_t)(A_PROC0 + PROC), s, act, W_PROC0 + PROC)
+    SecBuf<R> sb;
+    sb.n = 0;
+    double r[3] = {0.0, 0.0, 0.0};
+    uint32_t row = 0;
+    uint16_t slab = 0;
+    if (act) {
+        row = d.row[s];
+        slab = d.slab[s];
+        r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+        Prim<R> p;
+        p.T = d.T[s];
+        p.u[0] = d.ux[s]; p.u[1] = d.uy[s]; p.u[2] = d.uz[s];
+        p.key = d.key[s];
+        p.step = d.step[s];
+        p.type = d.type[s];
+        p.alive = true;
+        uint8_t fl = d.flags[s];
+        PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+        StepRng<R> rng(d.seed, pp.event, p.key, p.step, (fl & F_DREW) ? 2 : 1);
+        StepTally tl = {0.0, 0, 0, 0};
+        switch (PROC) {
+        case P_COMPTON: sample_compton<R>(pp, p, rng, sb, tl); break;
+        case P_PHOTO:   sample_photo<R>(pp, p, sb, tl); break;
+        case P_PAIR:    sample_pair<R>(pp, p, rng, sb, tl); break;
+        case P_MOLLER:  sample_moller<R>(pp, p, rng, sb, tl); break;
+        case P_BHABHA:  sample_bhabha<R>(pp, p, rng, sb, tl); break;
+        default:        sample_brems<R>(pp, p, rng, sb, tl); break;
+        }
+        uint32_t steps = p.step + 1;
+        d.step[s] = steps;
+        if (p.alive && steps > kMaxSteps) {
+            atomicAdd(&d.ledger[row].n_guard, 1ull);
+            p.step = steps;
+            if (p.type != kGamma) stop_lepton<R>(pp, p, sb, tl);
+            else { tl.edep += (double)p.T; p.alive = false; }
+        }
+        record_tally(d, row, slab, tl);
+        if (p.alive) {
+            d.T[s] = p.T;
+            d.ux[s] = p.u[0]; d.uy[s] = p.u[1]; d.uz[s] = p.u[2];
+            d.nl[s] = R(-1);
+            d.action[s] = A_IDLE;
+        } else {
+            retire(d, s, row, steps);
+        }
+    }
+    append_secondaries(d, sb, row, slab, r);
+    EMS_END_TRACKS
+}
+
+// ---- stable counting sort of slot indices by a small key ----------------------------
+// Sort key of a slot at a sort point; 0xFF excludes the slot.
+//   keymode 0 (partition): the next action (< 16)
+//   keymode 1 (radix): action << 3 | type << 1 | (material & 1) (< 128)
+template <class R>
+__device__ __forceinline__ uint32_t sort_key(const Dev<R>& d, uint32_t s, int keymode)
+{
+    uint8_t a = d.action[s];
+    if (a == A_NONE || a == A_IDLE) return 0xFFu;
+    if (keymode == 0) return a;
+    uint32_t t = d.type[s];
+    uint32_t m = (uint32_t)d.smat[d.slab[s]] & 1u;
+    return ((uint32_t)a << 3) | (t << 1) | m;
+}
+
+constexpr int kSortThreads = 256;
+constexpr int kSortTile = 4096;      // slots per sort block
+
+// Per-tile histogram: cnt[bin * n_tiles + tile]
+template <class R, int NB>
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(Dev<R> d, int keymode, const uint8_t* ext_keys, uint32_t n,
+                                                            uint32_t* cnt, uint32_t n_tiles)
+{
+    __shared__ uint32_t h[NB];
+    for (int b = threadIdx.x; b < NB; b += kSortThreads) h[b] = 0;
+    __syncthreads();
+    uint32_t base = blockIdx.x * kSortTile;
+    for (int k = threadIdx.x; k < kSortTile; k += kSortThreads) {
+        uint32_t i = base + k;
+        if (i >= n) break;
+        uint32_t key = ext_keys ? ext_keys[i] : sort_key(d, i, keymode);
+        if (key < NB) atomicAdd(&h[key], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < NB; b += kSortThreads) cnt[b * n_tiles + blockIdx.x] = h[b];
+}
+
+// Exclusive scan of cnt (bin-major), in place, by one block; writes the
+// per-bin ranges of the actions into the counters.
+template <int NB>
+__global__ void __launch_bounds__(1024) k_sort_scan(uint32_t* cnt, uint32_t n_tiles, Counters* ctr, int keymode,
+                                                    uint32_t* bin_off)
+{
+    __shared__ uint32_t part[1024];
+    uint32_t total = NB * n_tiles;
+    uint32_t chunk = (total + 1023) / 1024;
+    uint32_t b0 = threadIdx.x * chunk, b1 = b0 + chunk < total ? b0 + chunk : total;
+    uint32_t s = 0;
+    for (uint32_t i = b0; i < b1; ++i) s += cnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (uint32_t i = b0; i < b1; ++i) {
+        uint32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+    __syncthreads();
+    // bin offsets and action ranges
+    if (threadIdx.x < NB) {
+        uint32_t b = threadIdx.x;
+        uint32_t off = cnt[b * n_tiles];
+        uint32_t end = (b + 1 < (uint32_t)NB) ? cnt[(b + 1) * n_tiles] : part[1023];
+        if (bin_off) { bin_off[b] = off; bin_off[NB + b] = end - off; }
+    }
+    __syncthreads();
+    if (ctr && threadIdx.x < 16) {
+        uint32_t a = threadIdx.x;
+        uint32_t lo_bin = keymode == 0 ? a : a << 3;
+        uint32_t hi_bin = keymode == 0 ? a + 1 : (a + 1) << 3;
+        if (lo_bin >= (uint32_t)NB) {
+            ctr->range_off[a] = part[1023];
+            ctr->range_cnt[a] = 0;
+        } else {
+            uint32_t off = cnt[lo_bin * n_tiles];
+            uint32_t end = hi_bin < (uint32_t)NB ? cnt[hi_bin * n_tiles] : part[1023];
+            ctr->range_off[a] = off;
+            ctr->range_cnt[a] = end - off;
+        }
+    }
+}
+
+// Stable scatter: within a tile, items keep index order per key (wave
+// ballots rank lanes of equal key; waves and rounds are ordered through LDS).
+template <class R, int NB>
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int keymode, const uint8_t* ext_keys,
+                                                               uint32_t n, const uint32_t* cnt, uint32_t n_tiles,
+                                                               uint32_t* perm)
+{
+    constexpr int NW = kSortThreads / 64;
+    __shared__ uint32_t run[NB];
+    __shared__ uint32_t wc[NW][NB];
+    for (int b = threadIdx.x; b < NB; b += kSortThreads) run[b] = cnt[b * n_tiles + blockIdx.x];
+    for (int b = threadIdx.x; b < NW * NB; b += kSortThreads) (&wc[0][0])[b] = 0;
+    __syncthreads();
+    int w = threadIdx.x >> 6;
+    int lane = lane_id();
+    uint32_t base = blockIdx.x * kSortTile;
+    for (int round = 0; round < kSortTile / kSortThreads; ++round) {
+        uint32_t i = base + round * kSortThreads + threadIdx.x;
+        uint32_t key = 0xFFFFFFFFu;
+        if (i < n) key = ext_keys ? ext_keys[i] : sort_key(d, i, keymode);
+        bool valid = key < (uint32_t)NB;
+        // rank among equal keys in this wave
+        uint32_t my_rank = 0;
+        uint64_t pending = __ballot(valid);
+        while (pending) {
+            int leader = __ffsll((long long)pending) - 1;
+            uint32_t lk = __shfl(key, leader, 64);
+            uint64_t same = __ballot(valid && key == lk);
+            if (valid && key == lk) my_rank = rank_below(same);
+            if (lane == leader) wc[w][lk] = (uint32_t)__popcll(same);
+            pending &= ~same;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[key] + my_rank;
+            for (int k = 0; k < w; ++k) pos += wc[k][key];
+            perm[pos] = i;
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < NB; b += kSortThreads) {
+            uint32_t add = 0;
+            for (int k = 0; k < NW; ++k) { add += wc[k][b]; wc[k][b] = 0; }
+            run[b] += add;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace ems

@@ -1,0 +1,72 @@
+"""Shared helpers for the GPU parity tests: build a library session and the
+oracle problem for the same workload, and convert track records."""
+import math
+
+import numpy as np
+
+import oracle
+import workloads
+
+
+def session_for(workload, n_slots=None, precision="f64", max_events=None, **kw):
+    from paper_2503_17608_amd import emstep
+    st = workload.stack
+    s = emstep.Session(n_slots or workload.n_slots, precision=precision,
+                       max_events=max_events or max(workload.n_events, 1), max_slabs=st.n_slabs,
+                       max_materials=len(st.materials), seed=workload.seed, **kw)
+    s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, workload.ecut)
+    return s
+
+
+def random_states(workload, n, rng, types=(0, 1, 2), e_max=1000.0, f32=False):
+    """Random single-track states inside the stack (some on planes / near walls)."""
+    st = workload.stack
+    z = st.z_planes
+    W = st.half_width
+    t = np.zeros(n, dtype=oracle.TRACK_DTYPE)
+    t["event"] = rng.integers(0, 2 ** 40, n)
+    t["key"] = rng.integers(0, 2 ** 63, n)
+    t["type"] = rng.choice(types, n)
+    t["slab"] = rng.integers(0, st.n_slabs, n)
+    t["step"] = rng.integers(0, 200, n)
+    t["alive"] = 1
+    t["T"] = np.exp(rng.uniform(math.log(workload.ecut * 1.0001), math.log(e_max), n))
+    t["nl"] = np.where(rng.uniform(size=n) < 0.5, -1.0, rng.exponential(1.0, n))
+    ct = rng.uniform(-1, 1, n)
+    ph = rng.uniform(0, 2 * math.pi, n)
+    sn = np.sqrt(1 - ct * ct)
+    t["u"] = np.stack([sn * np.cos(ph), sn * np.sin(ph), ct], 1)
+    sl = t["slab"]
+    frac = rng.uniform(0.0, 1.0, n)
+    on_lo = rng.uniform(size=n) < 0.1
+    frac[on_lo] = 0.0
+    t["r"][:, 2] = z[sl] + frac * (z[sl + 1] - z[sl])
+    t["r"][on_lo, 2] = z[sl[on_lo]]
+    t["r"][:, 0] = rng.uniform(-0.98 * W, 0.98 * W, n)
+    t["r"][:, 1] = rng.uniform(-0.98 * W, 0.98 * W, n)
+    if f32:
+        t["T"] = t["T"].astype(np.float32).astype(np.float64)
+        t["nl"] = t["nl"].astype(np.float32).astype(np.float64)
+        t["u"] = t["u"].astype(np.float32).astype(np.float64)
+        t["T"] = np.maximum(t["T"], np.nextafter(np.float32(workload.ecut), np.float32(1e9)).astype(np.float64))
+    return t
+
+
+def to_lib_tracks(orc_tracks, rows):
+    from paper_2503_17608_amd import emstep
+    t = np.zeros(len(orc_tracks), dtype=emstep.TRACK_DTYPE)
+    t["key"] = orc_tracks["key"]
+    t["row"] = rows
+    t["step"] = orc_tracks["step"]
+    t["type"] = orc_tracks["type"]
+    t["slab"] = orc_tracks["slab"]
+    t["T"] = orc_tracks["T"]
+    t["nl"] = orc_tracks["nl"]
+    t["r"] = orc_tracks["r"]
+    t["u"] = orc_tracks["u"]
+    return t
+
+
+def layer_sums(edep):
+    """Per-layer deposit (Pb + LAr pair of slabs)."""
+    return edep.reshape(edep.shape[0], -1, 2).sum(2)
