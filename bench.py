@@ -60,11 +60,13 @@ def parse():
     ap.add_argument("--events", type=int, default=0, help="override the number of events")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--precision", default="", choices=["", "f64", "mixed"])
-    ap.add_argument("--policy", default="none", choices=["none", "partition", "radix"])
+    ap.add_argument("--policy", default="queue", choices=["none", "partition", "radix", "queue"])
     ap.add_argument("--init-partition", type=int, default=0)
     ap.add_argument("--max-substeps", type=int, default=10)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0, help="iterations per captured HIP graph (0 = plain launches)")
+    ap.add_argument("--lds-tables", type=int, default=1)
+    ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=4000, help="oracle sample (events); 0 = skip")
@@ -91,7 +93,8 @@ def run_variant(w, args, precision, policy, init_partition, prof_kernel):
     s = emstep.Session(w.n_slots, precision=precision, max_events=w.n_events, max_slabs=st.n_slabs,
                        max_materials=len(st.materials), seed=w.seed, sort_policy=policy,
                        init_partition=init_partition, max_substeps=args.max_substeps, block_size=args.block_size,
-                       graph_iterations=args.graph, n_primaries=max(len(w.primaries), 1 << 16))
+                       graph_iterations=args.graph, lds_tables=args.lds_tables, streams=args.streams,
+                       n_primaries=max(len(w.primaries), 1 << 16))
     s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
     events = np.unique(w.primaries["event"])
 
@@ -177,8 +180,10 @@ def main():
         "config": {"workload": w.name, "events": w.n_events, "primaries": int(len(w.primaries)),
                    "n_slots": w.n_slots, "sort_policy": args.policy, "init_partition": args.init_partition,
                    "max_substeps": args.max_substeps, "graph_iterations": args.graph,
+                   "lds_tables": args.lds_tables, "streams": args.streams,
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
+        "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
     }
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
@@ -193,7 +198,8 @@ def main():
                            "tracks_per_launch": tracks / launches, "bytes_per_track": bpt}
     if args.compare:
         var = {}
-        for pol, part in [("none", 0), ("none", 1), ("partition", 0), ("partition", 1), ("radix", 0)]:
+        for pol, part in [("none", 0), ("none", 1), ("partition", 0), ("partition", 1), ("radix", 0),
+                          ("queue", 0), ("queue", 1)]:
             if pol == args.policy and part == args.init_partition:
                 continue
             rv = run_variant(w, args, precision, pol, part, None)

@@ -59,7 +59,16 @@ typedef enum {
 } ems_status;
 
 typedef enum { EMS_FP64 = 0, EMS_MIXED = 1 } ems_precision;
-typedef enum { EMS_SORT_NONE = 0, EMS_SORT_PARTITION = 1, EMS_SORT_RADIX = 2 } ems_sort_policy;
+/* Track ordering before the along-step and the interaction kernels:
+ *   NONE      every kernel runs over all slots and masks by next action;
+ *   PARTITION stable counting sort of slot indices by next action (LDS
+ *             histogram, scan, stable scatter) at both sort points;
+ *   RADIX     the same with the composite key action|particle|material;
+ *   QUEUE     the kernel that sets a track's next action appends its slot
+ *             to that action's list (wave-aggregated), so each kernel runs
+ *             over exactly its tracks without a separate sort pass; slot
+ *             order inside a list is ascending per wavefront. */
+typedef enum { EMS_SORT_NONE = 0, EMS_SORT_PARTITION = 1, EMS_SORT_RADIX = 2, EMS_SORT_QUEUE = 3 } ems_sort_policy;
 typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_particle;
 
 /* Physics table layout (per material, in this order, 181 nodes each):
@@ -83,7 +92,13 @@ typedef struct {
     int32_t max_substeps;      /* field substeps per track per iteration; <= 0 means unlimited */
     uint64_t seed;             /* Philox key word 0 */
     int32_t block_size;        /* threads per block for the step kernels; 0 = 256 */
-    int32_t graph_iterations;  /* iterations captured per HIP graph in ems_run; 0 = plain launches */
+    int32_t graph_iterations;  /* iterations captured per HIP graph in ems_run (needs a non-null
+                                  stream); 0 = plain launches */
+    int32_t lds_tables;        /* 1: each block of the pre-step and along-step kernels stages the
+                                  physics tables in LDS; 0: tables are read through the caches */
+    int32_t streams;           /* 1..4: independent kernels of an iteration (the along-step kernels;
+                                  the interaction kernels) run as concurrent branches on up to this
+                                  many default-priority streams created by the library */
 } ems_options;
 
 typedef struct { double Z, A, density, I_eV; } ems_material;

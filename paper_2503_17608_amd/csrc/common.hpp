@@ -102,6 +102,9 @@ struct Counters {
     unsigned int range_off[16];        // sorted mode: start of each action's index range
     unsigned int range_cnt[16];
     unsigned long long work[16];       // tracks processed per kernel role (see W_*)
+    unsigned int list_cnt[16];         // queue mode: entries of each action list (0 = pre-step list)
+    unsigned int alive_before;         // live tracks found by the vacancy pass (before the fill)
+    unsigned int pad2[3];
 };
 
 // work counter indices
@@ -156,19 +159,20 @@ template <class R>
 struct StepRng {
     uint64_t k0, k1, key, step;
     int j;
-    int have;          // block index cached in buf, -1 none
-    uint64_t buf[4];
+    int have;          // block index cached in b0..b3, -1 none
+    uint64_t b0, b1, b2, b3;
     __device__ StepRng(uint64_t seed, uint64_t event, uint64_t track_key, uint64_t step_, int j0)
-        : k0(seed), k1(event), key(track_key), step(step_), j(j0), have(-1) {}
+        : k0(seed), k1(event), key(track_key), step(step_), j(j0), have(-1), b0(0), b1(0), b2(0), b3(0) {}
     __device__ __forceinline__ R next()
     {
         int b = j >> 2;
         if (b != have) {
             U64x4 o = philox4x64_10(key, step, (uint64_t)b, 0, k0, k1);
-            buf[0] = o.w[0]; buf[1] = o.w[1]; buf[2] = o.w[2]; buf[3] = o.w[3];
+            b0 = o.w[0]; b1 = o.w[1]; b2 = o.w[2]; b3 = o.w[3];
             have = b;
         }
-        uint64_t w = buf[j & 3];
+        int q = j & 3;
+        uint64_t w = q == 0 ? b0 : (q == 1 ? b1 : (q == 2 ? b2 : b3));
         ++j;
         return unit_from<R>(w);
     }

@@ -47,7 +47,7 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 // Workspace layout: every region 256-byte aligned, offsets from the base.
 struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
-    uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, sort_cnt, bin_off, ctr;
+    uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, incr;
     uint64_t total;
     uint32_t n_tiles;
@@ -91,6 +91,7 @@ Layout make_layout(const ems_options& o)
     L.vac_cnt = take(4 * nvb);
     L.init_cnt = take(4 * nvb);
     L.perm = take(4 * n);
+    L.lists = o.sort_policy == EMS_SORT_QUEUE ? take(4ull * A_NUM * n) : take(0);
     L.n_tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
     L.sort_cnt = take(4ull * 128 * L.n_tiles);
     L.bin_off = take(4 * 256);
@@ -147,6 +148,11 @@ struct ems_ctx {
     uint64_t staging_cap = 0;
     hipEvent_t staging_ev;
     bool staging_busy = false;
+    // concurrent branches
+    int n_streams = 1;
+    hipStream_t workers[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev[2];
+    hipEvent_t join_ev[2][3];
     // graphs
     hipGraphExec_t graph = nullptr;
     int graph_iters = 0;
@@ -196,6 +202,7 @@ Dev<R> make_dev(const ems_ctx* c)
     d.vac_cnt = (uint32_t*)(b + L.vac_cnt);
     d.init_cnt = (uint32_t*)(b + L.init_cnt);
     d.perm = (uint32_t*)(b + L.perm);
+    d.lists = (uint32_t*)(b + L.lists);
     d.ctr = (Counters*)(b + L.ctr);
     d.tb.v = (const R*)(b + (sizeof(R) == 8 ? L.tables64 : L.tables32));
     d.tb.ln_e0 = (R)c->ln_e0;
@@ -214,7 +221,9 @@ Dev<R> make_dev(const ems_ctx* c)
     d.ledger = (Ledger*)(b + L.ledger);
     d.edep_stride = (int)c->opt.max_slabs;
     d.max_substeps = c->opt.max_substeps;
-    d.sorted = c->opt.sort_policy != EMS_SORT_NONE;
+    d.sorted = c->opt.sort_policy == EMS_SORT_NONE ? 0 : (c->opt.sort_policy == EMS_SORT_QUEUE ? 2 : 1);
+    d.stage_tables = c->opt.lds_tables ? 1 : 0;
+    d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
 }
 
@@ -277,21 +286,39 @@ struct Launcher {
     ems_ctx* c;
     bool prof;
     template <class F>
-    void run(int role, F&& f)
+    void run(int role, hipStream_t st, F&& f)
     {
         if (prof && (c->prof_mask & (1u << role))) {
             hipEvent_t a, b;
             (void)hipEventCreate(&a);
             (void)hipEventCreate(&b);
-            (void)hipEventRecord(a, c->stream);
+            (void)hipEventRecord(a, st);
             f();
-            (void)hipEventRecord(b, c->stream);
+            (void)hipEventRecord(b, st);
             c->prof_events.push_back({role, {a, b}});
         } else {
             f();
         }
     }
+    template <class F>
+    void run(int role, F&& f) { run(role, c->stream, f); }
 };
+
+// fork: workers [0, k) wait for the work enqueued so far on the main stream
+void fork(ems_ctx* c, int point, int k)
+{
+    (void)hipEventRecord(c->fork_ev[point], c->stream);
+    for (int i = 0; i < k; ++i) (void)hipStreamWaitEvent(c->workers[i], c->fork_ev[point], 0);
+}
+
+// join: the main stream waits for workers [0, k)
+void join(ems_ctx* c, int point, int k)
+{
+    for (int i = 0; i < k; ++i) {
+        (void)hipEventRecord(c->join_ev[point][i], c->workers[i]);
+        (void)hipStreamWaitEvent(c->stream, c->join_ev[point][i], 0);
+    }
+}
 
 template <class R>
 void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
@@ -339,20 +366,32 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
             }
         });
     }
-    ln.run(R_PRE, [&] { hipLaunchKernelGGL((k_pre_step<R>), dim3(g), dim3(bs), 0, st, d); });
-    if (d.sorted) launch_sort<R>(c, d, ln);
-    ln.run(R_ALONG_NEUTRAL, [&] { hipLaunchKernelGGL((k_along_straight<R, false>), dim3(g), dim3(bs), 0, st, d); });
+    const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
+    ln.run(R_PRE, [&] { hipLaunchKernelGGL((k_pre_step<R>), dim3(g), dim3(bs), lds, st, d); });
+    if (d.sorted == 1) launch_sort<R>(c, d, ln);
+    // along-step: photons and leptons are independent branches
+    const int nw = c->n_streams - 1;
+    hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
+    if (nw > 0) fork(c, 0, 1);
+    ln.run(R_ALONG_NEUTRAL, s_neutral,
+           [&] { hipLaunchKernelGGL((k_along_straight<R, false>), dim3(g), dim3(bs), lds, s_neutral, d); });
     if (d.has_field)
-        ln.run(R_ALONG_FIELD, [&] { hipLaunchKernelGGL((k_along_field<R>), dim3(g), dim3(bs), 0, st, d); });
+        ln.run(R_ALONG_FIELD, [&] { hipLaunchKernelGGL((k_along_field<R>), dim3(g), dim3(bs), lds, st, d); });
     else
-        ln.run(R_ALONG_CHARGED, [&] { hipLaunchKernelGGL((k_along_straight<R, true>), dim3(g), dim3(bs), 0, st, d); });
-    if (d.sorted) launch_sort<R>(c, d, ln);
-    ln.run(R_COMPTON, [&] { hipLaunchKernelGGL((k_interact<R, P_COMPTON>), dim3(g), dim3(bs), 0, st, d); });
-    ln.run(R_PHOTO, [&] { hipLaunchKernelGGL((k_interact<R, P_PHOTO>), dim3(g), dim3(bs), 0, st, d); });
-    ln.run(R_PAIR, [&] { hipLaunchKernelGGL((k_interact<R, P_PAIR>), dim3(g), dim3(bs), 0, st, d); });
-    ln.run(R_MOLLER, [&] { hipLaunchKernelGGL((k_interact<R, P_MOLLER>), dim3(g), dim3(bs), 0, st, d); });
-    ln.run(R_BHABHA, [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(g), dim3(bs), 0, st, d); });
-    ln.run(R_BREMS, [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(g), dim3(bs), 0, st, d); });
+        ln.run(R_ALONG_CHARGED,
+               [&] { hipLaunchKernelGGL((k_along_straight<R, true>), dim3(g), dim3(bs), lds, st, d); });
+    if (nw > 0) join(c, 0, 1);
+    if (d.sorted == 1) launch_sort<R>(c, d, ln);
+    // interactions: six independent branches spread over the streams
+    if (nw > 0) fork(c, 1, nw);
+    auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
+    ln.run(R_COMPTON, on(0), [&] { hipLaunchKernelGGL((k_interact<R, P_COMPTON>), dim3(g), dim3(bs), 0, on(0), d); });
+    ln.run(R_PHOTO, on(1), [&] { hipLaunchKernelGGL((k_interact<R, P_PHOTO>), dim3(g), dim3(bs), 0, on(1), d); });
+    ln.run(R_PAIR, on(2), [&] { hipLaunchKernelGGL((k_interact<R, P_PAIR>), dim3(g), dim3(bs), 0, on(2), d); });
+    ln.run(R_MOLLER, on(3), [&] { hipLaunchKernelGGL((k_interact<R, P_MOLLER>), dim3(g), dim3(bs), 0, on(3), d); });
+    ln.run(R_BHABHA, on(4), [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(g), dim3(bs), 0, on(4), d); });
+    ln.run(R_BREMS, on(5), [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(g), dim3(bs), 0, on(5), d); });
+    if (nw > 0) join(c, 1, nw);
 }
 
 void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
@@ -384,6 +423,7 @@ ems_status launch_batch(ems_ctx* c, int iters, bool no_init)
     bool prof = c->prof_mask != 0;
     int gi = c->opt.graph_iterations;
     if (gi > 0 && !prof && iters == gi) {
+        if (c->stream == nullptr) return fail(EMS_ERR_INVALID_ARG, "graph capture needs a non-null stream");
         if (!c->graph || c->graph_iters != gi || c->graph_no_init != (int)no_init) {
             ems_status s = drop_graph(c);
             if (s != EMS_OK) return s;
@@ -527,10 +567,11 @@ static ems_status validate(const ems_options* o)
     if (o->n_initializers == 0 || o->n_primaries == 0) return fail(EMS_ERR_INVALID_ARG, "buffer capacities");
     if (o->max_events == 0 || o->max_slabs == 0 || o->max_slabs > 65534 || o->max_materials == 0)
         return fail(EMS_ERR_INVALID_ARG, "max_events / max_slabs / max_materials");
-    if (o->sort_policy < 0 || o->sort_policy > 2) return fail(EMS_ERR_INVALID_ARG, "sort_policy");
+    if (o->sort_policy < 0 || o->sort_policy > 3) return fail(EMS_ERR_INVALID_ARG, "sort_policy");
     int bs = o->block_size;
     if (bs != 0 && (bs < 64 || bs > 1024 || (bs % 64) != 0)) return fail(EMS_ERR_INVALID_ARG, "block_size");
     if (o->graph_iterations < 0) return fail(EMS_ERR_INVALID_ARG, "graph_iterations");
+    if (o->streams < 0 || o->streams > 4) return fail(EMS_ERR_INVALID_ARG, "streams must be in [0, 4]");
     return EMS_OK;
 }
 
@@ -570,6 +611,14 @@ ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t b
     if (hipHostMalloc((void**)&c->staging, sizeof(Initializer) * c->staging_cap, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc staging"));
     (void)hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming);
+    c->n_streams = opt->streams > 1 ? opt->streams : 1;
+    for (int i = 0; i < c->n_streams - 1; ++i)
+        if (hipStreamCreateWithFlags(&c->workers[i], hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(EMS_ERR_DEVICE, "hipStreamCreate"));
+    for (int p = 0; p < 2; ++p) {
+        (void)hipEventCreateWithFlags(&c->fork_ev[p], hipEventDisableTiming);
+        for (int i = 0; i < 3; ++i) (void)hipEventCreateWithFlags(&c->join_ev[p][i], hipEventDisableTiming);
+    }
     // clear state: all slots vacant, counters and tallies zero, rows unassigned
     uint64_t n = opt->n_slots;
     hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, (uint8_t*)(c->ws + L.type), kDead, n);
@@ -601,6 +650,12 @@ void ems_destroy(ems_ctx* c)
     if (c->staging) {
         (void)hipHostFree(c->staging);
         (void)hipEventDestroy(c->staging_ev);
+        for (int i = 0; i < 3; ++i)
+            if (c->workers[i]) (void)hipStreamDestroy(c->workers[i]);
+        for (int p = 0; p < 2; ++p) {
+            (void)hipEventDestroy(c->fork_ev[p]);
+            for (int i = 0; i < 3; ++i) (void)hipEventDestroy(c->join_ev[p][i]);
+        }
     }
     delete c;
 }

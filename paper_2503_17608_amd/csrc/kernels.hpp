@@ -45,6 +45,7 @@ struct Dev {
     uint32_t* vac_cnt;      // per vacancy block
     uint32_t* init_cnt;     // per init block: charged initializers
     uint32_t* perm;
+    uint32_t* lists;        // queue mode: [A_NUM][n_slots] slot lists, list 0 = pre-step
     Counters* ctr;
     // physics / geometry
     Tables<R> tb;
@@ -61,10 +62,27 @@ struct Dev {
     Ledger* ledger;
     int edep_stride;
     int max_substeps;
-    int sorted;
+    int sorted;             // 0 masked over all slots, 1 sorted permutation ranges, 2 action lists
+    int stage_tables;       // copy the tables into LDS at block start
+    int n_tab;              // table values (n_materials * 8 * 181)
 };
 
+// Tables used by a block: staged into LDS (one copy per block, read by every
+// lookup of the block's tracks) or read through the caches.
+template <class R>
+__device__ __forceinline__ Tables<R> block_tables(const Dev<R>& d, R* lds)
+{
+    Tables<R> t = d.tb;
+    if (d.stage_tables) {
+        for (int i = threadIdx.x; i < d.n_tab; i += blockDim.x) lds[i] = d.tb.v[i];
+        __syncthreads();
+        t.v = lds;
+    }
+    return t;
+}
+
 constexpr int kVacBlock = 1024;   // slots per block of the vacancy and init kernels
+constexpr int kStepMaxBlock = 512;  // block-size bound of the step kernels (lets them keep state in VGPRs)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -79,6 +97,25 @@ __device__ __forceinline__ void count_work(const Dev<R>& d, int role, bool act)
 {
     uint64_t m = __ballot(act);
     if (lane_id() == 0 && m) atomicAdd(&d.ctr->work[role], (unsigned long long)__popcll(m));
+}
+
+// Queue mode: append slot s to the list of action `key` (lanes with act set).
+// One atomic per distinct key in the wave; lanes keep their order within it.
+template <class R>
+__device__ __forceinline__ void append_to_list(const Dev<R>& d, bool act, uint32_t key, uint32_t s)
+{
+    uint64_t pending = __ballot(act);
+    while (pending) {
+        int leader = __ffsll((unsigned long long)pending) - 1;
+        uint32_t lk = __shfl(key, leader, 64);
+        bool mine = act && key == lk;
+        uint64_t same = __ballot(mine);
+        uint32_t base = 0;
+        if (lane_id() == leader) base = atomicAdd(&d.ctr->list_cnt[lk], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if (mine) d.lists[(size_t)lk * d.n_slots + base + rank_below(same)] = s;
+        pending &= ~same;
+    }
 }
 
 // exclusive prefix of per-block counts: sum of cnt[0, b) with the whole block
@@ -125,6 +162,13 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
     uint32_t off = prefix;
     for (int i = 0; i < w; ++i) off += wcnt[i];
     if (v) d.vac[off + rank_below(m)] = s;
+    if (d.sorted == 2) {
+        // the complement, also in slot order: the pre-step list of live tracks
+        bool alive = (s < d.n_slots) && !v;
+        uint32_t alive_off = blockIdx.x * kVacBlock - prefix;
+        for (int i = 0; i < w; ++i) alive_off += 64u - wcnt[i];
+        if (alive) d.lists[alive_off + rank_below(~m & __ballot(s < d.n_slots))] = s;
+    }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         uint32_t blk = 0;
         for (int i = 0; i < kVacBlock / 64; ++i) blk += wcnt[i];
@@ -148,7 +192,10 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
         c->p_base = c->prim_next;
         c->queue_size = q - tq;
         c->prim_next += tp;
+        c->alive_before = d.n_slots - n_vac;
         c->n_alive += (uint32_t)(tq + tp);
+        c->list_cnt[0] = c->n_alive;
+        for (int a = 1; a < 16; ++a) c->list_cnt[a] = 0;
     }
 }
 
@@ -205,6 +252,7 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
     }
     count_work(d, W_INIT, act);
     if (!act) return;
+    if (d.sorted == 2) d.lists[c->alive_before + i] = slot;
     d.type[slot] = rec.type;
     d.action[slot] = A_IDLE;
     d.flags[slot] = 0;
@@ -231,14 +279,19 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
 // Iterate the tracks of action `a`: masked over all slots, or the index range
 // of `a` in the sorted permutation.  The loop bound is block-uniform so every
 // wave reaches the converged point at the end of each trip.
+#define EMS_TRACK_RANGE(d, a)                                                              \
+    const uint32_t _n = (d).sorted == 2 ? (d).ctr->list_cnt[a]                               \
+                        : ((d).sorted ? (d).ctr->range_cnt[a] : (d).n_slots);                \
+    const uint32_t _off = (d).sorted == 1 ? (d).ctr->range_off[a] : 0u;                     \
+    if (blockIdx.x * blockDim.x >= _n) return;
+
 #define EMS_FOR_TRACKS(d, a, s, act, role)                                                 \
-    const uint32_t _n = (d).sorted ? (d).ctr->range_cnt[a] : (d).n_slots;                    \
-    const uint32_t _off = (d).sorted ? (d).ctr->range_off[a] : 0u;                          \
     for (uint32_t _base = blockIdx.x * blockDim.x; _base < _n; _base += gridDim.x * blockDim.x) { \
         uint32_t _i = _base + threadIdx.x;                                                  \
         bool act = _i < _n;                                                                 \
         uint32_t s = 0;                                                                     \
-        if (act) s = (d).sorted ? (d).perm[_off + _i] : _i;                                 \
+        if (act) s = (d).sorted == 2 ? (d).lists[(size_t)(a) * (d).n_slots + _i]            \
+                     : ((d).sorted ? (d).perm[_off + _i] : _i);                             \
         if (act && (d).action[s] != (a)) act = false;                                       \
         count_work((d), (role), act);
 
@@ -263,23 +316,26 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
     uint32_t lo = __shfl((uint32_t)base, 0, 64), hi = __shfl((uint32_t)(base >> 32), 0, 64);
     base = ((unsigned long long)hi << 32) | lo;
     unsigned long long pos = base + (unsigned long long)(x - n);
-    for (int k = 0; k < n; ++k) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= n) break;
+        const Sec<R> v = sb.get(k);
         unsigned long long q = pos + (unsigned long long)k;
         if (q >= d.queue_cap) {
             atomicOr(&d.ctr->overflow, 1u);
             continue;
         }
         Initializer rec;
-        rec.T = (double)sb.T[k];
+        rec.T = (double)v.T;
         rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
-        rec.u[0] = (double)sb.u[k][0]; rec.u[1] = (double)sb.u[k][1]; rec.u[2] = (double)sb.u[k][2];
-        rec.key = sb.key[k];
+        rec.u[0] = (double)v.u[0]; rec.u[1] = (double)v.u[1]; rec.u[2] = (double)v.u[2];
+        rec.key = v.key;
         rec.row = row;
         rec.slab = slab;
-        rec.type = sb.type[k];
+        rec.type = (uint8_t)v.type;
         rec.pad = 0;
         d.queue[q] = rec;
-        atomicAdd(&d.ledger[row].n_sec[sb.type[k]], 1ull);
+        atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
     }
 }
 
@@ -304,48 +360,61 @@ __device__ __forceinline__ void retire(const Dev<R>& d, uint32_t s, uint32_t row
 
 // ---- pre-step: interaction length, physics step limit, along-step action -----------
 template <class R>
-__global__ void k_pre_step(Dev<R> d)
+__global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
 {
-    for (uint32_t base = blockIdx.x * blockDim.x; base < d.n_slots; base += gridDim.x * blockDim.x) {
-        uint32_t s = base + threadIdx.x;
-        bool act = s < d.n_slots;
+    extern __shared__ __align__(16) unsigned char ems_lds[];
+    const bool q = d.sorted == 2;
+    const uint32_t n = q ? d.ctr->list_cnt[0] : d.n_slots;
+    if (blockIdx.x * blockDim.x >= n) return;
+    const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        uint32_t i = base + threadIdx.x;
+        bool act = i < n;
+        uint32_t s = 0;
         uint8_t typ = kDead, fl = 0;
         if (act) {
+            s = q ? d.lists[i] : i;
             typ = d.type[s];
             act = typ != kDead;
         }
+        bool paused = false;
         if (act) {
             fl = d.flags[s];
-            act = !(fl & F_PAUSED);
+            paused = (fl & F_PAUSED) != 0;
+            act = !paused;
         }
         count_work(d, W_PRE, act);
-        if (!act) continue;
-        R T = d.T[s];
-        int mat = d.smat[d.slab[s]];
-        R nl = d.nl[s];
-        uint8_t nf = 0;
-        if (nl < R(0)) {
-            StepRng<R> rng(d.seed, d.row_event[d.row[s]], d.key[s], d.step[s], 0);
-            nl = -m_log(rng.next());
-            d.nl[s] = nl;
-            nf |= F_DREW;
-        }
-        Loc<R> l = locate(d.tb, T);
-        R sig = total_xs(d.tb, mat, typ, T, l, R(d.ecut));
-        R s_int = sig > R(0) ? nl / sig : R(INFINITY);
-        R s_phys = s_int;
-        if (typ != kGamma) {
-            R Rg = interp(range_tab(d.tb, mat, typ), l);
-            R s_loss = Rg <= R(kRFinal) ? Rg : m_max(R(kRFinal), R(kRhoRange) * Rg);
-            if (s_loss < s_int) {
-                s_phys = s_loss;
-                nf |= F_LOSS;
+        uint8_t na = A_FIELD;
+        if (act) {
+            R T = d.T[s];
+            int mat = d.smat[d.slab[s]];
+            R nl = d.nl[s];
+            uint8_t nf = 0;
+            if (nl < R(0)) {
+                StepRng<R> rng(d.seed, d.row_event[d.row[s]], d.key[s], d.step[s], 0);
+                nl = -m_log(rng.next());
+                d.nl[s] = nl;
+                nf |= F_DREW;
             }
+            Loc<R> l = locate(tb, T);
+            R sig = total_xs(tb, mat, typ, T, l, R(d.ecut));
+            R s_int = sig > R(0) ? nl / sig : R(INFINITY);
+            R s_phys = s_int;
+            if (typ != kGamma) {
+                R Rg = interp(range_tab(tb, mat, typ), l);
+                R s_loss = Rg <= R(kRFinal) ? Rg : m_max(R(kRFinal), R(kRhoRange) * Rg);
+                if (s_loss < s_int) {
+                    s_phys = s_loss;
+                    nf |= F_LOSS;
+                }
+            }
+            d.xs[s] = sig;
+            d.sphys[s] = (double)s_phys;
+            d.flags[s] = nf;
+            na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
+            d.action[s] = na;
         }
-        d.xs[s] = sig;
-        d.sphys[s] = (double)s_phys;
-        d.flags[s] = nf;
-        d.action[s] = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
+        if (q) append_to_list(d, act || paused, na, s);
     }
 }
 
@@ -386,21 +455,21 @@ __device__ __forceinline__ double straight_distance(const double r[3], const dou
 // Common end of an along-step (S6-S8) for a step of length s.  Returns true
 // when the track remains alive; sets the next action.
 template <class R, bool CHARGED>
-__device__ __forceinline__ void finish_along(const Dev<R>& d, uint32_t s, int typ, R& T, R sig, double step_len,
+__device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int typ, R& T, R sig, double step_len,
                                              int face, uint8_t fl, int mat, uint16_t& slab, const double r[3],
                                              SecBuf<R>& sb, StepTally& tl, const PhysParams& pp, bool& alive,
                                              uint8_t& next_action, R& nl)
 {
     uint32_t step = d.step[s];
     if (CHARGED) {
-        const R* Rt = range_tab(d.tb, mat, typ);
-        Loc<R> l = locate(d.tb, T);
+        const R* Rt = range_tab(tb, mat, typ);
+        Loc<R> l = locate(tb, T);
         R Rg = interp(Rt, l);
         bool stop = false;
         if (face == F_NONE && (fl & F_LOSS) && Rg <= R(kRFinal)) {
             stop = true;
         } else {
-            R Tn = inverse_range(d.tb, Rt, (R)((double)Rg - step_len));
+            R Tn = inverse_range(tb, Rt, (R)((double)Rg - step_len), l.i + 1);
             if (Tn < R(d.ecut)) stop = true;
             else {
                 tl.edep += (double)T - (double)Tn;
@@ -441,19 +510,15 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, uint32_t s, int ty
         R U1 = rng.next();
         R sig1;
         Loc<R> l1;
-        if (CHARGED) {
-            l1 = locate(d.tb, T);
-            sig1 = total_xs(d.tb, mat, typ, T, l1, R(d.ecut));
-        } else {
-            l1 = locate(d.tb, T);
-            sig1 = sig;
-        }
+        l1 = locate(tb, T);
+        if (CHARGED) sig1 = total_xs(tb, mat, typ, T, l1, R(d.ecut));
+        else sig1 = sig;
         nl = R(-1);
         if (sig1 > R(0)) {
             R target = U1 * sig1, cum = R(0);
             int proc = proc_of(typ, n_proc(typ) - 1);
             for (int k = 0; k < n_proc(typ); ++k) {
-                cum += proc_xs(d.tb, mat, proc_of(typ, k), T, l1, R(d.ecut));
+                cum += proc_xs(tb, mat, proc_of(typ, k), T, l1, R(d.ecut));
                 if (target < cum) { proc = proc_of(typ, k); break; }
             }
             next_action = (uint8_t)(A_PROC0 + proc);
@@ -477,15 +542,19 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, uint32_t s, int ty
 
 // ---- along-step, straight line (photons, or charged without field) ------------------
 template <class R, bool CHARGED>
-__global__ void k_along_straight(Dev<R> d)
+__global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
 {
+    extern __shared__ __align__(16) unsigned char ems_lds[];
     const uint8_t A = CHARGED ? A_CHARGED : A_NEUTRAL;
+    EMS_TRACK_RANGE(d, A)
+    const Tables<R> tb = block_tables(d, (R*)ems_lds);
     EMS_FOR_TRACKS(d, A, s, act, CHARGED ? W_CHARGED : W_NEUTRAL)
     SecBuf<R> sb;
     sb.n = 0;
     double r[3] = {0.0, 0.0, 0.0};
     uint32_t row = 0;
     uint16_t slab0 = 0;
+    uint8_t next = A_NONE;
     if (act) {
         int typ = d.type[s];
         row = d.row[s];
@@ -513,7 +582,7 @@ __global__ void k_along_straight(Dev<R> d)
         PhysParams pp = {d.seed, d.row_event[row], d.ecut};
         bool alive = true;
         uint8_t na = A_IDLE;
-        finish_along<R, CHARGED>(d, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+        finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
         record_tally(d, row, slab0, tl);
         d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
         if (alive) {
@@ -521,11 +590,13 @@ __global__ void k_along_straight(Dev<R> d)
             d.nl[s] = nl;
             d.slab[s] = slab;
             d.action[s] = na;
+            next = na;
         } else {
             retire(d, s, row, d.step[s]);
         }
     }
     append_secondaries(d, sb, row, slab0, r);
+    if (d.sorted == 2) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
 }
 
@@ -592,14 +663,18 @@ __device__ __forceinline__ void normalize_d(double v[3])
 // next iteration (paper, "Reducing load imbalance").  Momentum is fixed during
 // the step, so a paused step ends exactly as an uninterrupted one.
 template <class R>
-__global__ void k_along_field(Dev<R> d)
+__global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
 {
+    extern __shared__ __align__(16) unsigned char ems_lds[];
+    EMS_TRACK_RANGE(d, A_FIELD)
+    const Tables<R> tb = block_tables(d, (R*)ems_lds);
     EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
     SecBuf<R> sb;
     sb.n = 0;
     double r[3] = {0.0, 0.0, 0.0};
     uint32_t row = 0;
     uint16_t slab0 = 0;
+    uint8_t next = A_NONE;
     if (act) {
         int typ = d.type[s];
         row = d.row[s];
@@ -709,26 +784,29 @@ __global__ void k_along_field(Dev<R> d)
             PhysParams pp = {d.seed, d.row_event[row], d.ecut};
             bool alive = true;
             uint8_t na = A_IDLE;
-            finish_along<R, true>(d, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+            finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
             record_tally(d, row, slab0, tl);
             if (alive) {
                 d.T[s] = T;
                 d.nl[s] = nl;
                 d.slab[s] = slab;
                 d.action[s] = na;
+                next = na;
             } else {
                 retire(d, s, row, d.step[s]);
             }
         }
     }
     append_secondaries(d, sb, row, slab0, r);
+    if (d.sorted == 2) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
 }
 
 // ---- discrete interactions: one kernel per process ---------------------------------
 template <class R, int PROC>
-__global__ void k_interact(Dev<R> d)
+__global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
 {
+    EMS_TRACK_RANGE(d, (uint8_t)(A_PROC0 + PROC))
     EMS_FOR_TRACKS(d, (uint8_t)(A_PROC0 + PROC), s, act, W_PROC0 + PROC)
     SecBuf<R> sb;
     sb.n = 0;

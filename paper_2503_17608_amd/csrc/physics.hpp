@@ -94,17 +94,18 @@ __device__ __forceinline__ const R* range_tab(const Tables<R>& tb, int mat, int 
     return tb.tab(mat, type == kPositron ? TB_RANGE_EP : TB_RANGE_EM);
 }
 
-// Exact inverse of the piecewise-linear range map: the interval comes from an
-// upper-bound binary search on the node ranges; ln T is linear in R inside it.
+// Exact inverse of the piecewise-linear range map: the interval is the one an
+// upper-bound search on the node ranges finds (first node with R > r, minus
+// one); ln T is linear in R inside it.  The search walks down from a starting
+// node `j0` (the interval of the pre-step energy, since r <= R(T)), which
+// finds the same interval as a binary search in one or two probes.
 template <class R>
-__device__ __forceinline__ R inverse_range(const Tables<R>& tb, const R* Rt, R r)
+__device__ __forceinline__ R inverse_range(const Tables<R>& tb, const R* Rt, R r, int j0)
 {
-    int lo = 0, hi = kNodes;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (Rt[mid] > r) hi = mid; else lo = mid + 1;
-    }
-    int i = lo - 1;
+    int j = j0 < kNodes ? j0 : kNodes;
+    while (j < kNodes && !(Rt[j] > r)) ++j;
+    while (j > 0 && Rt[j - 1] > r) --j;
+    int i = j - 1;
     if (i < 0) i = 0;
     if (i > kNodes - 2) i = kNodes - 2;
     R t = R(i) + (r - Rt[i]) / (Rt[i + 1] - Rt[i]);
@@ -137,17 +138,34 @@ __device__ __forceinline__ void normalize3(R v[3])
     v[0] /= n; v[1] /= n; v[2] /= n;
 }
 
-// up to three secondaries produced by one track step
+// up to three secondaries produced by one track step, kept in registers
+// (fixed slots, selected with compile-time indices after unrolling)
+template <class R>
+struct Sec {
+    R T;
+    R u[3];
+    uint64_t key;
+    int type;
+};
+
 template <class R>
 struct SecBuf {
     int n;
-    uint8_t type[3];
-    R T[3];
-    R u[3][3];
-    uint64_t key[3];
+    Sec<R> s0, s1, s2;
     __device__ __forceinline__ void add(int t, R e, const R d[3], uint64_t k)
     {
-        type[n] = (uint8_t)t; T[n] = e; u[n][0] = d[0]; u[n][1] = d[1]; u[n][2] = d[2]; key[n] = k; ++n;
+        Sec<R> v;
+        v.T = e; v.u[0] = d[0]; v.u[1] = d[1]; v.u[2] = d[2]; v.key = k; v.type = t;
+        if (n == 0) s0 = v;
+        else if (n == 1) s1 = v;
+        else s2 = v;
+        ++n;
+    }
+    __device__ __forceinline__ Sec<R> get(int k) const
+    {
+        if (k == 0) return s0;
+        if (k == 1) return s1;
+        return s2;
     }
 };
 
@@ -167,7 +185,7 @@ struct PhysParams {
 // photons of m c^2, back to back, isotropic (Philox domain 4, block 0);
 // deposited locally when m c^2 is below the cut
 template <class R>
-__device__ void annihilate(const PhysParams& pp, uint64_t key, uint64_t step, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void annihilate(const PhysParams& pp, uint64_t key, uint64_t step, SecBuf<R>& sb, StepTally& tl)
 {
     tl.n_annih += 1;
     if (kMe < pp.ecut) {
@@ -208,7 +226,7 @@ __device__ __forceinline__ void stop_lepton(const PhysParams& pp, Prim<R>& t, Se
 }
 
 template <class R>
-__device__ void sample_compton(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void sample_compton(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
 {
     const R ec = R(pp.ecut);
     R E = t.T, kap = E / R(kMe);
@@ -250,7 +268,7 @@ __device__ void sample_compton(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng
 }
 
 template <class R>
-__device__ void sample_photo(const PhysParams& pp, Prim<R>& t, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void sample_photo(const PhysParams& pp, Prim<R>& t, SecBuf<R>& sb, StepTally& tl)
 {
     R Te = t.T;
     if (Te >= R(pp.ecut)) sb.add(kElectron, Te, t.u, child_key(pp.seed, pp.event, t.key, t.step, 0));
@@ -260,7 +278,7 @@ __device__ void sample_photo(const PhysParams& pp, Prim<R>& t, SecBuf<R>& sb, St
 }
 
 template <class R>
-__device__ void sample_pair(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void sample_pair(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
 {
     const R ec = R(pp.ecut);
     R E = t.T, a = R(kMe) / E, x = R(0.5);
@@ -288,7 +306,7 @@ __device__ void sample_pair(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, S
 }
 
 template <class R>
-__device__ void delta_final(const PhysParams& pp, Prim<R>& t, R eps, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void delta_final(const PhysParams& pp, Prim<R>& t, R eps, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
 {
     const R ec = R(pp.ecut);
     R T = t.T;
@@ -314,7 +332,7 @@ __device__ void delta_final(const PhysParams& pp, Prim<R>& t, R eps, StepRng<R>&
 }
 
 template <class R>
-__device__ void sample_moller(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void sample_moller(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
 {
     R T = t.T, xc = R(pp.ecut) / T;
     R g = (T + R(kMe)) / R(kMe);
@@ -333,7 +351,7 @@ __device__ void sample_moller(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng,
 }
 
 template <class R>
-__device__ void sample_bhabha(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void sample_bhabha(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
 {
     R T = t.T, xc = R(pp.ecut) / T;
     R g = (T + R(kMe)) / R(kMe);
@@ -355,7 +373,7 @@ __device__ void sample_bhabha(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng,
 }
 
 template <class R>
-__device__ void sample_brems(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
+__device__ __forceinline__ void sample_brems(const PhysParams& pp, Prim<R>& t, StepRng<R>& rng, SecBuf<R>& sb, StepTally& tl)
 {
     const R ec = R(pp.ecut);
     R T = t.T, E = T + R(kMe);

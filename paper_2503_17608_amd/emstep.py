@@ -11,6 +11,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch must be loaded before the library: its bundled HIP runtime carries the
+# same SONAME as the system one, so the library then binds to that single
+# runtime (the one that owns the workspace tensor and the stream)
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libemstep.so")
@@ -22,8 +26,8 @@ _lib = C.CDLL(LIB_PATH)
 
 ABI_VERSION = 1
 FP64, MIXED = 0, 1
-SORT_NONE, SORT_PARTITION, SORT_RADIX = 0, 1, 2
-SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX}
+SORT_NONE, SORT_PARTITION, SORT_RADIX, SORT_QUEUE = 0, 1, 2, 3
+SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX, "queue": SORT_QUEUE}
 GAMMA, ELECTRON, POSITRON = 0, 1, 2
 TABLE_NODES, TABLES_PER_MATERIAL = 181, 8
 
@@ -37,6 +41,7 @@ class Options(C.Structure):
         ("max_events", C.c_uint32), ("max_slabs", C.c_uint32), ("max_materials", C.c_uint32),
         ("sort_policy", C.c_int32), ("init_partition", C.c_int32), ("max_substeps", C.c_int32),
         ("seed", C.c_uint64), ("block_size", C.c_int32), ("graph_iterations", C.c_int32),
+        ("lds_tables", C.c_int32), ("streams", C.c_int32),
     ]
 
 
@@ -133,8 +138,8 @@ class Session:
 
     def __init__(self, n_slots, precision="f64", n_initializers=None, n_primaries=None, max_events=1024,
                  max_slabs=128, max_materials=4, sort_policy="none", init_partition=False, max_substeps=10,
-                 seed=1, block_size=0, graph_iterations=0, device="cuda:0", stream=None):
-        import torch
+                 seed=1, block_size=0, graph_iterations=0, lds_tables=1, streams=4, device="cuda:0",
+                 stream=None):
         o = Options()
         o.abi_version = ABI_VERSION
         o.precision = MIXED if precision in ("mixed", "f32", MIXED) else FP64
@@ -150,12 +155,20 @@ class Session:
         o.seed = int(seed)
         o.block_size = int(block_size)
         o.graph_iterations = int(graph_iterations)
+        o.lds_tables = int(lds_tables)
+        o.streams = int(streams)
         self.options = o
         nbytes = C.c_uint64(0)
         _check(_lib.ems_query_workspace(C.byref(o), C.byref(nbytes)), "ems_query_workspace")
         self.device = torch.device(device)
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if stream is not None:
+            self.stream = stream
+        elif graph_iterations > 0:
+            # graph capture needs a stream other than the null stream
+            self.stream = torch.cuda.Stream(self.device)
+        else:
+            self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         _check(_lib.ems_create(C.byref(o), C.c_void_p(self.workspace.data_ptr()), nbytes.value,
                                C.c_void_p(self.stream.cuda_stream), C.byref(h)), "ems_create")
