@@ -8,13 +8,21 @@ region of each step; the timed region covers the device loop only.
 
 Default workload: 10^4 electrons of 1 GeV into a 50-layer Pb (2 mm) / liquid
 Ar (5 mm) stack, 40 x 40 cm, uniform 1 T field along x, 0.1 MeV cut, 2^20
-track slots, FP64.
+track slots, FP64, slots sorted by next action, iterations replayed from
+captured HIP graphs.
 
-The JSON line carries the dominant kernel's roofline (algorithmic bytes per
-launch from the kernel's work counters and its per-track field traffic,
-divided by its average launch duration measured with HIP events on the
-library's stream during the timed steps) and the oracle's throughput on the
-host cores for a bounded sample of the same events.
+The JSON line carries the dominant kernel's roofline: algorithmic bytes per
+launch (the kernel's work counter times its per-track field traffic) divided
+by its average launch duration, measured with HIP events on the library's
+stream in one extra pass over the same batch (graph replay off for that pass),
+and the oracle's throughput on the host cores for a bounded sample of the same
+events.
+
+Other modes: --autotune (tune policy / tail threshold / block sizes on a
+sample first), --layer-error (per-layer deposit of this run against the FP64
+oracle on the same events), --serve (continuous batching with Poisson
+arrivals: p50/p99 event latency and throughput, against plain FP64 batch
+stepping of the same events).
 """
 from __future__ import annotations
 
@@ -43,12 +51,8 @@ BYTES_PER_TRACK = {
               "bremsstrahlung": 102, "init": 174},
 }
 
-WORKLOADS = {
-    "electron_showers_1gev_field": "electron_showers_1gev_field",
-    "small_electron_showers": "small_electron_showers",
-    "mixed_cone_showers": "mixed_cone_showers",
-    "batched_mixed_events": "batched_mixed_events",
-}
+WORKLOADS = ("electron_showers_1gev_field", "small_electron_showers", "mixed_cone_showers",
+             "batched_mixed_events", "serving_events")
 
 
 def parse():
@@ -56,21 +60,29 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="electron_showers_1gev_field", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="electron_showers_1gev_field", choices=WORKLOADS)
     ap.add_argument("--events", type=int, default=0, help="override the number of events")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--precision", default="", choices=["", "f64", "mixed"])
-    ap.add_argument("--policy", default="queue", choices=["none", "partition", "radix", "queue"])
+    ap.add_argument("--policy", default="partition", choices=["none", "partition", "radix", "queue"])
     ap.add_argument("--init-partition", type=int, default=0)
     ap.add_argument("--max-substeps", type=int, default=10)
     ap.add_argument("--block-size", type=int, default=0)
-    ap.add_argument("--graph", type=int, default=0, help="iterations per captured HIP graph (0 = plain launches)")
+    ap.add_argument("--graph", type=int, default=8, help="iterations per captured HIP graph (0 = plain launches)")
     ap.add_argument("--lds-tables", type=int, default=1)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=4000, help="oracle sample (events); 0 = skip")
     ap.add_argument("--compare", action="store_true", help="also time the other sort policies")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--layer-error", action="store_true")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-events", type=int, default=1000)
+    ap.add_argument("--load", type=float, default=0.7, help="arrival rate / closed-batch event rate")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the run, copy a device buffer of this size three times (a reference kernel "
+                         "of known traffic for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -79,61 +91,75 @@ def make_workload(name, events, slots):
     kw = {}
     if events:
         kw["n_events"] = events
-    w = getattr(workloads, WORKLOADS[name])(**kw)
+    w = getattr(workloads, name)(**kw)
     if slots:
         w.n_slots = slots
     return w
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel):
-    import torch
-
+def new_session(w, args, precision, policy, init_partition, graph=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
-    s = emstep.Session(w.n_slots, precision=precision, max_events=w.n_events, max_slabs=st.n_slabs,
+    s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
                        max_materials=len(st.materials), seed=w.seed, sort_policy=policy,
                        init_partition=init_partition, max_substeps=args.max_substeps, block_size=args.block_size,
-                       graph_iterations=args.graph, lds_tables=args.lds_tables, streams=args.streams,
-                       n_primaries=max(len(w.primaries), 1 << 16))
+                       graph_iterations=args.graph if graph is None else graph, lds_tables=args.lds_tables,
+                       streams=args.streams, n_primaries=max(len(w.primaries), 1 << 16))
     s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
+    return s
+
+
+def time_batch(s, primaries, events):
+    import torch
+    s.push(primaries)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = s.run(max_iterations=10_000_000)
+    torch.cuda.synchronize()
+    return c, time.perf_counter() - t0
+
+
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None):
+    s = new_session(w, args, precision, policy, init_partition)
     events = np.unique(w.primaries["event"])
-
-    def one_step():
-        s.push(w.primaries)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        c = s.run(max_iterations=10_000_000)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return c, dt
-
+    tuned = None
+    if tune is not None:
+        tuned = tune(s)
     for _ in range(args.warmup):
-        one_step()
+        time_batch(s, w.primaries, events)
         for e in events:
             s.release(int(e))
-    if prof_kernel:
-        s.profile(emstep.role_mask(prof_kernel))
-        s.profile_read()          # clear
     c0 = s.counters()
     total_t = 0.0
     iters = 0
     for k in range(args.steps):
         c_before = s.counters()
-        c, dt = one_step()
+        c, dt = time_batch(s, w.primaries, events)
         total_t += dt
         iters += c["iterations"] - c_before["iterations"]
-        if k + 1 < args.steps:
+        if k + 1 < args.steps or prof_kernel:
             for e in events:
                 s.release(int(e))
     c1 = s.counters()
-    prof = s.profile_read() if prof_kernel else {}
-    # one last correctness look: the energy ledger of the final step
+    prof = {}
+    work_prof = {}
+    if prof_kernel:
+        # one more pass over the same batch with HIP events around the kernel
+        from paper_2503_17608_amd import emstep
+        s.profile(emstep.role_mask(prof_kernel))
+        s.profile_read()
+        cp0 = s.counters()
+        time_batch(s, w.primaries, events)
+        cp1 = s.counters()
+        prof = s.profile_read()
+        s.profile(0)
+        work_prof = {k: cp1["work"][k] - cp0["work"][k] for k in cp1["work"]}
     edep, led = s.tallies_by_event(events)
     s.close()
     steps = c1["steps"] - c0["steps"]
     work = {k: c1["work"][k] - c0["work"][k] for k in c1["work"]}
     return {"steps": steps, "seconds": total_t, "iterations": iters, "work": work, "prof": prof,
-            "edep_total": float(edep.sum()), "escaped": float(led["escaped"].sum())}
+            "work_prof": work_prof, "edep": edep, "ledger": led, "tuned": tuned}
 
 
 def cpu_baseline(w, n_events):
@@ -151,6 +177,65 @@ def cpu_baseline(w, n_events):
             "sample": f"first {n_events} events of the workload ({steps} track-steps, {dt:.2f} s wall)"}
 
 
+def layer_error(w, edep):
+    """Per-layer mean deposit of `edep` against the FP64 oracle on the same events."""
+    import oracle
+    pb = oracle.problem_for(w)
+    tr, rows = oracle.tracks_from_primaries(w.primaries)
+    e_ref, _, _ = pb.run_events(tr, rows, w.n_events, len(os.sched_getaffinity(0)))
+    lg = edep.reshape(len(edep), -1, 2).sum(2).mean(0)
+    lr = e_ref.reshape(len(e_ref), -1, 2).sum(2).mean(0)
+    big = lr >= 0.01 * lr.sum()
+    err = np.abs(lg - lr) / np.where(lr > 0, lr, 1.0)
+    return {"max_rel_err_layers_ge_1pct": float(err[big].max()), "layers_checked": int(big.sum()),
+            "total_rel_err": float(abs(lg.sum() - lr.sum()) / lr.sum())}
+
+
+def serve_mode(args):
+    import torch
+
+    import workloads
+    from paper_2503_17608_amd import serving
+    w = workloads.serving_events(args.serve_events)
+    if args.slots:
+        w.n_slots = args.slots
+    events = serving.split_events(w.primaries)
+    precision = args.precision or "mixed"
+    # closed-batch event rate on a sample, to set the arrival rate
+    n_cal = min(64, len(events))
+    cal = np.concatenate([p for _, p in events[:n_cal]])
+    s = new_session(w, args, precision, args.policy, args.init_partition)
+    time_batch(s, cal, [e for e, _ in events[:n_cal]])
+    for e, _ in events[:n_cal]:
+        s.release(e)
+    _, dt_cal = time_batch(s, cal, [e for e, _ in events[:n_cal]])
+    for e, _ in events[:n_cal]:
+        s.release(e)
+    rate = args.load * n_cal / dt_cal
+    arrivals = workloads.poisson_arrival_times(w.seed, rate, len(events))
+    torch.cuda.synchronize()
+    res = serving.serve(s, events, arrivals, track_budget=w.n_slots, iterations_per_poll=max(args.graph, 1),
+                        keep_results=False)
+    s.close()
+    # plain FP64 batch stepping of the same events
+    s64 = new_session(w, args, "f64", args.policy, args.init_partition)
+    c64, dt64 = time_batch(s64, w.primaries, [e for e, _ in events])
+    s64.close()
+    out = {
+        "metric": "event latency p50/p99 and track-steps/s, continuous batching",
+        "value": res.steps / res.wall_s, "unit": "track-steps/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32+f64" if precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "events": len(events), "primaries": int(len(w.primaries)),
+                   "n_slots": w.n_slots, "arrival_rate_hz": rate, "load": args.load,
+                   "sort_policy": args.policy, "graph_iterations": args.graph},
+        "latency_ms": {"p50": 1e3 * res.percentile(50), "p99": 1e3 * res.percentile(99),
+                       "max": 1e3 * max(res.latency_s.values())},
+        "serve_wall_s": res.wall_s, "max_events_in_flight": res.max_in_flight,
+        "fp64_batch": {"value": c64["steps"] / dt64, "unit": "track-steps/s", "seconds": dt64},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -159,10 +244,26 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.serve:
+        serve_mode(args)
+        return
     w = make_workload(args.workload, args.events, args.slots)
     precision = args.precision or w.precision
     prof_kernel = None if args.no_roofline else args.roofline_kernel
-    r = run_variant(w, args, precision, args.policy, args.init_partition, prof_kernel)
+    tune = None
+    if args.autotune:
+        from paper_2503_17608_amd import autotune
+        ev = np.unique(w.primaries["event"])
+        sample = w.primaries[np.isin(w.primaries["event"], ev[: max(1, len(ev) // 8)])]
+        tune = lambda s: autotune.autotune(s, sample)  # noqa: E731
+    r = run_variant(w, args, precision, args.policy, args.init_partition, prof_kernel, tune)
     value = r["steps"] / r["seconds"]
     out = {
         "metric": "track-steps/s",
@@ -185,9 +286,11 @@ def main():
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
     }
+    if r["tuned"] is not None:
+        out["config"]["autotuned"] = {k: r["tuned"][k] for k in ("sort_policy", "tail_threshold", "block")}
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
-        tracks = r["work"][prof_kernel]
+        tracks = r["work_prof"][prof_kernel]
         bpt = BYTES_PER_TRACK[precision][prof_kernel]
         avg_s = ms / 1e3 / launches
         per_launch = tracks * bpt / launches
@@ -195,16 +298,20 @@ def main():
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                            "avg_launch_us": avg_s * 1e6, "launches": launches,
-                           "tracks_per_launch": tracks / launches, "bytes_per_track": bpt}
+                           "tracks_per_launch": tracks / launches, "bytes_per_track": bpt,
+                           "timing": "HIP events around every launch of the kernel in one extra pass over the "
+                                     "same batch (graph replay off for that pass)"}
     if args.compare:
         var = {}
         for pol, part in [("none", 0), ("none", 1), ("partition", 0), ("partition", 1), ("radix", 0),
-                          ("queue", 0), ("queue", 1)]:
+                          ("queue", 0)]:
             if pol == args.policy and part == args.init_partition:
                 continue
             rv = run_variant(w, args, precision, pol, part, None)
             var[f"{pol}+part{part}"] = rv["steps"] / rv["seconds"]
         out["variants"] = var
+    if args.layer_error:
+        out["layer_error_vs_fp64_oracle"] = layer_error(w, r["edep"])
     if args.cpu_events > 0:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_events, w.n_events))
     print(json.dumps(out), flush=True)

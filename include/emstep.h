@@ -64,10 +64,11 @@ typedef enum { EMS_FP64 = 0, EMS_MIXED = 1 } ems_precision;
  *   PARTITION stable counting sort of slot indices by next action (LDS
  *             histogram, scan, stable scatter) at both sort points;
  *   RADIX     the same with the composite key action|particle|material;
- *   QUEUE     the kernel that sets a track's next action appends its slot
- *             to that action's list (wave-aggregated), so each kernel runs
- *             over exactly its tracks without a separate sort pass; slot
- *             order inside a list is ascending per wavefront. */
+ *   QUEUE     PARTITION before the along-step kernels; before the
+ *             interaction kernels, the along-step kernels append each
+ *             interacting track's slot to its process list (wave-aggregated,
+ *             ascending slot order within a wavefront), so no second sort
+ *             pass runs. */
 typedef enum { EMS_SORT_NONE = 0, EMS_SORT_PARTITION = 1, EMS_SORT_RADIX = 2, EMS_SORT_QUEUE = 3 } ems_sort_policy;
 typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_particle;
 
@@ -91,7 +92,7 @@ typedef struct {
     int32_t init_partition;    /* 1: new charged tracks fill vacancies from the low end, neutral from the high end */
     int32_t max_substeps;      /* field substeps per track per iteration; <= 0 means unlimited */
     uint64_t seed;             /* Philox key word 0 */
-    int32_t block_size;        /* threads per block for the step kernels; 0 = 256 */
+    int32_t block_size;        /* threads per block for the step kernels (multiple of 64, <= 512); 0 = 256 */
     int32_t graph_iterations;  /* iterations captured per HIP graph in ems_run (needs a non-null
                                   stream); 0 = plain launches */
     int32_t lds_tables;        /* 1: each block of the pre-step and along-step kernels stages the
@@ -142,7 +143,7 @@ typedef struct {
     uint64_t pending_primaries;
     uint64_t steps;            /* completed steps of tracks that have finished */
     uint32_t overflow;         /* nonzero: the initializer buffer overflowed (results invalid) */
-    uint32_t pad;
+    uint32_t completed;        /* events completed since creation */
     /* cumulative tracks processed per kernel role: [1] init, [2] pre-step,
      * [4] neutral, [5] charged, [6] field along-step (track-iterations),
      * [7..12] Compton, photoelectric, pair, Moller, Bhabha, bremsstrahlung,
@@ -212,8 +213,10 @@ ems_status ems_run(ems_ctx* ctx, uint64_t max_iterations, ems_counters* out);
 /* Synchronize and read the counters. */
 ems_status ems_read_counters(ems_ctx* ctx, ems_counters* out);
 
-/* Events whose tracks have all finished since the last poll (serving).
- * Writes up to `cap` event ids to `events` and their count to *n. */
+/* Events whose tracks have all finished since the last poll (serving): an
+ * event completes when its last pushed primary and last secondary have
+ * retired.  Writes up to `cap` event ids to `events` (completion order) and
+ * their count to *n; synchronizes the stream. */
 ems_status ems_poll_completed(ems_ctx* ctx, uint64_t* events, uint32_t cap, uint32_t* n);
 
 /* Energy deposited per slab (n_slabs values) and the ledger of `event`. */
@@ -252,6 +255,21 @@ ems_status ems_debug_read_secondaries(ems_ctx* ctx, ems_track* out, uint64_t cap
  * (PARTITION: keys < 16; RADIX: keys < 256); perm[i] = index of the i-th
  * smallest key, equal keys in index order. */
 ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm);
+
+/* Run-time tuning (the autotuner's knobs; results do not depend on them).
+ * block[i] is the block size of kernel role i (role order as returned by
+ * ems_profile_read: vacancies, init, pre_step, sort, along_neutral,
+ * along_charged, along_field, compton, photoelectric, pair, moller, bhabha,
+ * bremsstrahlung); 0 keeps ems_options.block_size.  Below tail_threshold
+ * live tracks an iteration skips the reordering and runs masked (the device
+ * decides per iteration).  Setting it re-captures graphs on the next run. */
+typedef struct {
+    int32_t sort_policy;
+    uint32_t tail_threshold;
+    int32_t block[16];
+} ems_tuning;
+ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
+ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);
 
 /* Average duration [ms] of each kernel over the iterations launched since the
  * last call, measured with HIP events around every launch on the library's

@@ -102,9 +102,11 @@ struct Counters {
     unsigned int range_off[16];        // sorted mode: start of each action's index range
     unsigned int range_cnt[16];
     unsigned long long work[16];       // tracks processed per kernel role (see W_*)
-    unsigned int list_cnt[16];         // queue mode: entries of each action list (0 = pre-step list)
+    unsigned int list_cnt[16];         // queue policy: entries of each interaction list
     unsigned int alive_before;         // live tracks found by the vacancy pass (before the fill)
-    unsigned int pad2[3];
+    unsigned int done_count;           // events completed so far (entries written to the ring)
+    unsigned int phase_sorted;         // this iteration reorders tracks (occupancy above the tail threshold)
+    unsigned int pad2;
 };
 
 // work counter indices
@@ -116,7 +118,7 @@ enum : int {
 // Host-visible snapshot copied to pinned memory after each batch
 struct Snapshot {
     unsigned long long queue_size, prim_next, prim_end, iterations, steps_done;
-    unsigned int n_vac, n_alive, overflow, pad;
+    unsigned int n_vac, n_alive, overflow, done_count;
     unsigned long long work[16];
 };
 

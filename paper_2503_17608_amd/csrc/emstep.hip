@@ -48,7 +48,7 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
-    uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, incr;
+    uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, incr;
     uint64_t total;
     uint32_t n_tiles;
 };
@@ -91,7 +91,7 @@ Layout make_layout(const ems_options& o)
     L.vac_cnt = take(4 * nvb);
     L.init_cnt = take(4 * nvb);
     L.perm = take(4 * n);
-    L.lists = o.sort_policy == EMS_SORT_QUEUE ? take(4ull * A_NUM * n) : take(0);
+    L.lists = take(4ull * A_NUM * n);
     L.n_tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
     L.sort_cnt = take(4ull * 128 * L.n_tiles);
     L.bin_off = take(4 * 256);
@@ -105,6 +105,9 @@ Layout make_layout(const ems_options& o)
     L.row_event = take(8 * (uint64_t)o.max_events);
     L.edep = take(8 * (uint64_t)o.max_events * o.max_slabs);
     L.ledger = take(sizeof(Ledger) * (uint64_t)o.max_events);
+    L.live = take(4 * (uint64_t)o.max_events);
+    L.done_ring = take(8 * (uint64_t)o.max_events);
+    L.row_gen = take(4 * (uint64_t)o.max_events);
     L.incr = take(8ull * o.max_materials * 2 * (kNodes - 1));
     L.total = off;
     return L;
@@ -137,8 +140,10 @@ struct ems_ctx {
     std::vector<uint64_t> row_event;           // host copy, UINT64_MAX = free
     std::vector<uint32_t> free_rows;
     std::vector<uint64_t> row_pending;         // primaries pushed per row (for completion)
+    std::vector<uint32_t> row_gen;             // bumped at every registration of a row
     // primaries ring
     uint64_t prim_end = 0;                     // host-owned
+    uint32_t done_read = 0;                    // completion-ring entries already returned
     // pinned host memory
     Snapshot* snap = nullptr;                  // ring of snapshots
     int snap_slots = 4;
@@ -157,6 +162,10 @@ struct ems_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_iters = 0;
     int graph_no_init = -1;
+    // tuning (switchable at run time)
+    int policy = 0;
+    uint32_t tail_threshold = 0;
+    int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
@@ -220,8 +229,14 @@ Dev<R> make_dev(const ems_ctx* c)
     d.edep = (double*)(b + L.edep);
     d.ledger = (Ledger*)(b + L.ledger);
     d.edep_stride = (int)c->opt.max_slabs;
+    d.live = (unsigned int*)(b + L.live);
+    d.done_ring = (unsigned long long*)(b + L.done_ring);
+    d.row_gen = (const unsigned int*)(b + L.row_gen);
+    d.n_rows = c->opt.max_events;
     d.max_substeps = c->opt.max_substeps;
-    d.sorted = c->opt.sort_policy == EMS_SORT_NONE ? 0 : (c->opt.sort_policy == EMS_SORT_QUEUE ? 2 : 1);
+    d.sorted = c->policy == EMS_SORT_NONE ? 0 : 1;
+    d.sorted2 = c->policy == EMS_SORT_NONE ? 0 : (c->policy == EMS_SORT_QUEUE ? 2 : 1);
+    d.tail_threshold = c->tail_threshold;
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
@@ -247,14 +262,26 @@ __global__ void k_reset_queue(Counters* c)
     c->overflow = 0;
 }
 
-__global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double* edep, Ledger* led, uint32_t n_slabs)
+__global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double* edep, Ledger* led, uint32_t n_slabs,
+                          unsigned int* live, unsigned int* row_gen, unsigned int gen)
 {
     // register an event on a row and clear the row's tallies
     for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)row * n_slabs + i] = 0.0;
     if (threadIdx.x == 0) {
         row_event[row] = ev;
         led[row] = Ledger{};
+        live[row] = 0u;
+        row_gen[row] = gen;
     }
+}
+
+// pushed primaries count toward their event until they retire
+__global__ void k_count_primaries(const Initializer* prims, uint64_t cap, uint64_t start, uint64_t n,
+                                  unsigned int* live)
+{
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&live[prims[(start + i) % cap].row], 1u);
 }
 
 __global__ void k_snapshot(const Counters* c, Snapshot* out)
@@ -268,7 +295,7 @@ __global__ void k_snapshot(const Counters* c, Snapshot* out)
     s.n_vac = c->n_vac;
     s.n_alive = c->n_alive;
     s.overflow = c->overflow;
-    s.pad = 0;
+    s.done_count = c->done_count;
     for (int i = 0; i < 16; ++i) s.work[i] = c->work[i];
     *out = s;
 }
@@ -323,12 +350,12 @@ void join(ems_ctx* c, int point, int k)
 template <class R>
 void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
 {
-    const int policy = c->opt.sort_policy;
+    const int policy = c->policy;
     uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
     ln.run(R_SORT, [&] {
-        if (policy == EMS_SORT_PARTITION) {
+        if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
             hipLaunchKernelGGL((k_sort_hist<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n, cnt, nt);
             hipLaunchKernelGGL((k_sort_scan<16>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, d.ctr, 0, nullptr);
             hipLaunchKernelGGL((k_sort_scatter<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n,
@@ -347,10 +374,11 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
 {
     Dev<R> d = make_dev<R>(c);
     Launcher ln{c, prof};
-    const int bs = c->opt.block_size > 0 ? c->opt.block_size : 256;
+    const int bs_def = c->opt.block_size > 0 ? c->opt.block_size : 256;
     const uint32_t n = d.n_slots;
     const uint32_t nvb = (n + kVacBlock - 1) / kVacBlock;
-    const uint32_t g = grid_for(n, bs);
+    auto B = [&](int role) { return c->block[role] > 0 ? c->block[role] : bs_def; };
+    auto G = [&](int role) { return grid_for(n, B(role)); };
     hipStream_t st = c->stream;
     ln.run(R_VAC, [&] {
         hipLaunchKernelGGL((k_vac_count<R>), dim3(nvb), dim3(kVacBlock), 0, st, d);
@@ -367,30 +395,38 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         });
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
-    ln.run(R_PRE, [&] { hipLaunchKernelGGL((k_pre_step<R>), dim3(g), dim3(bs), lds, st, d); });
+    ln.run(R_PRE, [&] { hipLaunchKernelGGL((k_pre_step<R>), dim3(G(R_PRE)), dim3(B(R_PRE)), lds, st, d); });
     if (d.sorted == 1) launch_sort<R>(c, d, ln);
     // along-step: photons and leptons are independent branches
     const int nw = c->n_streams - 1;
     hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
     if (nw > 0) fork(c, 0, 1);
     ln.run(R_ALONG_NEUTRAL, s_neutral,
-           [&] { hipLaunchKernelGGL((k_along_straight<R, false>), dim3(g), dim3(bs), lds, s_neutral, d); });
+           [&] {
+               hipLaunchKernelGGL((k_along_straight<R, false>), dim3(G(R_ALONG_NEUTRAL)), dim3(B(R_ALONG_NEUTRAL)), lds,
+                                  s_neutral, d);
+           });
     if (d.has_field)
-        ln.run(R_ALONG_FIELD, [&] { hipLaunchKernelGGL((k_along_field<R>), dim3(g), dim3(bs), lds, st, d); });
+        ln.run(R_ALONG_FIELD, [&] {
+            hipLaunchKernelGGL((k_along_field<R>), dim3(G(R_ALONG_FIELD)), dim3(B(R_ALONG_FIELD)), lds, st, d);
+        });
     else
         ln.run(R_ALONG_CHARGED,
-               [&] { hipLaunchKernelGGL((k_along_straight<R, true>), dim3(g), dim3(bs), lds, st, d); });
+               [&] {
+                   hipLaunchKernelGGL((k_along_straight<R, true>), dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)),
+                                      lds, st, d);
+               });
     if (nw > 0) join(c, 0, 1);
-    if (d.sorted == 1) launch_sort<R>(c, d, ln);
+    if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
     // interactions: six independent branches spread over the streams
     if (nw > 0) fork(c, 1, nw);
     auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
-    ln.run(R_COMPTON, on(0), [&] { hipLaunchKernelGGL((k_interact<R, P_COMPTON>), dim3(g), dim3(bs), 0, on(0), d); });
-    ln.run(R_PHOTO, on(1), [&] { hipLaunchKernelGGL((k_interact<R, P_PHOTO>), dim3(g), dim3(bs), 0, on(1), d); });
-    ln.run(R_PAIR, on(2), [&] { hipLaunchKernelGGL((k_interact<R, P_PAIR>), dim3(g), dim3(bs), 0, on(2), d); });
-    ln.run(R_MOLLER, on(3), [&] { hipLaunchKernelGGL((k_interact<R, P_MOLLER>), dim3(g), dim3(bs), 0, on(3), d); });
-    ln.run(R_BHABHA, on(4), [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(g), dim3(bs), 0, on(4), d); });
-    ln.run(R_BREMS, on(5), [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(g), dim3(bs), 0, on(5), d); });
+    ln.run(R_COMPTON, on(0), [&] { hipLaunchKernelGGL((k_interact<R, P_COMPTON>), dim3(G(R_COMPTON)), dim3(B(R_COMPTON)), 0, on(0), d); });
+    ln.run(R_PHOTO, on(1), [&] { hipLaunchKernelGGL((k_interact<R, P_PHOTO>), dim3(G(R_PHOTO)), dim3(B(R_PHOTO)), 0, on(1), d); });
+    ln.run(R_PAIR, on(2), [&] { hipLaunchKernelGGL((k_interact<R, P_PAIR>), dim3(G(R_PAIR)), dim3(B(R_PAIR)), 0, on(2), d); });
+    ln.run(R_MOLLER, on(3), [&] { hipLaunchKernelGGL((k_interact<R, P_MOLLER>), dim3(G(R_MOLLER)), dim3(B(R_MOLLER)), 0, on(3), d); });
+    ln.run(R_BHABHA, on(4), [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d); });
+    ln.run(R_BREMS, on(5), [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d); });
     if (nw > 0) join(c, 1, nw);
 }
 
@@ -463,7 +499,7 @@ void to_counters(const Snapshot& s, ems_counters* out)
     out->pending_primaries = s.prim_end - s.prim_next;
     out->steps = s.steps_done;
     out->overflow = s.overflow;
-    out->pad = 0;
+    out->completed = s.done_count;
     for (int i = 0; i < 16; ++i) out->work[i] = s.work[i];
 }
 
@@ -478,6 +514,7 @@ __global__ void k_inject(Dev<R> d, const ems_track* t, uint64_t n)
         return;
     }
     const ems_track& r = t[i];
+    atomicAdd(&d.live[r.row], 1u);
     d.type[i] = (uint8_t)r.type;
     d.action[i] = A_IDLE;
     d.flags[i] = 0;
@@ -542,8 +579,10 @@ ems_status assign_row(ems_ctx* c, uint64_t ev, uint32_t* row)
     c->free_rows.pop_back();
     c->row_of[ev] = r;
     c->row_event[r] = ev;
+    c->row_gen[r] += 1;
     hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), r, ev,
-                       (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs);
+                       (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs,
+                       (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[r]);
     HIP_TRY(hipGetLastError());
     *row = r;
     return EMS_OK;
@@ -569,7 +608,7 @@ static ems_status validate(const ems_options* o)
         return fail(EMS_ERR_INVALID_ARG, "max_events / max_slabs / max_materials");
     if (o->sort_policy < 0 || o->sort_policy > 3) return fail(EMS_ERR_INVALID_ARG, "sort_policy");
     int bs = o->block_size;
-    if (bs != 0 && (bs < 64 || bs > 1024 || (bs % 64) != 0)) return fail(EMS_ERR_INVALID_ARG, "block_size");
+    if (bs != 0 && (bs < 64 || bs > 512 || (bs % 64) != 0)) return fail(EMS_ERR_INVALID_ARG, "block_size");
     if (o->graph_iterations < 0) return fail(EMS_ERR_INVALID_ARG, "graph_iterations");
     if (o->streams < 0 || o->streams > 4) return fail(EMS_ERR_INVALID_ARG, "streams must be in [0, 4]");
     return EMS_OK;
@@ -602,6 +641,7 @@ ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t b
     (void)hipGetDevice(&c->device);
     c->row_event.assign(opt->max_events, UINT64_MAX);
     c->row_pending.assign(opt->max_events, 0);
+    c->row_gen.assign(opt->max_events, 0);
     for (uint32_t r = opt->max_events; r > 0; --r) c->free_rows.push_back(r - 1);
     auto cleanup = [&](ems_status st) { ems_destroy(c); return st; };
     if (hipHostMalloc((void**)&c->snap, sizeof(Snapshot) * c->snap_slots, hipHostMallocDefault) != hipSuccess)
@@ -611,6 +651,7 @@ ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t b
     if (hipHostMalloc((void**)&c->staging, sizeof(Initializer) * c->staging_cap, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc staging"));
     (void)hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming);
+    c->policy = opt->sort_policy;
     c->n_streams = opt->streams > 1 ? opt->streams : 1;
     for (int i = 0; i < c->n_streams - 1; ++i)
         if (hipStreamCreateWithFlags(&c->workers[i], hipStreamNonBlocking) != hipSuccess)
@@ -814,6 +855,9 @@ ems_status ems_push_primaries(ems_ctx* c, const ems_primary* p, uint64_t n)
                                    hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipEventRecord(c->staging_ev, c->stream));
         c->staging_busy = true;
+        hipLaunchKernelGGL(k_count_primaries, dim3((chunk + 255) / 256), dim3(256), 0, c->stream, (const Initializer*)dst,
+                           cap, c->prim_end, chunk, (unsigned int*)(c->ws + c->L.live));
+        HIP_TRY(hipGetLastError());
         c->prim_end += chunk;
         done += chunk;
     }
@@ -827,7 +871,14 @@ ems_status ems_step(ems_ctx* c, uint32_t iterations, ems_counters* out)
 {
     ems_status s = check_ready(c);
     if (s != EMS_OK) return s;
-    for (uint32_t i = 0; i < iterations; ++i) {
+    const uint32_t gi = c->opt.graph_iterations > 0 ? (uint32_t)c->opt.graph_iterations : 0;
+    uint32_t done = 0;
+    while (gi > 0 && iterations - done >= gi) {
+        s = launch_batch(c, (int)gi, false);
+        if (s != EMS_OK) return s;
+        done += gi;
+    }
+    for (; done < iterations; ++done) {
         s = launch_batch(c, 1, false);
         if (s != EMS_OK) return s;
     }
@@ -899,9 +950,33 @@ ems_status ems_read_counters(ems_ctx* c, ems_counters* out)
 
 ems_status ems_poll_completed(ems_ctx* c, uint64_t* events, uint32_t cap, uint32_t* n)
 {
-    (void)c; (void)events; (void)cap;
-    if (n) *n = 0;
-    return fail(EMS_ERR_UNSUPPORTED, "completion polling is not available in this build");
+    if (!c || !n || (!events && cap)) return fail(EMS_ERR_INVALID_ARG, "null");
+    *n = 0;
+    Snapshot sn;
+    ems_status s = snapshot_now(c, &sn);
+    if (s != EMS_OK) return s;
+    uint32_t rows_n = c->opt.max_events;
+    uint32_t avail = sn.done_count - c->done_read;
+    if (avail > rows_n) {
+        // older entries were overwritten; they belonged to registrations that were
+        // released without polling (at most rows_n registrations are live at once)
+        c->done_read = sn.done_count - rows_n;
+        avail = rows_n;
+    }
+    if (avail == 0) return EMS_OK;
+    std::vector<uint64_t> ring(rows_n);
+    HIP_TRY(hipMemcpyAsync(ring.data(), c->ws + c->L.done_ring, 8ull * rows_n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // entries of an earlier registration of a row (released without polling) are skipped
+    uint32_t m = 0, k = 0;
+    for (; k < avail && m < cap; ++k) {
+        uint64_t e = ring[(c->done_read + k) % rows_n];
+        uint32_t row = (uint32_t)e, gen = (uint32_t)(e >> 32);
+        if (row < rows_n && c->row_gen[row] == gen && c->row_event[row] != UINT64_MAX) events[m++] = c->row_event[row];
+    }
+    c->done_read += k;
+    *n = m;
+    return EMS_OK;
 }
 
 ems_status ems_read_edep(ems_ctx* c, uint64_t event, double* per_slab, uint32_t n_slabs, ems_ledger* ledger)
@@ -951,9 +1026,11 @@ ems_status ems_release_event(ems_ctx* c, uint64_t event)
     c->row_of.erase(it);
     c->row_event[row] = UINT64_MAX;
     c->row_pending[row] = 0;
+    c->row_gen[row] += 1;
     hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), row,
                        (uint64_t)UINT64_MAX, (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger),
-                       (uint32_t)c->opt.max_slabs);
+                       (uint32_t)c->opt.max_slabs, (unsigned int*)(c->ws + c->L.live),
+                       (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[row]);
     HIP_TRY(hipGetLastError());
     c->free_rows.push_back(row);
     return EMS_OK;
@@ -1077,6 +1154,30 @@ ems_status ems_debug_sort(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t p
     (void)hipFree(dk);
     (void)hipFree(dp);
     (void)hipFree(cnt);
+    return EMS_OK;
+}
+
+ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
+{
+    if (!c || !t) return fail(EMS_ERR_INVALID_ARG, "null");
+    if (t->sort_policy < 0 || t->sort_policy > 3) return fail(EMS_ERR_INVALID_ARG, "sort_policy");
+    for (int i = 0; i < 16; ++i) {
+        int b = t->block[i];
+        if (b != 0 && (b < 64 || b > 512 || (b % 64) != 0))
+            return fail(EMS_ERR_INVALID_ARG, "block sizes must be 0 or a multiple of 64 in [64, 512]");
+    }
+    c->policy = t->sort_policy;
+    c->tail_threshold = t->tail_threshold;
+    for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
+    return drop_graph(c);
+}
+
+ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
+{
+    if (!c || !t) return fail(EMS_ERR_INVALID_ARG, "null");
+    t->sort_policy = c->policy;
+    t->tail_threshold = c->tail_threshold;
+    for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }
 

@@ -45,7 +45,7 @@ struct Dev {
     uint32_t* vac_cnt;      // per vacancy block
     uint32_t* init_cnt;     // per init block: charged initializers
     uint32_t* perm;
-    uint32_t* lists;        // queue mode: [A_NUM][n_slots] slot lists, list 0 = pre-step
+    uint32_t* lists;        // queue policy: [A_NUM][n_slots] slot lists of the interaction actions
     Counters* ctr;
     // physics / geometry
     Tables<R> tb;
@@ -60,9 +60,15 @@ struct Dev {
     const uint64_t* row_event;
     double* edep;           // [rows][edep_stride]
     Ledger* ledger;
+    unsigned int* live;     // per row: primaries pending + tracks alive or queued
+    unsigned long long* done_ring;  // completed events as (generation << 32 | row), capacity rows
+    const unsigned int* row_gen;    // registration generation of each row
+    unsigned int n_rows;
     int edep_stride;
     int max_substeps;
-    int sorted;             // 0 masked over all slots, 1 sorted permutation ranges, 2 action lists
+    int sorted;             // along-step kernels: 0 masked over all slots, 1 sorted permutation ranges
+    int sorted2;            // interaction kernels: 0 masked, 1 sorted ranges, 2 lists filled by the along-step
+    unsigned int tail_threshold;  // below this many live tracks an iteration runs masked (no reordering)
     int stage_tables;       // copy the tables into LDS at block start
     int n_tab;              // table values (n_materials * 8 * 181)
 };
@@ -99,7 +105,36 @@ __device__ __forceinline__ void count_work(const Dev<R>& d, int role, bool act)
     if (lane_id() == 0 && m) atomicAdd(&d.ctr->work[role], (unsigned long long)__popcll(m));
 }
 
-// Queue mode: append slot s to the list of action `key` (lanes with act set).
+// Wave-level sum of `v` added to *counter by lane 0 (all lanes must call)
+__device__ __forceinline__ void wave_add(unsigned long long* counter, unsigned long long v)
+{
+    uint32_t lo = (uint32_t)v;
+    uint32_t hi = (uint32_t)(v >> 32);
+    unsigned long long sum = 0;
+    // counts are small: reduce the low word and the high word separately
+    for (int o = 32; o > 0; o >>= 1) {
+        lo += __shfl_down(lo, o, 64);
+        hi += __shfl_down(hi, o, 64);
+    }
+    sum = ((unsigned long long)hi << 32) + lo;
+    if (lane_id() == 0 && sum) atomicAdd(counter, sum);
+}
+
+// A retired track leaves its event; the last one out records the event as
+// complete.  Called after the track's own secondaries were appended (which
+// count the event up first), so the count cannot reach zero early.
+template <class R>
+__device__ __forceinline__ void leave_event(const Dev<R>& d, bool retired, uint32_t row)
+{
+    if (!retired) return;
+    unsigned int old = atomicSub(&d.live[row], 1u);
+    if (old == 1u) {
+        unsigned int k = atomicAdd(&d.ctr->done_count, 1u);
+        d.done_ring[k % d.n_rows] = ((unsigned long long)d.row_gen[row] << 32) | row;
+    }
+}
+
+// Queue policy: append slot s to the list of action `key` (lanes with act set).
 // One atomic per distinct key in the wave; lanes keep their order within it.
 template <class R>
 __device__ __forceinline__ void append_to_list(const Dev<R>& d, bool act, uint32_t key, uint32_t s)
@@ -162,13 +197,6 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
     uint32_t off = prefix;
     for (int i = 0; i < w; ++i) off += wcnt[i];
     if (v) d.vac[off + rank_below(m)] = s;
-    if (d.sorted == 2) {
-        // the complement, also in slot order: the pre-step list of live tracks
-        bool alive = (s < d.n_slots) && !v;
-        uint32_t alive_off = blockIdx.x * kVacBlock - prefix;
-        for (int i = 0; i < w; ++i) alive_off += 64u - wcnt[i];
-        if (alive) d.lists[alive_off + rank_below(~m & __ballot(s < d.n_slots))] = s;
-    }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         uint32_t blk = 0;
         for (int i = 0; i < kVacBlock / 64; ++i) blk += wcnt[i];
@@ -195,7 +223,8 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
         c->alive_before = d.n_slots - n_vac;
         c->n_alive += (uint32_t)(tq + tp);
         c->list_cnt[0] = c->n_alive;
-        for (int a = 1; a < 16; ++a) c->list_cnt[a] = 0;
+        for (int a = 1; a < 16; ++a) c->list_cnt[a] = 0;     // lists are refilled every iteration
+        c->phase_sorted = (d.sorted || d.sorted2) && c->n_alive >= d.tail_threshold ? 1u : 0u;
     }
 }
 
@@ -252,7 +281,6 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
     }
     count_work(d, W_INIT, act);
     if (!act) return;
-    if (d.sorted == 2) d.lists[c->alive_before + i] = slot;
     d.type[slot] = rec.type;
     d.action[slot] = A_IDLE;
     d.flags[slot] = 0;
@@ -280,9 +308,10 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
 // of `a` in the sorted permutation.  The loop bound is block-uniform so every
 // wave reaches the converged point at the end of each trip.
 #define EMS_TRACK_RANGE(d, a)                                                              \
-    const uint32_t _n = (d).sorted == 2 ? (d).ctr->list_cnt[a]                               \
-                        : ((d).sorted ? (d).ctr->range_cnt[a] : (d).n_slots);                \
-    const uint32_t _off = (d).sorted == 1 ? (d).ctr->range_off[a] : 0u;                     \
+    const int _mode = (d).ctr->phase_sorted ? ((a) >= A_PROC0 ? (d).sorted2 : (d).sorted) : 0; \
+    const uint32_t _n = _mode == 2 ? (d).ctr->list_cnt[a]                                    \
+                        : (_mode ? (d).ctr->range_cnt[a] : (d).n_slots);                     \
+    const uint32_t _off = _mode == 1 ? (d).ctr->range_off[a] : 0u;                          \
     if (blockIdx.x * blockDim.x >= _n) return;
 
 #define EMS_FOR_TRACKS(d, a, s, act, role)                                                 \
@@ -290,8 +319,8 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
         uint32_t _i = _base + threadIdx.x;                                                  \
         bool act = _i < _n;                                                                 \
         uint32_t s = 0;                                                                     \
-        if (act) s = (d).sorted == 2 ? (d).lists[(size_t)(a) * (d).n_slots + _i]            \
-                     : ((d).sorted ? (d).perm[_off + _i] : _i);                             \
+        if (act) s = _mode == 2 ? (d).lists[(size_t)(a) * (d).n_slots + _i]                 \
+                     : (_mode ? (d).perm[_off + _i] : _i);                                  \
         if (act && (d).action[s] != (a)) act = false;                                       \
         count_work((d), (role), act);
 
@@ -336,6 +365,7 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
         rec.pad = 0;
         d.queue[q] = rec;
         atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
+        atomicAdd(&d.live[row], 1u);
     }
 }
 
@@ -348,14 +378,14 @@ __device__ __forceinline__ void record_tally(const Dev<R>& d, uint32_t row, int 
     if (tl.capped) atomicAdd(&d.ledger[row].n_reject_cap, 1ull);
 }
 
-// a track finishes: free its slot and add its steps to the event ledger
+// a track finishes: free its slot and add its steps to the event ledger (the
+// global step counter is summed per wavefront by the caller)
 template <class R>
 __device__ __forceinline__ void retire(const Dev<R>& d, uint32_t s, uint32_t row, uint32_t steps)
 {
     d.type[s] = kDead;
     d.action[s] = A_NONE;
     atomicAdd(&d.ledger[row].steps, (unsigned long long)steps);
-    atomicAdd(&d.ctr->steps_done, (unsigned long long)steps);
 }
 
 // ---- pre-step: interaction length, physics step limit, along-step action -----------
@@ -363,35 +393,41 @@ template <class R>
 __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
 {
     extern __shared__ __align__(16) unsigned char ems_lds[];
-    const bool q = d.sorted == 2;
-    const uint32_t n = q ? d.ctr->list_cnt[0] : d.n_slots;
+    const uint32_t n = d.n_slots;
     if (blockIdx.x * blockDim.x >= n) return;
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         uint32_t i = base + threadIdx.x;
         bool act = i < n;
         uint32_t s = 0;
+        if (act) s = i;
+        // issue every load of the slot up front (all in bounds for a valid
+        // index), so that the chain of dependent accesses is short
         uint8_t typ = kDead, fl = 0;
+        R T = R(0), nl = R(0);
+        uint16_t slab = 0;
+        uint32_t row = 0, step = 0;
+        uint64_t key = 0;
         if (act) {
-            s = q ? d.lists[i] : i;
             typ = d.type[s];
-            act = typ != kDead;
-        }
-        bool paused = false;
-        if (act) {
             fl = d.flags[s];
-            paused = (fl & F_PAUSED) != 0;
-            act = !paused;
+            T = d.T[s];
+            nl = d.nl[s];
+            slab = d.slab[s];
+            row = d.row[s];
+            step = d.step[s];
+            key = d.key[s];
         }
+        act = act && typ != kDead;
+        bool paused = act && (fl & F_PAUSED) != 0;
+        act = act && !paused;
         count_work(d, W_PRE, act);
         uint8_t na = A_FIELD;
         if (act) {
-            R T = d.T[s];
-            int mat = d.smat[d.slab[s]];
-            R nl = d.nl[s];
+            int mat = d.smat[slab];
             uint8_t nf = 0;
             if (nl < R(0)) {
-                StepRng<R> rng(d.seed, d.row_event[d.row[s]], d.key[s], d.step[s], 0);
+                StepRng<R> rng(d.seed, d.row_event[row], key, step, 0);
                 nl = -m_log(rng.next());
                 d.nl[s] = nl;
                 nf |= F_DREW;
@@ -414,7 +450,6 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
             na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
             d.action[s] = na;
         }
-        if (q) append_to_list(d, act || paused, na, s);
     }
 }
 
@@ -555,6 +590,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     uint32_t row = 0;
     uint16_t slab0 = 0;
     uint8_t next = A_NONE;
+    uint32_t retired = 0;
     if (act) {
         int typ = d.type[s];
         row = d.row[s];
@@ -592,11 +628,14 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
             d.action[s] = na;
             next = na;
         } else {
-            retire(d, s, row, d.step[s]);
+            retired = d.step[s];
+            retire(d, s, row, retired);
         }
     }
     append_secondaries(d, sb, row, slab0, r);
-    if (d.sorted == 2) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+    leave_event(d, retired != 0, row);
+    wave_add(&d.ctr->steps_done, retired);
+    if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
 }
 
@@ -675,6 +714,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     uint32_t row = 0;
     uint16_t slab0 = 0;
     uint8_t next = A_NONE;
+    uint32_t retired = 0, att = 0, paused_n = 0;
     if (act) {
         int typ = d.type[s];
         row = d.row[s];
@@ -698,9 +738,8 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
         double zlo = d.zp[slab], zhi = d.zp[slab + 1];
         int face = F_NONE;
         bool paused = false;
-        int att = 0;
         for (;;) {
-            if (d.max_substeps > 0 && att >= d.max_substeps) { paused = true; break; }
+            if (d.max_substeps > 0 && att >= (uint32_t)d.max_substeps) { paused = true; break; }
             double rem = s_phys - s_done;
             double h = h_try > 0.0 ? h_try : fmin(rem, h_chord);
             bool last = (h_try == 0.0 && h == rem);
@@ -766,8 +805,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
         }
         d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
         d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
-        atomicAdd(&d.ctr->work[W_SUBSTEPS], (unsigned long long)att);
-        if (paused) atomicAdd(&d.ctr->work[W_PAUSED], 1ull);
+        paused_n = paused ? 1u : 0u;
         if (paused) {
             d.sdone[s] = s_done;
             d.htry[s] = h_try;
@@ -793,12 +831,17 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
                 d.action[s] = na;
                 next = na;
             } else {
-                retire(d, s, row, d.step[s]);
+                retired = d.step[s];
+                retire(d, s, row, retired);
             }
         }
     }
     append_secondaries(d, sb, row, slab0, r);
-    if (d.sorted == 2) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+    leave_event(d, retired != 0, row);
+    wave_add(&d.ctr->steps_done, retired);
+    wave_add(&d.ctr->work[W_SUBSTEPS], att);
+    wave_add(&d.ctr->work[W_PAUSED], paused_n);
+    if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
 }
 
@@ -813,6 +856,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     double r[3] = {0.0, 0.0, 0.0};
     uint32_t row = 0;
     uint16_t slab = 0;
+    uint32_t retired = 0;
     if (act) {
         row = d.row[s];
         slab = d.slab[s];
@@ -851,10 +895,13 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
             d.nl[s] = R(-1);
             d.action[s] = A_IDLE;
         } else {
+            retired = steps;
             retire(d, s, row, steps);
         }
     }
     append_secondaries(d, sb, row, slab, r);
+    leave_event(d, retired != 0, row);
+    wave_add(&d.ctr->steps_done, retired);
     EMS_END_TRACKS
 }
 
@@ -881,6 +928,7 @@ template <class R, int NB>
 __global__ void __launch_bounds__(kSortThreads) k_sort_hist(Dev<R> d, int keymode, const uint8_t* ext_keys, uint32_t n,
                                                             uint32_t* cnt, uint32_t n_tiles)
 {
+    if (!ext_keys && !d.ctr->phase_sorted) return;
     __shared__ uint32_t h[NB];
     for (int b = threadIdx.x; b < NB; b += kSortThreads) h[b] = 0;
     __syncthreads();
@@ -901,6 +949,7 @@ template <int NB>
 __global__ void __launch_bounds__(1024) k_sort_scan(uint32_t* cnt, uint32_t n_tiles, Counters* ctr, int keymode,
                                                     uint32_t* bin_off)
 {
+    if (ctr && !ctr->phase_sorted) return;
     __shared__ uint32_t part[1024];
     uint32_t total = NB * n_tiles;
     uint32_t chunk = (total + 1023) / 1024;
@@ -953,6 +1002,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int key
                                                                uint32_t n, const uint32_t* cnt, uint32_t n_tiles,
                                                                uint32_t* perm)
 {
+    if (!ext_keys && !d.ctr->phase_sorted) return;
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t run[NB];
     __shared__ uint32_t wc[NW][NB];

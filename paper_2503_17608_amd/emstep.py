@@ -49,13 +49,17 @@ class Material(C.Structure):
     _fields_ = [("Z", C.c_double), ("A", C.c_double), ("density", C.c_double), ("I_eV", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16)]
+
+
 class Counters(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("alive", C.c_uint64), ("queued", C.c_uint64),
                 ("pending_primaries", C.c_uint64), ("steps", C.c_uint64), ("overflow", C.c_uint32),
-                ("pad", C.c_uint32), ("work", C.c_uint64 * 16)]
+                ("completed", C.c_uint32), ("work", C.c_uint64 * 16)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "work")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "work"}
         d["work"] = {name: int(self.work[i]) for i, name in WORK_INDEX.items()}
         return d
 
@@ -105,6 +109,8 @@ _sigs = {
     "ems_debug_read_tracks": (C.c_int, [_P, _P, C.c_uint64]),
     "ems_debug_read_secondaries": (C.c_int, [_P, _P, C.c_uint64, C.POINTER(C.c_uint64)]),
     "ems_debug_sort": (C.c_int, [_P, _P, C.c_uint64, C.c_int32, _P]),
+    "ems_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "ems_get_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
     "ems_profile_enable": (C.c_int, [_P, C.c_int32]),
     "ems_profile_read": (C.c_int, [_P, _P, _P, _P, C.c_uint32, C.POINTER(C.c_uint32)]),
 }
@@ -258,6 +264,16 @@ class Session:
     def release(self, event):
         _check(_lib.ems_release_event(self._h, int(event)), "ems_release_event")
 
+    def poll_completed(self, cap=4096):
+        ev = np.zeros(cap, dtype=np.uint64)
+        n = C.c_uint32(0)
+        _check(_lib.ems_poll_completed(self._h, _ptr(ev), cap, C.byref(n)), "ems_poll_completed")
+        return ev[: n.value]
+
+    def launch(self, iterations):
+        """Enqueue step iterations without waiting (graph batches when configured)."""
+        _check(_lib.ems_step(self._h, int(iterations), None), "ems_step")
+
     # -- test hooks ---------------------------------------------------------------------
     def register_event(self, event):
         r = C.c_uint32(0)
@@ -290,6 +306,25 @@ class Session:
         perm = np.zeros(len(k), dtype=np.uint32)
         _check(_lib.ems_debug_sort(self._h, _ptr(k), len(k), SORT_POLICIES[policy], _ptr(perm)), "ems_debug_sort")
         return perm
+
+    def tuning(self):
+        t = Tuning()
+        _check(_lib.ems_get_tuning(self._h, C.byref(t)), "ems_get_tuning")
+        return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
+                "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
+
+    def set_tuning(self, sort_policy=None, tail_threshold=None, block=None):
+        """Change knobs that affect speed only; block maps kernel role names to block sizes."""
+        cur = Tuning()
+        _check(_lib.ems_get_tuning(self._h, C.byref(cur)), "ems_get_tuning")
+        if sort_policy is not None:
+            cur.sort_policy = SORT_POLICIES[sort_policy] if isinstance(sort_policy, str) else int(sort_policy)
+        if tail_threshold is not None:
+            cur.tail_threshold = int(tail_threshold)
+        if block is not None:
+            for name, b in block.items():
+                cur.block[KERNEL_ROLES.index(name)] = int(b)
+        _check(_lib.ems_set_tuning(self._h, C.byref(cur)), "ems_set_tuning")
 
     def profile(self, mask):
         _check(_lib.ems_profile_enable(self._h, int(mask)), "ems_profile_enable")

@@ -239,3 +239,21 @@ def test_mixed_precision_per_layer_error():
     err = np.abs(lg[big] - lr[big]) / lr[big]
     print("mixed per-layer max rel err", err.max(), "steps", c["steps"], steps)
     assert err.max() <= 0.005
+
+
+def test_tuning_does_not_change_results():
+    w = workloads.electron_showers_1gev_field(20, n_slots=1 << 14)
+    e_ref, l_ref, steps = _run_oracle(w)
+    s = session_for(w, sort_policy="partition", graph_iterations=4)
+    for tuning in [dict(sort_policy="radix", tail_threshold=3000, block={"pre_step": 64, "along_field": 512}),
+                   dict(sort_policy="queue", tail_threshold=0, block={"along_neutral": 128, "compton": 448}),
+                   dict(sort_policy="none", tail_threshold=100000, block={"bremsstrahlung": 64})]:
+        s.set_tuning(**tuning)
+        s.push(w.primaries)
+        c = s.run()
+        edep, led = s.tallies_by_event(np.arange(w.n_events))
+        for e in range(w.n_events):
+            s.release(e)
+        assert _ledger_equal_int(led, l_ref) is None, tuning
+        assert np.abs(edep - e_ref).max() <= 1e-9 * 1000.0, tuning
+    s.close()

@@ -172,3 +172,13 @@ def poisson_arrival_times(seed: int, rate_hz: float, n: int) -> np.ndarray:
         t += -math.log(unit(w)) / rate_hz
         out[k] = t
     return out
+
+
+def serving_events(n_events: int = 1000, seed: int = 1, per_event=(1, 200), e_range=(10.0, 100000.0),
+                   first_event: int = 0) -> Workload:
+    """Events of 1-200 mixed primaries, log-uniform 10 MeV-100 GeV, +z; 50-layer stack, 1 T; for Poisson
+    arrivals (see poisson_arrival_times)."""
+    st = sampling_stack(50, 40.0, (1.0, 0.0, 0.0))
+    return Workload("pb_lar50_serving_1-200mixed_0.01-100GeV_B1T", st, 0.1, seed, n_events,
+                    make_primaries(seed, n_events, per_event, "mixed", e_range, first_event=first_event),
+                    1 << 23, precision="mixed")
