@@ -114,6 +114,11 @@ enum : int {
     W_INIT = 1, W_PRE = 2, W_SORT = 3, W_NEUTRAL = 4, W_CHARGED = 5, W_FIELD = 6, W_PROC0 = 7,
     W_PAUSED = 13, W_SUBSTEPS = 14
 };
+// partial-counter slots: [0, 16) work per kernel, [16, 32) completed steps of
+// the tracks each kernel retired (one slot per kernel, since kernels of an
+// iteration may run concurrently and every slot has a single writer)
+constexpr int kNumW = 32;
+constexpr int kStepsSlot = 16;
 
 // Host-visible snapshot copied to pinned memory after each batch
 struct Snapshot {

@@ -48,7 +48,8 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
-    uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, incr;
+    uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
+    uint32_t part_stride;
     uint64_t total;
     uint32_t n_tiles;
 };
@@ -108,6 +109,9 @@ Layout make_layout(const ems_options& o)
     L.live = take(4 * (uint64_t)o.max_events);
     L.done_ring = take(8 * (uint64_t)o.max_events);
     L.row_gen = take(4 * (uint64_t)o.max_events);
+    L.row_state = take(4 * (uint64_t)o.max_events);
+    L.part_stride = (uint32_t)std::max<uint64_t>(2048, nvb);
+    L.part = take(8ull * kNumW * L.part_stride);
     L.incr = take(8ull * o.max_materials * 2 * (kNodes - 1));
     L.total = off;
     return L;
@@ -232,6 +236,9 @@ Dev<R> make_dev(const ems_ctx* c)
     d.live = (unsigned int*)(b + L.live);
     d.done_ring = (unsigned long long*)(b + L.done_ring);
     d.row_gen = (const unsigned int*)(b + L.row_gen);
+    d.row_state = (unsigned int*)(b + L.row_state);
+    d.part = (unsigned long long*)(b + L.part);
+    d.part_stride = L.part_stride;
     d.n_rows = c->opt.max_events;
     d.max_substeps = c->opt.max_substeps;
     d.sorted = c->policy == EMS_SORT_NONE ? 0 : 1;
@@ -263,7 +270,7 @@ __global__ void k_reset_queue(Counters* c)
 }
 
 __global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double* edep, Ledger* led, uint32_t n_slabs,
-                          unsigned int* live, unsigned int* row_gen, unsigned int gen)
+                          unsigned int* live, unsigned int* row_gen, unsigned int gen, unsigned int* row_state)
 {
     // register an event on a row and clear the row's tallies
     for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)row * n_slabs + i] = 0.0;
@@ -272,6 +279,7 @@ __global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double
         led[row] = Ledger{};
         live[row] = 0u;
         row_gen[row] = gen;
+        row_state[row] = ev != UINT64_MAX ? 1u : 0u;
     }
 }
 
@@ -284,20 +292,36 @@ __global__ void k_count_primaries(const Initializer* prims, uint64_t cap, uint64
     atomicAdd(&live[prims[(start + i) % cap].row], 1u);
 }
 
-__global__ void k_snapshot(const Counters* c, Snapshot* out)
+// Copy the loop counters and sum the per-block partial counters (one block)
+__global__ void __launch_bounds__(1024) k_snapshot(const Counters* c, const unsigned long long* part, uint32_t stride,
+                                                   Snapshot* out)
 {
-    Snapshot s;
-    s.queue_size = c->queue_size;
-    s.prim_next = c->prim_next;
-    s.prim_end = c->prim_end;
-    s.iterations = c->iterations;
-    s.steps_done = c->steps_done;
-    s.n_vac = c->n_vac;
-    s.n_alive = c->n_alive;
-    s.overflow = c->overflow;
-    s.done_count = c->done_count;
-    for (int i = 0; i < 16; ++i) s.work[i] = c->work[i];
-    *out = s;
+    __shared__ unsigned long long acc[kNumW];
+    if (threadIdx.x < kNumW) acc[threadIdx.x] = 0;
+    __syncthreads();
+    for (int w = 0; w < kNumW; ++w) {
+        unsigned long long v = 0;
+        for (uint32_t i = threadIdx.x; i < stride; i += blockDim.x) v += part[(size_t)w * stride + i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(&acc[w], v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Snapshot s;
+        s.queue_size = c->queue_size;
+        s.prim_next = c->prim_next;
+        s.prim_end = c->prim_end;
+        s.iterations = c->iterations;
+        unsigned long long steps = 0;
+        for (int i = kStepsSlot; i < kNumW; ++i) steps += acc[i];
+        s.steps_done = steps;
+        s.n_vac = c->n_vac;
+        s.n_alive = c->n_alive;
+        s.overflow = c->overflow;
+        s.done_count = c->done_count;
+        for (int i = 0; i < 16; ++i) s.work[i] = acc[i];
+        *out = s;
+    }
 }
 
 uint32_t grid_for(uint64_t n, int bs)
@@ -352,19 +376,21 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
 {
     const int policy = c->policy;
     uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
+    uint32_t* tot = (uint32_t*)(c->ws + c->L.bin_off);
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
     ln.run(R_SORT, [&] {
         if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
             hipLaunchKernelGGL((k_sort_hist<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n, cnt, nt);
-            hipLaunchKernelGGL((k_sort_scan<16>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, d.ctr, 0, nullptr);
+            hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr, tot);
             hipLaunchKernelGGL((k_sort_scatter<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n,
-                               cnt, nt, d.perm);
+                               cnt, nt, (const uint32_t*)tot, d.perm);
         } else {
             hipLaunchKernelGGL((k_sort_hist<R, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, nullptr, n, cnt, nt);
-            hipLaunchKernelGGL((k_sort_scan<128>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, d.ctr, 1, nullptr);
+            hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
+                               tot);
             hipLaunchKernelGGL((k_sort_scatter<R, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, nullptr, n,
-                               cnt, nt, d.perm);
+                               cnt, nt, (const uint32_t*)tot, d.perm);
         }
     });
 }
@@ -428,6 +454,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     ln.run(R_BHABHA, on(4), [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d); });
     ln.run(R_BREMS, on(5), [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d); });
     if (nw > 0) join(c, 1, nw);
+    hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
 }
 
 void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
@@ -483,7 +510,8 @@ ems_status launch_batch(ems_ctx* c, int iters, bool no_init)
 ems_status snapshot_now(ems_ctx* c, Snapshot* out)
 {
     Snapshot* slot = &c->snap[0];
-    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, c->stream, (const Counters*)(c->ws + c->L.ctr), slot);
+    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1024), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
+                       (const unsigned long long*)(c->ws + c->L.part), c->L.part_stride, slot);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     *out = *slot;
@@ -582,7 +610,8 @@ ems_status assign_row(ems_ctx* c, uint64_t ev, uint32_t* row)
     c->row_gen[r] += 1;
     hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), r, ev,
                        (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs,
-                       (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[r]);
+                       (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[r],
+                       (unsigned int*)(c->ws + c->L.row_state));
     HIP_TRY(hipGetLastError());
     *row = r;
     return EMS_OK;
@@ -908,8 +937,8 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
             if (s != EMS_OK) return s;
             launched += batch;
             int slot = (int)(seq % c->snap_slots);
-            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
-                               &c->snap[slot]);
+            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1024), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
+                               (const unsigned long long*)(c->ws + c->L.part), c->L.part_stride, &c->snap[slot]);
             HIP_TRY(hipEventRecord(c->snap_ev[slot], c->stream));
             ++seq;
             ++in_flight;
@@ -1030,7 +1059,7 @@ ems_status ems_release_event(ems_ctx* c, uint64_t event)
     hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), row,
                        (uint64_t)UINT64_MAX, (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger),
                        (uint32_t)c->opt.max_slabs, (unsigned int*)(c->ws + c->L.live),
-                       (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[row]);
+                       (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[row], (unsigned int*)(c->ws + c->L.row_state));
     HIP_TRY(hipGetLastError());
     c->free_rows.push_back(row);
     return EMS_OK;
@@ -1129,24 +1158,24 @@ ems_status ems_debug_sort(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t p
         if (keys[i] >= nb) return fail(EMS_ERR_INVALID_ARG, "key out of range for the policy");
     uint32_t nt = (uint32_t)((n + kSortTile - 1) / kSortTile);
     uint8_t* dk = nullptr;
-    uint32_t *dp = nullptr, *cnt = nullptr;
+    uint32_t *dp = nullptr, *cnt = nullptr, *tot = nullptr;
     HIP_TRY(hipMalloc(&dk, n));
     HIP_TRY(hipMalloc(&dp, 4 * n));
     HIP_TRY(hipMalloc(&cnt, 4ull * 128 * nt));
+    HIP_TRY(hipMalloc(&tot, 4ull * 128));
     HIP_TRY(hipMemcpyAsync(dk, keys, n, hipMemcpyHostToDevice, c->stream));
     Dev<double> d{};
     if (nb == 16) {
         hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk, (uint32_t)n, cnt, nt);
-        hipLaunchKernelGGL((k_sort_scan<16>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, (Counters*)nullptr, 0,
-                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr, tot);
         hipLaunchKernelGGL((k_sort_scatter<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk,
-                           (uint32_t)n, cnt, nt, dp);
+                           (uint32_t)n, cnt, nt, (const uint32_t*)tot, dp);
     } else {
         hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk, (uint32_t)n, cnt, nt);
-        hipLaunchKernelGGL((k_sort_scan<128>), dim3(1), dim3(1024), 0, c->stream, cnt, nt, (Counters*)nullptr, 1,
-                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
+                           tot);
         hipLaunchKernelGGL((k_sort_scatter<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk,
-                           (uint32_t)n, cnt, nt, dp);
+                           (uint32_t)n, cnt, nt, (const uint32_t*)tot, dp);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(perm, dp, 4 * n, hipMemcpyDeviceToHost, c->stream));

@@ -60,6 +60,9 @@ struct Dev {
     const uint64_t* row_event;
     double* edep;           // [rows][edep_stride]
     Ledger* ledger;
+    unsigned long long* part;   // per-block partial counters [kNumW][part_stride] (no global atomics)
+    unsigned int part_stride;
+    unsigned int* row_state;    // 1 while an event occupies the row and has not been reported complete
     unsigned int* live;     // per row: primaries pending + tracks alive or queued
     unsigned long long* done_ring;  // completed events as (generation << 32 | row), capacity rows
     const unsigned int* row_gen;    // registration generation of each row
@@ -97,41 +100,37 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// one atomic per wave: number of active lanes
+// Per-block partial counters: every block adds its own entry with a plain
+// read-modify-write (only that block writes it during a launch), so hot
+// kernels issue no same-address global atomics; the snapshot kernel sums the
+// entries.  All threads of the block must call (block-uniform control flow).
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v)
+{
+    __shared__ unsigned long long red[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nw; ++i) t += red[i];
+    return t;          // valid in thread 0
+}
+
 template <class R>
-__device__ __forceinline__ void count_work(const Dev<R>& d, int role, bool act)
+__device__ __forceinline__ void flush_count(const Dev<R>& d, int role, unsigned long long v)
 {
-    uint64_t m = __ballot(act);
-    if (lane_id() == 0 && m) atomicAdd(&d.ctr->work[role], (unsigned long long)__popcll(m));
+    unsigned long long t = block_sum(v);
+    if (threadIdx.x == 0 && t) d.part[(size_t)role * d.part_stride + blockIdx.x] += t;
 }
 
-// Wave-level sum of `v` added to *counter by lane 0 (all lanes must call)
-__device__ __forceinline__ void wave_add(unsigned long long* counter, unsigned long long v)
-{
-    uint32_t lo = (uint32_t)v;
-    uint32_t hi = (uint32_t)(v >> 32);
-    unsigned long long sum = 0;
-    // counts are small: reduce the low word and the high word separately
-    for (int o = 32; o > 0; o >>= 1) {
-        lo += __shfl_down(lo, o, 64);
-        hi += __shfl_down(hi, o, 64);
-    }
-    sum = ((unsigned long long)hi << 32) + lo;
-    if (lane_id() == 0 && sum) atomicAdd(counter, sum);
-}
-
-// A retired track leaves its event; the last one out records the event as
-// complete.  Called after the track's own secondaries were appended (which
-// count the event up first), so the count cannot reach zero early.
+// A retired track leaves its event (no-return atomic); completion is detected
+// after the iteration by the row scan.
 template <class R>
 __device__ __forceinline__ void leave_event(const Dev<R>& d, bool retired, uint32_t row)
 {
-    if (!retired) return;
-    unsigned int old = atomicSub(&d.live[row], 1u);
-    if (old == 1u) {
-        unsigned int k = atomicAdd(&d.ctr->done_count, 1u);
-        d.done_ring[k % d.n_rows] = ((unsigned long long)d.row_gen[row] << 32) | row;
-    }
+    if (retired) atomicSub(&d.live[row], 1u);
 }
 
 // Queue policy: append slot s to the list of action `key` (lanes with act set).
@@ -279,7 +278,7 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
     } else {
         if (act) slot = d.vac[i];
     }
-    count_work(d, W_INIT, act);
+    flush_count(d, W_INIT, act ? 1ull : 0ull);
     if (!act) return;
     d.type[slot] = rec.type;
     d.action[slot] = A_IDLE;
@@ -308,6 +307,7 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
 // of `a` in the sorted permutation.  The loop bound is block-uniform so every
 // wave reaches the converged point at the end of each trip.
 #define EMS_TRACK_RANGE(d, a)                                                              \
+    unsigned long long _work = 0;                                                           \
     const int _mode = (d).ctr->phase_sorted ? ((a) >= A_PROC0 ? (d).sorted2 : (d).sorted) : 0; \
     const uint32_t _n = _mode == 2 ? (d).ctr->list_cnt[a]                                    \
                         : (_mode ? (d).ctr->range_cnt[a] : (d).n_slots);                     \
@@ -322,29 +322,41 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
         if (act) s = _mode == 2 ? (d).lists[(size_t)(a) * (d).n_slots + _i]                 \
                      : (_mode ? (d).perm[_off + _i] : _i);                                  \
         if (act && (d).action[s] != (a)) act = false;                                       \
-        count_work((d), (role), act);
+        _work += act ? 1u : 0u;
 
 #define EMS_END_TRACKS }
 
-// ---- secondary append (wave-aggregated) ------------------------------------------
+// ---- secondary append (block-aggregated) ------------------------------------------
+// One global atomic per block that has secondaries (none if it has none);
+// lanes get consecutive initializer records in lane order within each wave.
+// All threads of the block must call it (block-uniform control flow).
 template <class R>
 __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row,
                                                    uint16_t slab, const double r[3])
 {
-    int n = sb.n;
-    int lane = lane_id();
+    __shared__ unsigned int wtot[16];
+    __shared__ unsigned long long bbase;
+    const int n = sb.n;
+    if (__syncthreads_count(n) == 0) return;     // block-uniform
+    const int lane = lane_id(), w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     int x = n;
     for (int o = 1; o < 64; o <<= 1) {
         int y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    int total = __shfl(x, 63, 64);
-    if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&d.ctr->queue_size, (unsigned long long)total);
-    uint32_t lo = __shfl((uint32_t)base, 0, 64), hi = __shfl((uint32_t)(base >> 32), 0, 64);
-    base = ((unsigned long long)hi << 32) | lo;
-    unsigned long long pos = base + (unsigned long long)(x - n);
+    if (lane == 63) wtot[w] = (unsigned int)x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int tot = 0;
+        for (int i = 0; i < nw; ++i) {
+            unsigned int t = wtot[i];
+            wtot[i] = tot;                            // exclusive prefix per wave
+            tot += t;
+        }
+        bbase = atomicAdd(&d.ctr->queue_size, (unsigned long long)tot);
+    }
+    __syncthreads();
+    unsigned long long pos = bbase + wtot[w] + (unsigned long long)(x - n);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (k >= n) break;
@@ -367,6 +379,7 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
         atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
         atomicAdd(&d.live[row], 1u);
     }
+    __syncthreads();                                  // wtot / bbase are reused by the next trip
 }
 
 template <class R>
@@ -396,6 +409,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
     const uint32_t n = d.n_slots;
     if (blockIdx.x * blockDim.x >= n) return;
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    unsigned long long work = 0;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         uint32_t i = base + threadIdx.x;
         bool act = i < n;
@@ -421,7 +435,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
         act = act && typ != kDead;
         bool paused = act && (fl & F_PAUSED) != 0;
         act = act && !paused;
-        count_work(d, W_PRE, act);
+        work += act ? 1u : 0u;
         uint8_t na = A_FIELD;
         if (act) {
             int mat = d.smat[slab];
@@ -451,6 +465,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
             d.action[s] = na;
         }
     }
+    flush_count(d, W_PRE, work);
 }
 
 // ---- geometry helpers -----------------------------------------------------------
@@ -583,6 +598,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     const uint8_t A = CHARGED ? A_CHARGED : A_NEUTRAL;
     EMS_TRACK_RANGE(d, A)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    unsigned long long ret_acc = 0;
     EMS_FOR_TRACKS(d, A, s, act, CHARGED ? W_CHARGED : W_NEUTRAL)
     SecBuf<R> sb;
     sb.n = 0;
@@ -634,9 +650,11 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     }
     append_secondaries(d, sb, row, slab0, r);
     leave_event(d, retired != 0, row);
-    wave_add(&d.ctr->steps_done, retired);
+    ret_acc += retired;
     if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
+    flush_count(d, CHARGED ? W_CHARGED : W_NEUTRAL, _work);
+    flush_count(d, kStepsSlot + (CHARGED ? W_CHARGED : W_NEUTRAL), ret_acc);
 }
 
 // ---- along-step in a uniform field -------------------------------------------------
@@ -707,6 +725,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     extern __shared__ __align__(16) unsigned char ems_lds[];
     EMS_TRACK_RANGE(d, A_FIELD)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0;
     EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
     SecBuf<R> sb;
     sb.n = 0;
@@ -838,11 +857,15 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     }
     append_secondaries(d, sb, row, slab0, r);
     leave_event(d, retired != 0, row);
-    wave_add(&d.ctr->steps_done, retired);
-    wave_add(&d.ctr->work[W_SUBSTEPS], att);
-    wave_add(&d.ctr->work[W_PAUSED], paused_n);
+    ret_acc += retired;
+    sub_acc += att;
+    pause_acc += paused_n;
     if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
+    flush_count(d, W_FIELD, _work);
+    flush_count(d, kStepsSlot + W_FIELD, ret_acc);
+    flush_count(d, W_SUBSTEPS, sub_acc);
+    flush_count(d, W_PAUSED, pause_acc);
 }
 
 // ---- discrete interactions: one kernel per process ---------------------------------
@@ -850,6 +873,7 @@ template <class R, int PROC>
 __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
 {
     EMS_TRACK_RANGE(d, (uint8_t)(A_PROC0 + PROC))
+    unsigned long long ret_acc = 0;
     EMS_FOR_TRACKS(d, (uint8_t)(A_PROC0 + PROC), s, act, W_PROC0 + PROC)
     SecBuf<R> sb;
     sb.n = 0;
@@ -901,8 +925,25 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     }
     append_secondaries(d, sb, row, slab, r);
     leave_event(d, retired != 0, row);
-    wave_add(&d.ctr->steps_done, retired);
+    ret_acc += retired;
     EMS_END_TRACKS
+    flush_count(d, W_PROC0 + PROC, _work);
+    flush_count(d, kStepsSlot + W_PROC0 + PROC, ret_acc);
+}
+
+// ---- event completion ---------------------------------------------------------------
+// After an iteration, an occupied row whose live count is zero has finished:
+// record it once in the completion ring (entries carry the row's generation).
+template <class R>
+__global__ void k_scan_completions(Dev<R> d)
+{
+    uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= d.n_rows) return;
+    if (d.row_state[row] == 1u && d.live[row] == 0u) {
+        d.row_state[row] = 0u;
+        unsigned int k = atomicAdd(&d.ctr->done_count, 1u);
+        d.done_ring[k % d.n_rows] = ((unsigned long long)d.row_gen[row] << 32) | row;
+    }
 }
 
 // ---- stable counting sort of slot indices by a small key ----------------------------
@@ -921,7 +962,7 @@ __device__ __forceinline__ uint32_t sort_key(const Dev<R>& d, uint32_t s, int ke
 }
 
 constexpr int kSortThreads = 256;
-constexpr int kSortTile = 4096;      // slots per sort block
+constexpr int kSortTile = 1024;      // slots per sort block
 
 // Per-tile histogram: cnt[bin * n_tiles + tile]
 template <class R, int NB>
@@ -943,56 +984,38 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(Dev<R> d, int keymod
     for (int b = threadIdx.x; b < NB; b += kSortThreads) cnt[b * n_tiles + blockIdx.x] = h[b];
 }
 
-// Exclusive scan of cnt (bin-major), in place, by one block; writes the
-// per-bin ranges of the actions into the counters.
+// Per-bin exclusive scan of the tile counts: block `bin` scans cnt[bin][*]
+// in place (tile order) and writes the bin's total.
 template <int NB>
-__global__ void __launch_bounds__(1024) k_sort_scan(uint32_t* cnt, uint32_t n_tiles, Counters* ctr, int keymode,
-                                                    uint32_t* bin_off)
+__global__ void __launch_bounds__(256) k_sort_scan(uint32_t* cnt, uint32_t n_tiles, const Counters* ctr,
+                                                   uint32_t* bin_total)
 {
     if (ctr && !ctr->phase_sorted) return;
-    __shared__ uint32_t part[1024];
-    uint32_t total = NB * n_tiles;
-    uint32_t chunk = (total + 1023) / 1024;
-    uint32_t b0 = threadIdx.x * chunk, b1 = b0 + chunk < total ? b0 + chunk : total;
-    uint32_t s = 0;
-    for (uint32_t i = b0; i < b1; ++i) s += cnt[i];
-    part[threadIdx.x] = s;
+    __shared__ uint32_t wsum[4];
+    const uint32_t bin = blockIdx.x;
+    uint32_t* c = cnt + (size_t)bin * n_tiles;
+    const uint32_t per = (n_tiles + 255) / 256;
+    const uint32_t t0 = threadIdx.x * per, t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
+    uint32_t local = 0;
+    for (uint32_t t = t0; t < t1; ++t) local += c[t];
+    // block-wide exclusive scan of the per-thread sums
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = local;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    uint32_t run = before + x - local;
+    for (uint32_t t = t0; t < t1; ++t) {
+        uint32_t v = c[t];
+        c[t] = run;
+        run += v;
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (uint32_t i = b0; i < b1; ++i) {
-        uint32_t c = cnt[i];
-        cnt[i] = run;
-        run += c;
-    }
-    __syncthreads();
-    // bin offsets and action ranges
-    if (threadIdx.x < NB) {
-        uint32_t b = threadIdx.x;
-        uint32_t off = cnt[b * n_tiles];
-        uint32_t end = (b + 1 < (uint32_t)NB) ? cnt[(b + 1) * n_tiles] : part[1023];
-        if (bin_off) { bin_off[b] = off; bin_off[NB + b] = end - off; }
-    }
-    __syncthreads();
-    if (ctr && threadIdx.x < 16) {
-        uint32_t a = threadIdx.x;
-        uint32_t lo_bin = keymode == 0 ? a : a << 3;
-        uint32_t hi_bin = keymode == 0 ? a + 1 : (a + 1) << 3;
-        if (lo_bin >= (uint32_t)NB) {
-            ctr->range_off[a] = part[1023];
-            ctr->range_cnt[a] = 0;
-        } else {
-            uint32_t off = cnt[lo_bin * n_tiles];
-            uint32_t end = hi_bin < (uint32_t)NB ? cnt[hi_bin * n_tiles] : part[1023];
-            ctr->range_off[a] = off;
-            ctr->range_cnt[a] = end - off;
-        }
-    }
+    if (threadIdx.x == 255) bin_total[bin] = before + x;
 }
 
 // Stable scatter: within a tile, items keep index order per key (wave
@@ -1000,13 +1023,37 @@ __global__ void __launch_bounds__(1024) k_sort_scan(uint32_t* cnt, uint32_t n_ti
 template <class R, int NB>
 __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int keymode, const uint8_t* ext_keys,
                                                                uint32_t n, const uint32_t* cnt, uint32_t n_tiles,
-                                                               uint32_t* perm)
+                                                               const uint32_t* bin_total, uint32_t* perm)
 {
     if (!ext_keys && !d.ctr->phase_sorted) return;
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t run[NB];
+    __shared__ uint32_t bbase[NB + 1];
     __shared__ uint32_t wc[NW][NB];
-    for (int b = threadIdx.x; b < NB; b += kSortThreads) run[b] = cnt[b * n_tiles + blockIdx.x];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < NB; ++b) {
+            bbase[b] = acc;
+            acc += bin_total[b];
+        }
+        bbase[NB] = acc;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < NB; b += kSortThreads) run[b] = bbase[b] + cnt[b * n_tiles + blockIdx.x];
+    if (!ext_keys && blockIdx.x == 0 && threadIdx.x < 16) {
+        // index range of each action in the sorted permutation
+        uint32_t a = threadIdx.x;
+        uint32_t lo_bin = keymode == 0 ? a : a << 3;
+        uint32_t hi_bin = keymode == 0 ? a + 1 : (a + 1) << 3;
+        if (lo_bin >= (uint32_t)NB) {
+            d.ctr->range_off[a] = bbase[NB];
+            d.ctr->range_cnt[a] = 0;
+        } else {
+            uint32_t end = hi_bin < (uint32_t)NB ? bbase[hi_bin] : bbase[NB];
+            d.ctr->range_off[a] = bbase[lo_bin];
+            d.ctr->range_cnt[a] = end - bbase[lo_bin];
+        }
+    }
     for (int b = threadIdx.x; b < NW * NB; b += kSortThreads) (&wc[0][0])[b] = 0;
     __syncthreads();
     int w = threadIdx.x >> 6;
