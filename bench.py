@@ -13,8 +13,11 @@ captured HIP graphs.
 
 The JSON line carries the dominant kernel's roofline: algorithmic bytes per
 launch (the kernel's work counter times its per-track field traffic) divided
-by its average launch duration, measured with HIP events on the library's
-stream in one extra pass over the same batch (graph replay off for that pass),
+by its average launch duration, measured with HIP start/stop events stamped by
+the kernel's own dispatch packets in one extra pass over the same batch (graph
+replay off for that pass); `traffic` is the calibrated hardware byte count per
+launch from a committed counter summary, when one was taken on the current
+kernel sources and this configuration,
 and the oracle's throughput on the host cores for a bounded sample of the same
 events.
 
@@ -50,6 +53,45 @@ BYTES_PER_TRACK = {
               "compton": 102, "photoelectric": 102, "pair": 102, "moller": 102, "bhabha": 102,
               "bremsstrahlung": 102, "init": 174},
 }
+
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest():
+    """SHA-256 over the library's kernel and ABI sources: hardware byte counts
+    taken on other sources do not describe the current kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2503_17608_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hpp", ".hip")))
+    files.append(os.path.join(ROOT, "include", "emstep.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel, key):
+    """Calibrated HBM bytes per launch of `kernel` from a committed counter
+    summary (a `traffic:` JSON line in profiles/*.md) taken on these exact
+    sources and this configuration; None when there is none."""
+    if not os.path.isdir(PROFILES):
+        return None
+    digest = source_digest()
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, name)):
+            if not line.startswith("traffic: "):
+                continue
+            try:
+                t = json.loads(line[len("traffic: "):])
+            except ValueError:
+                continue
+            if t.get("kernel") == kernel and t.get("sources_sha256") == digest and t.get("config") == key:
+                return t
+    return None
+
 
 WORKLOADS = ("electron_showers_1gev_field", "small_electron_showers", "mixed_cone_showers",
              "batched_mixed_events", "serving_events")
@@ -295,12 +337,19 @@ def main():
         avg_s = ms / 1e3 / launches
         per_launch = tracks * bpt / launches
         achieved = per_launch / avg_s / 1e9
+        key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
+               "init_partition": args.init_partition, "max_substeps": args.max_substeps}
+        t = committed_traffic(prof_kernel, key)
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": t["bytes_per_launch"] if t else None,
+                           "traffic_unit": "bytes/launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                           "algorithmic_bytes_per_launch": per_launch,
                            "avg_launch_us": avg_s * 1e6, "launches": launches,
                            "tracks_per_launch": tracks / launches, "bytes_per_track": bpt,
-                           "timing": "HIP events around every launch of the kernel in one extra pass over the "
-                                     "same batch (graph replay off for that pass)"}
+                           "timing": "HIP start/stop events stamped by the kernel's own dispatch packet "
+                                     "(hipExtLaunchKernel) on every launch of the kernel, in one extra pass over "
+                                     "the same batch (graph replay off for that pass)"}
     if args.compare:
         var = {}
         for pol, part in [("none", 0), ("none", 1), ("partition", 0), ("partition", 1), ("radix", 0),

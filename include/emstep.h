@@ -196,8 +196,10 @@ ems_status ems_read_tables(ems_ctx* ctx, double* out, uint64_t n_doubles);
 
 /* Queue primaries (copied to device).  Each event id is given a tally row on
  * first sight.  Errors: STATE (nothing loaded), INVALID_ARG (bad type, slab,
- * energy below the cut), CAPACITY (primary buffer or event rows full; nothing
- * is queued in that case). */
+ * energy below the cut or not finite, direction not unit, position outside
+ * the given slab or the lateral walls), CAPACITY (primary buffer or event
+ * rows full).  Nothing is queued when an error is returned.  n == 0 is a
+ * no-op. */
 ems_status ems_push_primaries(ems_ctx* ctx, const ems_primary* p, uint64_t n);
 
 /* Enqueue `iterations` step iterations (asynchronous; no host wait).  If

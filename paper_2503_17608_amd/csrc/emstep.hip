@@ -10,6 +10,7 @@
 // once into a HIP graph and replayed.  No synchronous memory operation is
 // issued inside the loop (paper, "Asynchronous memory management").
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdio>
@@ -137,6 +138,7 @@ struct ems_ctx {
     uint32_t n_materials = 0, n_slabs = 0;
     bool have_mats = false, have_geom = false, have_tables = false;
     double ecut = 0.0, half_width = 0.0, B[3] = {0, 0, 0};
+    std::vector<double> zp_host;   // z planes, for validating primaries
     double ln_e0, dlog;
     std::vector<ems_material> mats;
     // events
@@ -333,26 +335,41 @@ uint32_t grid_for(uint64_t n, int bs)
     return (uint32_t)g;
 }
 
+// Launches the step kernels.  For a profiled role the role's first kernel
+// carries the start event and its last kernel the stop event; both are
+// stamped by the kernels' own dispatch packets (hipExtLaunchKernel), so the
+// elapsed time is the execution of the role's kernels with no marker packets
+// in between.
 struct Launcher {
     ems_ctx* c;
     bool prof;
-    template <class F>
-    void run(int role, hipStream_t st, F&& f)
+    hipEvent_t start = nullptr;
+    template <class... KArgs, class... Args>
+    void k(int role, bool first, bool last, void (*kernel)(KArgs...), dim3 g, dim3 b, size_t lds, hipStream_t st,
+           Args... args)
     {
-        if (prof && (c->prof_mask & (1u << role))) {
-            hipEvent_t a, b;
+        if (!(prof && (c->prof_mask & (1u << role)))) {
+            kernel<<<g, b, lds, st>>>(args...);
+            return;
+        }
+        hipEvent_t a = nullptr, z = nullptr;
+        if (first) {
             (void)hipEventCreate(&a);
-            (void)hipEventCreate(&b);
-            (void)hipEventRecord(a, st);
-            f();
-            (void)hipEventRecord(b, st);
-            c->prof_events.push_back({role, {a, b}});
-        } else {
-            f();
+            start = a;
+        }
+        if (last) (void)hipEventCreate(&z);
+        hipExtLaunchKernelGGL(kernel, g, b, (uint32_t)lds, st, a, z, 0u, args...);
+        if (last) {
+            c->prof_events.push_back({role, {start, z}});
+            start = nullptr;
         }
     }
-    template <class F>
-    void run(int role, F&& f) { run(role, c->stream, f); }
+    // a role made of one kernel
+    template <class... KArgs, class... Args>
+    void one(int role, void (*kernel)(KArgs...), dim3 g, dim3 b, size_t lds, hipStream_t st, Args... args)
+    {
+        k(role, true, true, kernel, g, b, lds, st, args...);
+    }
 };
 
 // fork: workers [0, k) wait for the work enqueued so far on the main stream
@@ -379,20 +396,21 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
     uint32_t* tot = (uint32_t*)(c->ws + c->L.bin_off);
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
-    ln.run(R_SORT, [&] {
-        if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
-            hipLaunchKernelGGL((k_sort_hist<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n, cnt, nt);
-            hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr, tot);
-            hipLaunchKernelGGL((k_sort_scatter<R, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, nullptr, n,
-                               cnt, nt, (const uint32_t*)tot, d.perm);
-        } else {
-            hipLaunchKernelGGL((k_sort_hist<R, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, nullptr, n, cnt, nt);
-            hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
-                               tot);
-            hipLaunchKernelGGL((k_sort_scatter<R, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, nullptr, n,
-                               cnt, nt, (const uint32_t*)tot, d.perm);
-        }
-    });
+    if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
+        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
+             (const uint8_t*)nullptr, n, cnt, nt);
+        ln.k(R_SORT, false, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
+             tot);
+        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
+             (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
+    } else {
+        ln.k(R_SORT, true, false, k_sort_hist<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1,
+             (const uint8_t*)nullptr, n, cnt, nt);
+        ln.k(R_SORT, false, false, k_sort_scan<128>, dim3(128), dim3(256), 0, c->stream, cnt, nt,
+             (const Counters*)d.ctr, tot);
+        ln.k(R_SORT, false, true, k_sort_scatter<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1,
+             (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
+    }
 }
 
 template <class R>
@@ -406,53 +424,41 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     auto B = [&](int role) { return c->block[role] > 0 ? c->block[role] : bs_def; };
     auto G = [&](int role) { return grid_for(n, B(role)); };
     hipStream_t st = c->stream;
-    ln.run(R_VAC, [&] {
-        hipLaunchKernelGGL((k_vac_count<R>), dim3(nvb), dim3(kVacBlock), 0, st, d);
-        hipLaunchKernelGGL((k_vac_scatter<R>), dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1);
-    });
+    ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1);
     if (!no_init) {
-        ln.run(R_INIT, [&] {
-            if (c->opt.init_partition) {
-                hipLaunchKernelGGL((k_init_count<R>), dim3(nvb), dim3(kVacBlock), 0, st, d);
-                hipLaunchKernelGGL((k_init<R, true>), dim3(nvb), dim3(kVacBlock), 0, st, d);
-            } else {
-                hipLaunchKernelGGL((k_init<R, false>), dim3(nvb), dim3(kVacBlock), 0, st, d);
-            }
-        });
+        if (c->opt.init_partition) {
+            ln.k(R_INIT, true, false, k_init_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+            ln.k(R_INIT, false, true, k_init<R, true>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+        } else {
+            ln.one(R_INIT, k_init<R, false>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+        }
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
-    ln.run(R_PRE, [&] { hipLaunchKernelGGL((k_pre_step<R>), dim3(G(R_PRE)), dim3(B(R_PRE)), lds, st, d); });
+    ln.one(R_PRE, k_pre_step<R>, dim3(G(R_PRE)), dim3(B(R_PRE)), lds, st, d);
     if (d.sorted == 1) launch_sort<R>(c, d, ln);
     // along-step: photons and leptons are independent branches
     const int nw = c->n_streams - 1;
     hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
     if (nw > 0) fork(c, 0, 1);
-    ln.run(R_ALONG_NEUTRAL, s_neutral,
-           [&] {
-               hipLaunchKernelGGL((k_along_straight<R, false>), dim3(G(R_ALONG_NEUTRAL)), dim3(B(R_ALONG_NEUTRAL)), lds,
-                                  s_neutral, d);
-           });
+    ln.one(R_ALONG_NEUTRAL, k_along_straight<R, false>, dim3(G(R_ALONG_NEUTRAL)), dim3(B(R_ALONG_NEUTRAL)), lds,
+           s_neutral, d);
     if (d.has_field)
-        ln.run(R_ALONG_FIELD, [&] {
-            hipLaunchKernelGGL((k_along_field<R>), dim3(G(R_ALONG_FIELD)), dim3(B(R_ALONG_FIELD)), lds, st, d);
-        });
+        ln.one(R_ALONG_FIELD, k_along_field<R>, dim3(G(R_ALONG_FIELD)), dim3(B(R_ALONG_FIELD)), lds, st, d);
     else
-        ln.run(R_ALONG_CHARGED,
-               [&] {
-                   hipLaunchKernelGGL((k_along_straight<R, true>), dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)),
-                                      lds, st, d);
-               });
+        ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
+               st, d);
     if (nw > 0) join(c, 0, 1);
     if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
     // interactions: six independent branches spread over the streams
     if (nw > 0) fork(c, 1, nw);
     auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
-    ln.run(R_COMPTON, on(0), [&] { hipLaunchKernelGGL((k_interact<R, P_COMPTON>), dim3(G(R_COMPTON)), dim3(B(R_COMPTON)), 0, on(0), d); });
-    ln.run(R_PHOTO, on(1), [&] { hipLaunchKernelGGL((k_interact<R, P_PHOTO>), dim3(G(R_PHOTO)), dim3(B(R_PHOTO)), 0, on(1), d); });
-    ln.run(R_PAIR, on(2), [&] { hipLaunchKernelGGL((k_interact<R, P_PAIR>), dim3(G(R_PAIR)), dim3(B(R_PAIR)), 0, on(2), d); });
-    ln.run(R_MOLLER, on(3), [&] { hipLaunchKernelGGL((k_interact<R, P_MOLLER>), dim3(G(R_MOLLER)), dim3(B(R_MOLLER)), 0, on(3), d); });
-    ln.run(R_BHABHA, on(4), [&] { hipLaunchKernelGGL((k_interact<R, P_BHABHA>), dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d); });
-    ln.run(R_BREMS, on(5), [&] { hipLaunchKernelGGL((k_interact<R, P_BREMS>), dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d); });
+    ln.one(R_COMPTON, k_interact<R, P_COMPTON>, dim3(G(R_COMPTON)), dim3(B(R_COMPTON)), 0, on(0), d);
+    ln.one(R_PHOTO, k_interact<R, P_PHOTO>, dim3(G(R_PHOTO)), dim3(B(R_PHOTO)), 0, on(1), d);
+    ln.one(R_PAIR, k_interact<R, P_PAIR>, dim3(G(R_PAIR)), dim3(B(R_PAIR)), 0, on(2), d);
+    ln.one(R_MOLLER, k_interact<R, P_MOLLER>, dim3(G(R_MOLLER)), dim3(B(R_MOLLER)), 0, on(3), d);
+    ln.one(R_BHABHA, k_interact<R, P_BHABHA>, dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d);
+    ln.one(R_BREMS, k_interact<R, P_BREMS>, dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d);
     if (nw > 0) join(c, 1, nw);
     hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
 }
@@ -765,6 +771,7 @@ ems_status ems_load_geometry(ems_ctx* c, const double* zp, const int32_t* sm, ui
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->n_slabs = n_slabs;
     c->half_width = half_width;
+    c->zp_host.assign(zp, zp + n_slabs + 1);
     c->B[0] = B[0]; c->B[1] = B[1]; c->B[2] = B[2];
     c->have_geom = true;
     return drop_graph(c);
@@ -838,6 +845,9 @@ ems_status ems_push_primaries(ems_ctx* c, const ems_primary* p, uint64_t n)
         if (!(q.T >= c->ecut) || !std::isfinite(q.T)) return fail(EMS_ERR_INVALID_ARG, "primary energy below the cut");
         double un = q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
         if (!(std::fabs(un - 1.0) < 1e-6)) return fail(EMS_ERR_INVALID_ARG, "primary direction not unit");
+        if (!(q.r[2] >= c->zp_host[q.slab] && q.r[2] <= c->zp_host[q.slab + 1]) ||
+            !(std::fabs(q.r[0]) <= c->half_width && std::fabs(q.r[1]) <= c->half_width))
+            return fail(EMS_ERR_INVALID_ARG, "primary position outside its slab");
         if (c->row_of.find(q.event) == c->row_of.end() && seen.emplace(q.event, 1).second) ++new_events;
     }
     if (new_events > c->free_rows.size()) return fail(EMS_ERR_CAPACITY, "not enough free event rows");

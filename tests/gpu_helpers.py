@@ -70,3 +70,30 @@ def to_lib_tracks(orc_tracks, rows):
 def layer_sums(edep):
     """Per-layer deposit (Pb + LAr pair of slabs)."""
     return edep.reshape(edep.shape[0], -1, 2).sum(2)
+
+
+def ledger_int_mismatch(a, b, fields=("n_pair", "n_annih", "steps", "n_guard")):
+    """Name of the first integer ledger field that differs between a and b, or None."""
+    for f in fields:
+        if not np.array_equal(a[f], b[f]):
+            return f
+    if not np.array_equal(a["n_sec"], b["n_sec"]):
+        return "n_sec"
+    return None
+
+
+def run_oracle(w, events=None, threads=None):
+    """Oracle per-event deposits, ledgers and total steps for the events of
+    `w` (all, or the given ids in that order)."""
+    import os
+    pb = oracle.problem_for(w)
+    if events is None:
+        tr, rows = oracle.tracks_from_primaries(w.primaries)
+        n = w.n_events
+    else:
+        events = np.asarray(events, dtype=np.uint64)
+        p = w.primaries[np.isin(w.primaries["event"], events)]
+        pos = {int(e): i for i, e in enumerate(events)}
+        tr, rows = oracle.tracks_from_primaries(p, [pos[int(e)] for e in p["event"]])
+        n = len(events)
+    return pb.run_events(tr, rows, n, threads or len(os.sched_getaffinity(0)))

@@ -16,18 +16,12 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_helpers import layer_sums, random_states, session_for, to_lib_tracks
+from tests.gpu_helpers import layer_sums, ledger_int_mismatch, random_states, session_for, to_lib_tracks
 
 pytestmark = pytest.mark.gpu
 
 
-def _ledger_equal_int(a, b, fields=("n_pair", "n_annih", "steps", "n_guard")):
-    for f in fields:
-        if not np.array_equal(a[f], b[f]):
-            return f
-    if not np.array_equal(a["n_sec"], b["n_sec"]):
-        return "n_sec"
-    return None
+_ledger_equal_int = ledger_int_mismatch
 
 
 # ----------------------------------------------------------------------------- tables
