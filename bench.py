@@ -9,7 +9,8 @@ region of each step; the timed region covers the device loop only.
 Default workload: 10^4 electrons of 1 GeV into a 50-layer Pb (2 mm) / liquid
 Ar (5 mm) stack, 40 x 40 cm, uniform 1 T field along x, 0.1 MeV cut, 2^20
 track slots, FP64, slots sorted by next action, iterations replayed from
-captured HIP graphs.
+captured HIP graphs, the last tracks (below 65536 alive, queued or pending)
+stepped in history mode by the drain kernel.
 
 The JSON line carries the dominant kernel's roofline: algorithmic bytes per
 launch (the kernel's work counter times its per-track field traffic) divided
@@ -113,6 +114,9 @@ def parse():
     ap.add_argument("--graph", type=int, default=8, help="iterations per captured HIP graph (0 = plain launches)")
     ap.add_argument("--lds-tables", type=int, default=1)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--drain-threshold", type=int, default=65536,
+                    help="run the last tracks in history mode below this many live+queued+pending (0 = off)")
+    ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=4000, help="oracle sample (events); 0 = skip")
@@ -139,7 +143,7 @@ def make_workload(name, events, slots):
     return w
 
 
-def new_session(w, args, precision, policy, init_partition, graph=None):
+def new_session(w, args, precision, policy, init_partition, graph=None, drain=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
     s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
@@ -148,6 +152,9 @@ def new_session(w, args, precision, policy, init_partition, graph=None):
                        graph_iterations=args.graph if graph is None else graph, lds_tables=args.lds_tables,
                        streams=args.streams, n_primaries=max(len(w.primaries), 1 << 16))
     s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
+    drain = args.drain_threshold if drain is None else drain
+    if drain > 0:
+        s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps)
     return s
 
 
@@ -161,8 +168,8 @@ def time_batch(s, primaries, events):
     return c, time.perf_counter() - t0
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None):
-    s = new_session(w, args, precision, policy, init_partition)
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None):
+    s = new_session(w, args, precision, policy, init_partition, drain=drain)
     events = np.unique(w.primaries["event"])
     tuned = None
     if tune is not None:
@@ -217,6 +224,21 @@ def cpu_baseline(w, n_events):
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "track-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_events} events of the workload ({steps} track-steps, {dt:.2f} s wall)"}
+
+
+def path_roofline(work, steps, rate, precision):
+    """Whole-path HBM roofline: algorithmic bytes per track-step (every step
+    kernel's processed tracks times its per-track field traffic, summed over
+    the batch, divided by the steps) times track-steps/s, against the HBM
+    peak.  A drain trip counts as a pre-step plus a field along-step (its
+    interactions are not counted)."""
+    bpt = BYTES_PER_TRACK[precision]
+    total = sum(work.get(k, 0) * b for k, b in bpt.items())
+    total += work.get("drain", 0) * (bpt["pre_step"] + bpt["along_field"])
+    b_step = total / max(steps, 1)
+    achieved = rate * b_step / 1e9
+    return {"bound": "hbm", "bytes_per_step": b_step, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS}
 
 
 def layer_error(w, edep):
@@ -324,6 +346,7 @@ def main():
                    "n_slots": w.n_slots, "sort_policy": args.policy, "init_partition": args.init_partition,
                    "max_substeps": args.max_substeps, "graph_iterations": args.graph,
                    "lds_tables": args.lds_tables, "streams": args.streams,
+                   "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
@@ -338,7 +361,8 @@ def main():
         per_launch = tracks * bpt / launches
         achieved = per_launch / avg_s / 1e9
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
-               "init_partition": args.init_partition, "max_substeps": args.max_substeps}
+               "init_partition": args.init_partition, "max_substeps": args.max_substeps,
+               "drain_threshold": args.drain_threshold}
         t = committed_traffic(prof_kernel, key)
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -350,14 +374,16 @@ def main():
                            "timing": "HIP start/stop events stamped by the kernel's own dispatch packet "
                                      "(hipExtLaunchKernel) on every launch of the kernel, in one extra pass over "
                                      "the same batch (graph replay off for that pass)"}
+    out["path_roofline"] = path_roofline(r["work"], r["steps"], value, precision)
     if args.compare:
         var = {}
-        for pol, part in [("none", 0), ("none", 1), ("partition", 0), ("partition", 1), ("radix", 0),
-                          ("queue", 0)]:
-            if pol == args.policy and part == args.init_partition:
+        for pol, part, dr in [("none", 0, None), ("none", 1, None), ("partition", 0, None), ("partition", 1, None),
+                              ("radix", 0, None), ("queue", 0, None), ("none", 0, 0), ("partition", 0, 0)]:
+            if pol == args.policy and part == args.init_partition and dr is None:
                 continue
-            rv = run_variant(w, args, precision, pol, part, None)
-            var[f"{pol}+part{part}"] = rv["steps"] / rv["seconds"]
+            rv = run_variant(w, args, precision, pol, part, None, drain=dr)
+            tag = f"{pol}+part{part}" + ("+nodrain" if dr == 0 else "")
+            var[tag] = rv["steps"] / rv["seconds"]
         out["variants"] = var
     if args.layer_error:
         out["layer_error_vs_fp64_oracle"] = layer_error(w, r["edep"])

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 1u
+#define EMS_ABI_VERSION 2u
 
 typedef enum {
     EMS_OK = 0,
@@ -262,13 +262,24 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * block[i] is the block size of kernel role i (role order as returned by
  * ems_profile_read: vacancies, init, pre_step, sort, along_neutral,
  * along_charged, along_field, compton, photoelectric, pair, moller, bhabha,
- * bremsstrahlung); 0 keeps ems_options.block_size.  Below tail_threshold
- * live tracks an iteration skips the reordering and runs masked (the device
- * decides per iteration).  Setting it re-captures graphs on the next run. */
+ * bremsstrahlung, drain); 0 keeps ems_options.block_size.  Below
+ * tail_threshold live tracks an iteration skips the reordering and runs
+ * masked (the device decides per iteration).
+ *
+ * Drain (ems_run only; 0 = off): once the latest counter snapshot shows fewer
+ * than drain_threshold tracks alive, queued or pending, each further
+ * iteration fills the vacant slots and then runs one history-mode kernel: a
+ * thread per occupied slot steps its track and then that track's secondaries
+ * (a private stack of 8; the rest go back to the initializer buffer) for up
+ * to drain_steps steps (> 0).  It removes the per-iteration launch latency of
+ * the last, nearly empty iterations; the physics is the same per-track code.
+ * Setting the tuning re-captures graphs on the next run. */
 typedef struct {
     int32_t sort_policy;
     uint32_t tail_threshold;
     int32_t block[16];
+    uint32_t drain_threshold;
+    uint32_t drain_steps;
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

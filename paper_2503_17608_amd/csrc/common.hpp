@@ -112,12 +112,16 @@ struct Counters {
 // work counter indices
 enum : int {
     W_INIT = 1, W_PRE = 2, W_SORT = 3, W_NEUTRAL = 4, W_CHARGED = 5, W_FIELD = 6, W_PROC0 = 7,
-    W_PAUSED = 13, W_SUBSTEPS = 14
+    W_PAUSED = 13, W_SUBSTEPS = 14, W_DRAIN = 15
 };
 // partial-counter slots: [0, 16) work per kernel, [16, 32) completed steps of
 // the tracks each kernel retired (one slot per kernel, since kernels of an
 // iteration may run concurrently and every slot has a single writer)
 constexpr int kNumW = 32;
+constexpr uint32_t kDrainThreadsMax = 1u << 16;   // drain kernel threads (each with a private stack)
+constexpr int kDrainDepth = 8;                     // private secondary stack depth per drain thread
+constexpr uint32_t kDrainStepsDefault = 4096;      // steps per drain thread and launch
+constexpr int kDrainSubsteps = 1024;               // field substeps per drain trip before a pause
 constexpr int kStepsSlot = 16;
 
 // Host-visible snapshot copied to pinned memory after each batch

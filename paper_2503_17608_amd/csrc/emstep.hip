@@ -50,7 +50,9 @@ struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
+    uint64_t drain_stack;
     uint32_t part_stride;
+    uint32_t drain_threads;   // capacity of the drain kernel (threads with a private stack)
     uint64_t total;
     uint32_t n_tiles;
 };
@@ -114,17 +116,19 @@ Layout make_layout(const ems_options& o)
     L.part_stride = (uint32_t)std::max<uint64_t>(2048, nvb);
     L.part = take(8ull * kNumW * L.part_stride);
     L.incr = take(8ull * o.max_materials * 2 * (kNodes - 1));
+    L.drain_threads = (uint32_t)std::min<uint64_t>(kDrainThreadsMax, align_up(n, 256));
+    L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
     L.total = off;
     return L;
 }
 
 enum Role {
     R_VAC = 0, R_INIT, R_PRE, R_SORT, R_ALONG_NEUTRAL, R_ALONG_CHARGED, R_ALONG_FIELD,
-    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_NUM
+    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_DRAIN, R_NUM
 };
 const char* kRoleNames[R_NUM] = {"vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged",
                                  "along_field", "compton", "photoelectric", "pair", "moller", "bhabha",
-                                 "bremsstrahlung"};
+                                 "bremsstrahlung", "drain"};
 
 }  // namespace
 
@@ -171,6 +175,8 @@ struct ems_ctx {
     // tuning (switchable at run time)
     int policy = 0;
     uint32_t tail_threshold = 0;
+    uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
+    uint32_t drain_steps = kDrainStepsDefault;
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -425,7 +431,8 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     auto G = [&](int role) { return grid_for(n, B(role)); };
     hipStream_t st = c->stream;
     ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
-    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1);
+    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1,
+         (uint32_t*)nullptr);
     if (!no_init) {
         if (c->opt.init_partition) {
             ln.k(R_INIT, true, false, k_init_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
@@ -467,6 +474,33 @@ void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
 {
     if (c->opt.precision == EMS_MIXED) launch_iteration<float>(c, no_init, prof);
     else launch_iteration<double>(c, no_init, prof);
+}
+
+// One drain iteration: vacancies (and the list of occupied slots), fill from
+// the initializer buffer and the pending primaries, then one history-mode
+// launch over the occupied slots.
+template <class R>
+void launch_drain(ems_ctx* c, uint32_t threads)
+{
+    Dev<R> d = make_dev<R>(c);
+    Launcher ln{c, c->prof_mask != 0};
+    const uint32_t n = d.n_slots;
+    const uint32_t nvb = (n + kVacBlock - 1) / kVacBlock;
+    hipStream_t st = c->stream;
+    uint32_t* live_list = (uint32_t*)(c->ws + c->L.perm);
+    ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, 1, live_list);
+    ln.one(R_INIT, k_init<R, false>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+    const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
+    ln.one(R_DRAIN, k_drain<R>, dim3((threads + 255) / 256), dim3(256), lds, st, d, (const uint32_t*)live_list,
+           (Initializer*)(c->ws + c->L.drain_stack), threads, kDrainDepth, c->drain_steps);
+    hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
+}
+
+void launch_drain_any(ems_ctx* c, uint32_t threads)
+{
+    if (c->opt.precision == EMS_MIXED) launch_drain<float>(c, threads);
+    else launch_drain<double>(c, threads);
 }
 
 ems_status check_ready(ems_ctx* c)
@@ -939,13 +973,25 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
     uint64_t seq = 0;
     // batches in flight: after launching batch g we wait for the snapshot of batch g-1
     Snapshot done{};
+    bool have_done = false;
     bool finished = false;
     int in_flight = 0;
     while (!finished) {
         if (launched < max_iterations) {
-            s = launch_batch(c, batch, false);
-            if (s != EMS_OK) return s;
-            launched += batch;
+            // below the drain threshold (as of the latest snapshot) the rest
+            // of the work runs in history mode, one drain iteration at a time
+            uint64_t left = have_done ? (uint64_t)done.n_alive + done.queue_size + (done.prim_end - done.prim_next)
+                                      : UINT64_MAX;
+            if (c->drain_threshold > 0 && left < c->drain_threshold) {
+                uint64_t want = align_up(std::max<uint64_t>(2 * left, 256), 256);
+                launch_drain_any(c, (uint32_t)std::min<uint64_t>(want, c->L.drain_threads));
+                HIP_TRY(hipGetLastError());
+                launched += 1;
+            } else {
+                s = launch_batch(c, batch, false);
+                if (s != EMS_OK) return s;
+                launched += batch;
+            }
             int slot = (int)(seq % c->snap_slots);
             hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1024), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
                                (const unsigned long long*)(c->ws + c->L.part), c->L.part_stride, &c->snap[slot]);
@@ -957,6 +1003,7 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
             int slot = (int)((seq - in_flight) % c->snap_slots);
             HIP_TRY(hipEventSynchronize(c->snap_ev[slot]));
             done = c->snap[slot];
+            have_done = true;
             --in_flight;
             if (done.overflow) {
                 HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1205,8 +1252,11 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
         if (b != 0 && (b < 64 || b > 512 || (b % 64) != 0))
             return fail(EMS_ERR_INVALID_ARG, "block sizes must be 0 or a multiple of 64 in [64, 512]");
     }
+    if (t->drain_threshold > 0 && t->drain_steps == 0) return fail(EMS_ERR_INVALID_ARG, "drain_steps must be > 0");
     c->policy = t->sort_policy;
     c->tail_threshold = t->tail_threshold;
+    c->drain_threshold = t->drain_threshold;
+    c->drain_steps = t->drain_steps;
     for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
     return drop_graph(c);
 }
@@ -1216,6 +1266,8 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     if (!c || !t) return fail(EMS_ERR_INVALID_ARG, "null");
     t->sort_policy = c->policy;
     t->tail_threshold = c->tail_threshold;
+    t->drain_threshold = c->drain_threshold;
+    t->drain_steps = c->drain_steps;
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }

@@ -181,11 +181,15 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_count(Dev<R> d)
 // Writes vacant slot indices in slot order; the last block plans the fill:
 // initializers are taken from the top of the secondary buffer first (LIFO),
 // then from the pending primaries.
+//
+// With live_out set, the occupied slots are also listed there in slot order
+// (n_slots - n_vac of them), for the drain kernel.
 template <class R>
-__global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fill)
+__global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fill, uint32_t* live_out)
 {
     __shared__ uint32_t red[kVacBlock / 64];
     __shared__ uint32_t wcnt[kVacBlock / 64];
+    __shared__ uint32_t wlive[kVacBlock / 64];
     uint32_t prefix = block_prefix(d.vac_cnt, blockIdx.x, red);
     uint32_t s = blockIdx.x * kVacBlock + threadIdx.x;
     bool v = (s < d.n_slots) && d.type[s] == kDead;
@@ -196,6 +200,15 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
     uint32_t off = prefix;
     for (int i = 0; i < w; ++i) off += wcnt[i];
     if (v) d.vac[off + rank_below(m)] = s;
+    if (live_out) {                                   // block-uniform
+        bool l = (s < d.n_slots) && !v;
+        uint64_t ml = __ballot(l);
+        if (lane_id() == 0) wlive[w] = (uint32_t)__popcll(ml);
+        __syncthreads();
+        uint32_t lo = blockIdx.x * kVacBlock - prefix;   // occupied slots in earlier (full) blocks
+        for (int i = 0; i < w; ++i) lo += wlive[i];
+        if (l) live_out[lo + rank_below(ml)] = s;
+    }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         uint32_t blk = 0;
         for (int i = 0; i < kVacBlock / 64; ++i) blk += wcnt[i];
@@ -233,6 +246,32 @@ __device__ __forceinline__ const Initializer* taken(const Dev<R>& d, uint32_t i)
     const Counters* c = d.ctr;
     if (i < c->n_take_q) return &d.queue[c->q_base + c->n_take_q - 1 - i];
     return &d.prims[(c->p_base + (i - c->n_take_q)) % d.prim_cap];
+}
+
+// A new track in `slot` from an initializer record.
+template <class R>
+__device__ __forceinline__ void init_slot(const Dev<R>& d, uint32_t slot, const Initializer& rec)
+{
+    d.type[slot] = rec.type;
+    d.action[slot] = A_IDLE;
+    d.flags[slot] = 0;
+    d.nsearch[slot] = 0;
+    d.slab[slot] = rec.slab;
+    d.row[slot] = rec.row;
+    d.step[slot] = 0;
+    d.key[slot] = rec.key;
+    d.T[slot] = (R)rec.T;
+    d.nl[slot] = R(-1);
+    d.xs[slot] = R(0);
+    d.sphys[slot] = 0.0;
+    d.sdone[slot] = 0.0;
+    d.htry[slot] = 0.0;
+    d.x[slot] = rec.r[0];
+    d.y[slot] = rec.r[1];
+    d.z[slot] = rec.r[2];
+    d.ux[slot] = (R)rec.u[0];
+    d.uy[slot] = (R)rec.u[1];
+    d.uz[slot] = (R)rec.u[2];
 }
 
 // per-block count of charged initializers among the taken ones (partitioned fill)
@@ -280,26 +319,7 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
     }
     flush_count(d, W_INIT, act ? 1ull : 0ull);
     if (!act) return;
-    d.type[slot] = rec.type;
-    d.action[slot] = A_IDLE;
-    d.flags[slot] = 0;
-    d.nsearch[slot] = 0;
-    d.slab[slot] = rec.slab;
-    d.row[slot] = rec.row;
-    d.step[slot] = 0;
-    d.key[slot] = rec.key;
-    d.T[slot] = (R)rec.T;
-    d.nl[slot] = R(-1);
-    d.xs[slot] = R(0);
-    d.sphys[slot] = 0.0;
-    d.sdone[slot] = 0.0;
-    d.htry[slot] = 0.0;
-    d.x[slot] = rec.r[0];
-    d.y[slot] = rec.r[1];
-    d.z[slot] = rec.r[2];
-    d.ux[slot] = (R)rec.u[0];
-    d.uy[slot] = (R)rec.u[1];
-    d.uz[slot] = (R)rec.u[2];
+    init_slot(d, slot, rec);
 }
 
 // ---- work distribution ----------------------------------------------------------
@@ -401,6 +421,41 @@ __device__ __forceinline__ void retire(const Dev<R>& d, uint32_t s, uint32_t row
     atomicAdd(&d.ledger[row].steps, (unsigned long long)steps);
 }
 
+// Pre-step of one live, non-paused track (fields loaded by the caller):
+// interaction length, total cross section, physics step limit and the
+// along-step action, which it returns.
+template <class R>
+__device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint8_t typ, R T, R nl,
+                                             uint16_t slab, uint32_t row, uint32_t step, uint64_t key)
+{
+    int mat = d.smat[slab];
+    uint8_t nf = 0;
+    if (nl < R(0)) {
+        StepRng<R> rng(d.seed, d.row_event[row], key, step, 0);
+        nl = -m_log(rng.next());
+        d.nl[s] = nl;
+        nf |= F_DREW;
+    }
+    Loc<R> l = locate(tb, T);
+    R sig = total_xs(tb, mat, typ, T, l, R(d.ecut));
+    R s_int = sig > R(0) ? nl / sig : R(INFINITY);
+    R s_phys = s_int;
+    if (typ != kGamma) {
+        R Rg = interp(range_tab(tb, mat, typ), l);
+        R s_loss = Rg <= R(kRFinal) ? Rg : m_max(R(kRFinal), R(kRhoRange) * Rg);
+        if (s_loss < s_int) {
+            s_phys = s_loss;
+            nf |= F_LOSS;
+        }
+    }
+    d.xs[s] = sig;
+    d.sphys[s] = (double)s_phys;
+    d.flags[s] = nf;
+    uint8_t na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
+    d.action[s] = na;
+    return na;
+}
+
 // ---- pre-step: interaction length, physics step limit, along-step action -----------
 template <class R>
 __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
@@ -436,34 +491,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
         bool paused = act && (fl & F_PAUSED) != 0;
         act = act && !paused;
         work += act ? 1u : 0u;
-        uint8_t na = A_FIELD;
-        if (act) {
-            int mat = d.smat[slab];
-            uint8_t nf = 0;
-            if (nl < R(0)) {
-                StepRng<R> rng(d.seed, d.row_event[row], key, step, 0);
-                nl = -m_log(rng.next());
-                d.nl[s] = nl;
-                nf |= F_DREW;
-            }
-            Loc<R> l = locate(tb, T);
-            R sig = total_xs(tb, mat, typ, T, l, R(d.ecut));
-            R s_int = sig > R(0) ? nl / sig : R(INFINITY);
-            R s_phys = s_int;
-            if (typ != kGamma) {
-                R Rg = interp(range_tab(tb, mat, typ), l);
-                R s_loss = Rg <= R(kRFinal) ? Rg : m_max(R(kRFinal), R(kRhoRange) * Rg);
-                if (s_loss < s_int) {
-                    s_phys = s_loss;
-                    nf |= F_LOSS;
-                }
-            }
-            d.xs[s] = sig;
-            d.sphys[s] = (double)s_phys;
-            d.flags[s] = nf;
-            na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
-            d.action[s] = na;
-        }
+        if (act) pre_track(d, tb, s, typ, T, nl, slab, row, step, key);
     }
     flush_count(d, W_PRE, work);
 }
@@ -590,6 +618,56 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
     }
 }
 
+// Along-step of one straight-line track (photon, or charged without field).
+// Fills the secondaries, the point they start from, the tally row and the
+// slab of the step; `next` is the next action; `retired` the steps of a track
+// that finished (0 while it lives).
+template <class R, bool CHARGED>
+__device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, SecBuf<R>& sb,
+                                                     double r[3], uint32_t& row, uint16_t& slab0, uint8_t& next,
+                                                     uint32_t& retired)
+{
+    int typ = d.type[s];
+    row = d.row[s];
+    uint16_t slab = d.slab[s];
+    slab0 = slab;
+    int mat = d.smat[slab];
+    R T = d.T[s];
+    R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
+    double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
+    r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+    double s_phys = d.sphys[s];
+    uint8_t fl = d.flags[s];
+    R sig = d.xs[s];
+    R nl = d.nl[s];
+    int face;
+    double s_geo = straight_distance(r, ud, d.zp[slab], d.zp[slab + 1], d.W, &face);
+    double st;
+    if (s_geo <= s_phys) st = s_geo;
+    else { st = s_phys; face = F_NONE; }
+    r[0] = r[0] + st * ud[0];
+    r[1] = r[1] + st * ud[1];
+    r[2] = r[2] + st * ud[2];
+    if (face != F_NONE) r[face_axis(face)] = face_plane(d.zp, slab, d.W, face);
+    StepTally tl = {0.0, 0, 0, 0};
+    PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+    bool alive = true;
+    uint8_t na = A_IDLE;
+    finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+    record_tally(d, row, slab0, tl);
+    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+    if (alive) {
+        d.T[s] = T;
+        d.nl[s] = nl;
+        d.slab[s] = slab;
+        d.action[s] = na;
+        next = na;
+    } else {
+        retired = d.step[s];
+        retire(d, s, row, retired);
+    }
+}
+
 // ---- along-step, straight line (photons, or charged without field) ------------------
 template <class R, bool CHARGED>
 __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
@@ -607,47 +685,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     uint16_t slab0 = 0;
     uint8_t next = A_NONE;
     uint32_t retired = 0;
-    if (act) {
-        int typ = d.type[s];
-        row = d.row[s];
-        uint16_t slab = d.slab[s];
-        slab0 = slab;
-        int mat = d.smat[slab];
-        R T = d.T[s];
-        R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
-        double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
-        r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
-        double s_phys = d.sphys[s];
-        uint8_t fl = d.flags[s];
-        R sig = d.xs[s];
-        R nl = d.nl[s];
-        int face;
-        double s_geo = straight_distance(r, ud, d.zp[slab], d.zp[slab + 1], d.W, &face);
-        double st;
-        if (s_geo <= s_phys) st = s_geo;
-        else { st = s_phys; face = F_NONE; }
-        r[0] = r[0] + st * ud[0];
-        r[1] = r[1] + st * ud[1];
-        r[2] = r[2] + st * ud[2];
-        if (face != F_NONE) r[face_axis(face)] = face_plane(d.zp, slab, d.W, face);
-        StepTally tl = {0.0, 0, 0, 0};
-        PhysParams pp = {d.seed, d.row_event[row], d.ecut};
-        bool alive = true;
-        uint8_t na = A_IDLE;
-        finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
-        record_tally(d, row, slab0, tl);
-        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-        if (alive) {
-            d.T[s] = T;
-            d.nl[s] = nl;
-            d.slab[s] = slab;
-            d.action[s] = na;
-            next = na;
-        } else {
-            retired = d.step[s];
-            retire(d, s, row, retired);
-        }
-    }
+    if (act) along_straight_track<R, CHARGED>(d, tb, s, sb, r, row, slab0, next, retired);
     append_secondaries(d, sb, row, slab0, r);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
@@ -713,6 +751,136 @@ __device__ __forceinline__ void normalize_d(double v[3])
     v[0] /= n; v[1] /= n; v[2] /= n;
 }
 
+// Along-step of one charged track in the uniform field, with at most
+// `max_sub` RK4 evaluations (0: no cap) before the step pauses.  Outputs as
+// for the straight-line step, plus the RK4 evaluations made (`att`) and
+// whether the step paused (`paused_n`).
+template <class R>
+__device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int max_sub,
+                                                  SecBuf<R>& sb, double r[3], uint32_t& row, uint16_t& slab0,
+                                                  uint8_t& next, uint32_t& retired, uint32_t& att, uint32_t& paused_n)
+{
+    int typ = d.type[s];
+    row = d.row[s];
+    uint16_t slab = d.slab[s];
+    slab0 = slab;
+    int mat = d.smat[slab];
+    R T = d.T[s];
+    double u[3] = {(double)d.ux[s], (double)d.uy[s], (double)d.uz[s]};
+    r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+    double s_phys = d.sphys[s];
+    double s_done = d.sdone[s];
+    double h_try = d.htry[s];
+    int n_search = d.nsearch[s];
+    uint8_t fl = d.flags[s];
+    double Td = (double)T;
+    double q = typ == kPositron ? 1.0 : -1.0;
+    double p = sqrt(Td * (Td + 2.0 * kMe));
+    double kf = q * kCk / p;
+    double Bm = sqrt(d.B[0] * d.B[0] + d.B[1] * d.B[1] + d.B[2] * d.B[2]);
+    double h_chord = sqrt(8.0 * kDChord / (kCk * Bm / p));
+    double zlo = d.zp[slab], zhi = d.zp[slab + 1];
+    int face = F_NONE;
+    bool paused = false;
+    for (;;) {
+        if (max_sub > 0 && att >= (uint32_t)max_sub) { paused = true; break; }
+        double rem = s_phys - s_done;
+        double h = h_try > 0.0 ? h_try : fmin(rem, h_chord);
+        bool last = (h_try == 0.0 && h == rem);
+        double r1[3], u1[3];
+        rk4(r, u, h, kf, d.B, r1, u1);
+        ++att;
+        // first face crossed by the chord r -> r1
+        int fc = F_NONE;
+        double f = INFINITY;
+        for (int fa = F_ZLO; fa <= F_YHI; ++fa) {
+            int ax = face_axis(fa);
+            double pl = fa == F_ZLO ? zlo : (fa == F_ZHI ? zhi : face_plane(d.zp, slab, d.W, fa));
+            if (!beyond(fa, r1[ax], pl)) continue;
+            double fr = (pl - r[ax]) / (r1[ax] - r[ax]);
+            fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+            if (fr < f) { f = fr; fc = fa; }
+        }
+        if (fc == F_NONE) {
+            int nf = F_NONE;
+            if (h_try > 0.0) {
+                double bd = kDInt;
+                for (int fa = F_ZLO; fa <= F_YHI; ++fa) {
+                    double pl = fa == F_ZLO ? zlo : (fa == F_ZHI ? zhi : face_plane(d.zp, slab, d.W, fa));
+                    double dd = fabs(r1[face_axis(fa)] - pl);
+                    if (dd <= bd && (nf == F_NONE || dd < bd)) { bd = dd; nf = fa; }
+                }
+            }
+            r[0] = r1[0]; r[1] = r1[1]; r[2] = r1[2];
+            normalize_d(u1);
+            store_dir<R>(u1);
+            u[0] = u1[0]; u[1] = u1[1]; u[2] = u1[2];
+            if (nf != F_NONE) {
+                r[face_axis(nf)] = face_plane(d.zp, slab, d.W, nf);
+                s_done += h;
+                face = nf;
+                break;
+            }
+            if (last) { s_done = s_phys; break; }
+            s_done += h;
+            h_try = 0.0;
+            n_search = 0;
+            continue;
+        }
+        if (f == 0.0 && points_out(u, fc)) {
+            r[face_axis(fc)] = face_plane(d.zp, slab, d.W, fc);
+            face = fc;
+            break;
+        }
+        double ch[3] = {r1[0] - r[0], r1[1] - r[1], r1[2] - r[2]};
+        double clen = sqrt(ch[0] * ch[0] + ch[1] * ch[1] + ch[2] * ch[2]);
+        if ((1.0 - f) * clen <= kDInt || n_search >= kMaxSearch) {
+            for (int c = 0; c < 3; ++c) r[c] = r[c] + f * ch[c];
+            r[face_axis(fc)] = face_plane(d.zp, slab, d.W, fc);
+            normalize_d(u1);
+            store_dir<R>(u1);
+            u[0] = u1[0]; u[1] = u1[1]; u[2] = u1[2];
+            s_done += f * h;
+            face = fc;
+            break;
+        }
+        h_try = f > 0.0 ? f * h : 0.5 * h;
+        n_search += 1;
+    }
+    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+    d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
+    paused_n = paused ? 1u : 0u;
+    if (paused) {
+        d.sdone[s] = s_done;
+        d.htry[s] = h_try;
+        d.nsearch[s] = (uint8_t)n_search;
+        d.flags[s] = fl | F_PAUSED;
+    } else {
+        d.sdone[s] = 0.0;
+        d.htry[s] = 0.0;
+        d.nsearch[s] = 0;
+        d.flags[s] = fl & (uint8_t)~F_PAUSED;
+        R sig = d.xs[s];
+        R nl = d.nl[s];
+        StepTally tl = {0.0, 0, 0, 0};
+        PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+        bool alive = true;
+        uint8_t na = A_IDLE;
+        finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+        record_tally(d, row, slab0, tl);
+        if (alive) {
+            d.T[s] = T;
+            d.nl[s] = nl;
+            d.slab[s] = slab;
+            d.action[s] = na;
+            next = na;
+        } else {
+            retired = d.step[s];
+            retire(d, s, row, retired);
+        }
+    }
+}
+
 // Uniform-field propagation with RK4 substeps of at most sqrt(8 d_chord /
 // curvature), boundary search by chord fraction, and a cap of max_substeps
 // RK4 evaluations per iteration: at the cap the step pauses with its
@@ -734,127 +902,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     uint16_t slab0 = 0;
     uint8_t next = A_NONE;
     uint32_t retired = 0, att = 0, paused_n = 0;
-    if (act) {
-        int typ = d.type[s];
-        row = d.row[s];
-        uint16_t slab = d.slab[s];
-        slab0 = slab;
-        int mat = d.smat[slab];
-        R T = d.T[s];
-        double u[3] = {(double)d.ux[s], (double)d.uy[s], (double)d.uz[s]};
-        r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
-        double s_phys = d.sphys[s];
-        double s_done = d.sdone[s];
-        double h_try = d.htry[s];
-        int n_search = d.nsearch[s];
-        uint8_t fl = d.flags[s];
-        double Td = (double)T;
-        double q = typ == kPositron ? 1.0 : -1.0;
-        double p = sqrt(Td * (Td + 2.0 * kMe));
-        double kf = q * kCk / p;
-        double Bm = sqrt(d.B[0] * d.B[0] + d.B[1] * d.B[1] + d.B[2] * d.B[2]);
-        double h_chord = sqrt(8.0 * kDChord / (kCk * Bm / p));
-        double zlo = d.zp[slab], zhi = d.zp[slab + 1];
-        int face = F_NONE;
-        bool paused = false;
-        for (;;) {
-            if (d.max_substeps > 0 && att >= (uint32_t)d.max_substeps) { paused = true; break; }
-            double rem = s_phys - s_done;
-            double h = h_try > 0.0 ? h_try : fmin(rem, h_chord);
-            bool last = (h_try == 0.0 && h == rem);
-            double r1[3], u1[3];
-            rk4(r, u, h, kf, d.B, r1, u1);
-            ++att;
-            // first face crossed by the chord r -> r1
-            int fc = F_NONE;
-            double f = INFINITY;
-            for (int fa = F_ZLO; fa <= F_YHI; ++fa) {
-                int ax = face_axis(fa);
-                double pl = fa == F_ZLO ? zlo : (fa == F_ZHI ? zhi : face_plane(d.zp, slab, d.W, fa));
-                if (!beyond(fa, r1[ax], pl)) continue;
-                double fr = (pl - r[ax]) / (r1[ax] - r[ax]);
-                fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
-                if (fr < f) { f = fr; fc = fa; }
-            }
-            if (fc == F_NONE) {
-                int nf = F_NONE;
-                if (h_try > 0.0) {
-                    double bd = kDInt;
-                    for (int fa = F_ZLO; fa <= F_YHI; ++fa) {
-                        double pl = fa == F_ZLO ? zlo : (fa == F_ZHI ? zhi : face_plane(d.zp, slab, d.W, fa));
-                        double dd = fabs(r1[face_axis(fa)] - pl);
-                        if (dd <= bd && (nf == F_NONE || dd < bd)) { bd = dd; nf = fa; }
-                    }
-                }
-                r[0] = r1[0]; r[1] = r1[1]; r[2] = r1[2];
-                normalize_d(u1);
-                store_dir<R>(u1);
-                u[0] = u1[0]; u[1] = u1[1]; u[2] = u1[2];
-                if (nf != F_NONE) {
-                    r[face_axis(nf)] = face_plane(d.zp, slab, d.W, nf);
-                    s_done += h;
-                    face = nf;
-                    break;
-                }
-                if (last) { s_done = s_phys; break; }
-                s_done += h;
-                h_try = 0.0;
-                n_search = 0;
-                continue;
-            }
-            if (f == 0.0 && points_out(u, fc)) {
-                r[face_axis(fc)] = face_plane(d.zp, slab, d.W, fc);
-                face = fc;
-                break;
-            }
-            double ch[3] = {r1[0] - r[0], r1[1] - r[1], r1[2] - r[2]};
-            double clen = sqrt(ch[0] * ch[0] + ch[1] * ch[1] + ch[2] * ch[2]);
-            if ((1.0 - f) * clen <= kDInt || n_search >= kMaxSearch) {
-                for (int c = 0; c < 3; ++c) r[c] = r[c] + f * ch[c];
-                r[face_axis(fc)] = face_plane(d.zp, slab, d.W, fc);
-                normalize_d(u1);
-                store_dir<R>(u1);
-                u[0] = u1[0]; u[1] = u1[1]; u[2] = u1[2];
-                s_done += f * h;
-                face = fc;
-                break;
-            }
-            h_try = f > 0.0 ? f * h : 0.5 * h;
-            n_search += 1;
-        }
-        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-        d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
-        paused_n = paused ? 1u : 0u;
-        if (paused) {
-            d.sdone[s] = s_done;
-            d.htry[s] = h_try;
-            d.nsearch[s] = (uint8_t)n_search;
-            d.flags[s] = fl | F_PAUSED;
-        } else {
-            d.sdone[s] = 0.0;
-            d.htry[s] = 0.0;
-            d.nsearch[s] = 0;
-            d.flags[s] = fl & (uint8_t)~F_PAUSED;
-            R sig = d.xs[s];
-            R nl = d.nl[s];
-            StepTally tl = {0.0, 0, 0, 0};
-            PhysParams pp = {d.seed, d.row_event[row], d.ecut};
-            bool alive = true;
-            uint8_t na = A_IDLE;
-            finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
-            record_tally(d, row, slab0, tl);
-            if (alive) {
-                d.T[s] = T;
-                d.nl[s] = nl;
-                d.slab[s] = slab;
-                d.action[s] = na;
-                next = na;
-            } else {
-                retired = d.step[s];
-                retire(d, s, row, retired);
-            }
-        }
-    }
+    if (act) along_field_track<R>(d, tb, s, d.max_substeps, sb, r, row, slab0, next, retired, att, paused_n);
     append_secondaries(d, sb, row, slab0, r);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
@@ -866,6 +914,54 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
     flush_count(d, W_SUBSTEPS, sub_acc);
     flush_count(d, W_PAUSED, pause_acc);
+}
+
+// Discrete interaction PROC of one track at the end of its along-step.
+// Outputs as for the along-step (the secondaries start at the track's point).
+template <class R, int PROC>
+__device__ __forceinline__ void interact_track(const Dev<R>& d, uint32_t s, SecBuf<R>& sb, double r[3], uint32_t& row,
+                                               uint16_t& slab, uint32_t& retired)
+{
+    row = d.row[s];
+    slab = d.slab[s];
+    r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+    Prim<R> p;
+    p.T = d.T[s];
+    p.u[0] = d.ux[s]; p.u[1] = d.uy[s]; p.u[2] = d.uz[s];
+    p.key = d.key[s];
+    p.step = d.step[s];
+    p.type = d.type[s];
+    p.alive = true;
+    uint8_t fl = d.flags[s];
+    PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+    StepRng<R> rng(d.seed, pp.event, p.key, p.step, (fl & F_DREW) ? 2 : 1);
+    StepTally tl = {0.0, 0, 0, 0};
+    switch (PROC) {
+    case P_COMPTON: sample_compton<R>(pp, p, rng, sb, tl); break;
+    case P_PHOTO:   sample_photo<R>(pp, p, sb, tl); break;
+    case P_PAIR:    sample_pair<R>(pp, p, rng, sb, tl); break;
+    case P_MOLLER:  sample_moller<R>(pp, p, rng, sb, tl); break;
+    case P_BHABHA:  sample_bhabha<R>(pp, p, rng, sb, tl); break;
+    default:        sample_brems<R>(pp, p, rng, sb, tl); break;
+    }
+    uint32_t steps = p.step + 1;
+    d.step[s] = steps;
+    if (p.alive && steps > kMaxSteps) {
+        atomicAdd(&d.ledger[row].n_guard, 1ull);
+        p.step = steps;
+        if (p.type != kGamma) stop_lepton<R>(pp, p, sb, tl);
+        else { tl.edep += (double)p.T; p.alive = false; }
+    }
+    record_tally(d, row, slab, tl);
+    if (p.alive) {
+        d.T[s] = p.T;
+        d.ux[s] = p.u[0]; d.uy[s] = p.u[1]; d.uz[s] = p.u[2];
+        d.nl[s] = R(-1);
+        d.action[s] = A_IDLE;
+    } else {
+        retired = steps;
+        retire(d, s, row, steps);
+    }
 }
 
 // ---- discrete interactions: one kernel per process ---------------------------------
@@ -881,54 +977,142 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     uint32_t row = 0;
     uint16_t slab = 0;
     uint32_t retired = 0;
-    if (act) {
-        row = d.row[s];
-        slab = d.slab[s];
-        r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
-        Prim<R> p;
-        p.T = d.T[s];
-        p.u[0] = d.ux[s]; p.u[1] = d.uy[s]; p.u[2] = d.uz[s];
-        p.key = d.key[s];
-        p.step = d.step[s];
-        p.type = d.type[s];
-        p.alive = true;
-        uint8_t fl = d.flags[s];
-        PhysParams pp = {d.seed, d.row_event[row], d.ecut};
-        StepRng<R> rng(d.seed, pp.event, p.key, p.step, (fl & F_DREW) ? 2 : 1);
-        StepTally tl = {0.0, 0, 0, 0};
-        switch (PROC) {
-        case P_COMPTON: sample_compton<R>(pp, p, rng, sb, tl); break;
-        case P_PHOTO:   sample_photo<R>(pp, p, sb, tl); break;
-        case P_PAIR:    sample_pair<R>(pp, p, rng, sb, tl); break;
-        case P_MOLLER:  sample_moller<R>(pp, p, rng, sb, tl); break;
-        case P_BHABHA:  sample_bhabha<R>(pp, p, rng, sb, tl); break;
-        default:        sample_brems<R>(pp, p, rng, sb, tl); break;
-        }
-        uint32_t steps = p.step + 1;
-        d.step[s] = steps;
-        if (p.alive && steps > kMaxSteps) {
-            atomicAdd(&d.ledger[row].n_guard, 1ull);
-            p.step = steps;
-            if (p.type != kGamma) stop_lepton<R>(pp, p, sb, tl);
-            else { tl.edep += (double)p.T; p.alive = false; }
-        }
-        record_tally(d, row, slab, tl);
-        if (p.alive) {
-            d.T[s] = p.T;
-            d.ux[s] = p.u[0]; d.uy[s] = p.u[1]; d.uz[s] = p.u[2];
-            d.nl[s] = R(-1);
-            d.action[s] = A_IDLE;
-        } else {
-            retired = steps;
-            retire(d, s, row, steps);
-        }
-    }
+    if (act) interact_track<R, PROC>(d, s, sb, r, row, slab, retired);
     append_secondaries(d, sb, row, slab, r);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
     EMS_END_TRACKS
     flush_count(d, W_PROC0 + PROC, _work);
     flush_count(d, kStepsSlot + W_PROC0 + PROC, ret_acc);
+}
+
+// ---- drain: history-mode stepping of the last tracks ---------------------------------
+// When few tracks are left the step loop is bound by per-iteration launch
+// latency, not by work.  In a drain launch each thread takes one live slot and
+// steps its track to the end -- pre-step, along-step and interaction, through
+// the same per-track functions as the action kernels -- then continues with
+// its own secondaries, kept on a small private stack (LIFO, as in a
+// history-based transporter), and stops after `max_steps` steps.  Secondaries
+// that do not fit on the stack, and those left when the thread stops, go to
+// the initializer buffer for the step loop.  Random numbers are keyed by track
+// and step, so every track ends exactly as in the step loop.
+
+// Secondaries of one step: onto the private stack while it has room, else to
+// the initializer buffer (append-only while a drain runs).
+template <class R>
+__device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row, uint16_t slab,
+                                           const double r[3], Initializer* stack, uint32_t n_threads, uint32_t t,
+                                           int depth, int& sp)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= sb.n) break;
+        const Sec<R> v = sb.get(k);
+        Initializer rec;
+        rec.T = (double)v.T;
+        rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
+        rec.u[0] = (double)v.u[0]; rec.u[1] = (double)v.u[1]; rec.u[2] = (double)v.u[2];
+        rec.key = v.key;
+        rec.row = row;
+        rec.slab = slab;
+        rec.type = (uint8_t)v.type;
+        rec.pad = 0;
+        atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
+        atomicAdd(&d.live[row], 1u);
+        if (sp < depth) {
+            stack[(size_t)sp * n_threads + t] = rec;
+            ++sp;
+        } else {
+            unsigned long long q = atomicAdd(&d.ctr->queue_size, 1ull);
+            if (q < d.queue_cap) d.queue[q] = rec;
+            else atomicOr(&d.ctr->overflow, 1u);
+        }
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void drain_interact(const Dev<R>& d, int proc, uint32_t s, SecBuf<R>& sb, double r[3],
+                                               uint32_t& row, uint16_t& slab, uint32_t& retired)
+{
+    switch (proc) {
+    case P_COMPTON: interact_track<R, P_COMPTON>(d, s, sb, r, row, slab, retired); break;
+    case P_PHOTO:   interact_track<R, P_PHOTO>(d, s, sb, r, row, slab, retired); break;
+    case P_PAIR:    interact_track<R, P_PAIR>(d, s, sb, r, row, slab, retired); break;
+    case P_MOLLER:  interact_track<R, P_MOLLER>(d, s, sb, r, row, slab, retired); break;
+    case P_BHABHA:  interact_track<R, P_BHABHA>(d, s, sb, r, row, slab, retired); break;
+    default:        interact_track<R, P_BREMS>(d, s, sb, r, row, slab, retired); break;
+    }
+}
+
+// Thread t takes the t-th live slot: first the slots alive before this
+// iteration's fill (listed by the vacancy pass), then the slots just filled.
+template <class R>
+__global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_list, Initializer* stack,
+                                               uint32_t n_threads, int depth, uint32_t max_steps)
+{
+    extern __shared__ __align__(16) unsigned char ems_lds[];
+    const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_old = d.ctr->alive_before;
+    const uint32_t n_new = d.ctr->n_take_q + d.ctr->n_take_p;
+    unsigned long long ret_acc = 0, work = 0;
+    if (t < n_threads && t < n_old + n_new) {
+        const uint32_t s = t < n_old ? live_list[t] : d.vac[t - n_old];
+        int sp = 0;
+        for (uint32_t k = 0; k < max_steps; ++k) {
+            if (d.type[s] == kDead) {
+                if (sp == 0) break;
+                --sp;
+                const Initializer rec = stack[(size_t)sp * n_threads + t];
+                init_slot(d, s, rec);
+            }
+            uint8_t a;
+            if (d.flags[s] & F_PAUSED) {
+                a = A_FIELD;
+            } else {
+                a = pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
+            }
+            SecBuf<R> sb;
+            sb.n = 0;
+            double r[3] = {0.0, 0.0, 0.0};
+            uint32_t row = 0, retired = 0;
+            uint16_t slab0 = 0;
+            uint8_t next = A_NONE;
+            if (a == A_NEUTRAL) {
+                along_straight_track<R, false>(d, tb, s, sb, r, row, slab0, next, retired);
+            } else if (a == A_CHARGED) {
+                along_straight_track<R, true>(d, tb, s, sb, r, row, slab0, next, retired);
+            } else {
+                // a paused step resumes on the next trip (pausing does not change the result)
+                uint32_t att = 0, paused_n = 0;
+                along_field_track<R>(d, tb, s, kDrainSubsteps, sb, r, row, slab0, next, retired, att, paused_n);
+            }
+            drain_push(d, sb, row, slab0, r, stack, n_threads, t, depth, sp);
+            if (next >= A_PROC0 && next < A_NUM) {
+                SecBuf<R> sb2;
+                sb2.n = 0;
+                double r2[3] = {0.0, 0.0, 0.0};
+                uint16_t slab2 = 0;
+                drain_interact<R>(d, next - A_PROC0, s, sb2, r2, row, slab2, retired);
+                drain_push(d, sb2, row, slab2, r2, stack, n_threads, t, depth, sp);
+            }
+            if (retired) {
+                leave_event(d, true, row);
+                ret_acc += retired;
+            }
+            ++work;
+        }
+        // what is left on the stack goes back to the step loop
+        while (sp > 0) {
+            --sp;
+            const Initializer rec = stack[(size_t)sp * n_threads + t];
+            unsigned long long q = atomicAdd(&d.ctr->queue_size, 1ull);
+            if (q < d.queue_cap) d.queue[q] = rec;
+            else atomicOr(&d.ctr->overflow, 1u);
+        }
+    }
+    flush_count(d, W_DRAIN, work);
+    flush_count(d, kStepsSlot + W_DRAIN, ret_acc);
 }
 
 // ---- event completion ---------------------------------------------------------------

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 FP64, MIXED = 0, 1
 SORT_NONE, SORT_PARTITION, SORT_RADIX, SORT_QUEUE = 0, 1, 2, 3
 SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX, "queue": SORT_QUEUE}
@@ -50,7 +50,8 @@ class Material(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16)]
+    _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16),
+                ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32)]
 
 
 class Counters(C.Structure):
@@ -66,7 +67,7 @@ class Counters(C.Structure):
 
 WORK_INDEX = {1: "init", 2: "pre_step", 4: "along_neutral", 5: "along_charged", 6: "along_field",
               7: "compton", 8: "photoelectric", 9: "pair", 10: "moller", 11: "bhabha", 12: "bremsstrahlung",
-              13: "field_paused", 14: "field_substeps"}
+              13: "field_paused", 14: "field_substeps", 15: "drain"}
 
 
 PRIMARY_DTYPE = np.dtype([
@@ -311,9 +312,10 @@ class Session:
         t = Tuning()
         _check(_lib.ems_get_tuning(self._h, C.byref(t)), "ems_get_tuning")
         return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
+                "drain_threshold": t.drain_threshold, "drain_steps": t.drain_steps,
                 "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
 
-    def set_tuning(self, sort_policy=None, tail_threshold=None, block=None):
+    def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None):
         """Change knobs that affect speed only; block maps kernel role names to block sizes."""
         cur = Tuning()
         _check(_lib.ems_get_tuning(self._h, C.byref(cur)), "ems_get_tuning")
@@ -321,6 +323,10 @@ class Session:
             cur.sort_policy = SORT_POLICIES[sort_policy] if isinstance(sort_policy, str) else int(sort_policy)
         if tail_threshold is not None:
             cur.tail_threshold = int(tail_threshold)
+        if drain_threshold is not None:
+            cur.drain_threshold = int(drain_threshold)
+        if drain_steps is not None:
+            cur.drain_steps = int(drain_steps)
         if block is not None:
             for name, b in block.items():
                 cur.block[KERNEL_ROLES.index(name)] = int(b)
@@ -340,7 +346,7 @@ class Session:
 
 
 KERNEL_ROLES = ["vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged", "along_field",
-                "compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung"]
+                "compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "drain"]
 
 
 def role_mask(*names):

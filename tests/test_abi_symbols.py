@@ -38,7 +38,7 @@ def test_option_validation_on_host():
     # argument validation runs before any device call
     from paper_2503_17608_amd import emstep
     o = emstep.Options()
-    o.abi_version = 1
+    o.abi_version = emstep.ABI_VERSION
     o.n_slots = 0
     n = ctypes.c_uint64(0)
     assert emstep._lib.ems_query_workspace(ctypes.byref(o), ctypes.byref(n)) == emstep.ERR_INVALID_ARG
@@ -51,4 +51,7 @@ def test_option_validation_on_host():
     assert emstep._lib.ems_query_workspace(ctypes.byref(o), ctypes.byref(n)) == emstep.OK
     assert n.value > 4096 * 100
     o.block_size = 100
+    assert emstep._lib.ems_query_workspace(ctypes.byref(o), ctypes.byref(n)) == emstep.ERR_INVALID_ARG
+    o.block_size = 0
+    o.abi_version = emstep.ABI_VERSION - 1
     assert emstep._lib.ems_query_workspace(ctypes.byref(o), ctypes.byref(n)) == emstep.ERR_INVALID_ARG

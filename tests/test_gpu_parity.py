@@ -251,3 +251,32 @@ def test_tuning_does_not_change_results():
         assert _ledger_equal_int(led, l_ref) is None, tuning
         assert np.abs(edep - e_ref).max() <= 1e-9 * 1000.0, tuning
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_drain_mode_matches_step_loop_and_oracle(precision):
+    """History-mode drain of the last tracks gives the step loop's results:
+    every track is stepped by the same per-track code with the same keyed
+    random numbers, whatever the threshold, the per-launch step budget (small
+    budgets stop threads mid-shower and hand their stacks back) or the
+    slot count."""
+    w = workloads.electron_showers_1gev_field(30, n_slots=1 << 15)
+    ref_e, ref_l, ref_c = _run_lib(w, precision=precision, sort_policy="partition", graph_iterations=4)
+    if precision == "f64":
+        e_or, l_or, steps = _run_oracle(w)
+        assert ref_c["steps"] == steps
+        assert _ledger_equal_int(ref_l, l_or) is None
+    for thr, budget, slots in [(1 << 30, 4096, 1 << 15), (4000, 3, 1 << 15), (20000, 64, 5000), (1000, 100000, 1 << 16)]:
+        s = session_for(w, n_slots=slots, precision=precision, sort_policy="partition", graph_iterations=4)
+        s.set_tuning(drain_threshold=thr, drain_steps=budget)
+        s.push(w.primaries)
+        c = s.run(max_iterations=1_000_000)
+        edep, led = s.tallies_by_event(np.arange(w.n_events))
+        s.close()
+        tag = (precision, thr, budget, slots)
+        assert c["overflow"] == 0, tag
+        assert c["work"]["drain"] > 0, tag
+        assert c["steps"] == ref_c["steps"], (tag, c["steps"], ref_c["steps"])
+        assert _ledger_equal_int(led, ref_l) is None, (tag, _ledger_equal_int(led, ref_l))
+        scale = np.abs(ref_e).max(1, keepdims=True)
+        assert np.all(np.abs(edep - ref_e) <= 1e-12 * scale + 1e-300), tag
