@@ -117,6 +117,7 @@ def parse():
     ap.add_argument("--drain-threshold", type=int, default=65536,
                     help="run the last tracks in history mode below this many live+queued+pending (0 = off)")
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
+    ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=4000, help="oracle sample (events); 0 = skip")
@@ -143,7 +144,7 @@ def make_workload(name, events, slots):
     return w
 
 
-def new_session(w, args, precision, policy, init_partition, graph=None, drain=None):
+def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
     s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
@@ -153,8 +154,9 @@ def new_session(w, args, precision, policy, init_partition, graph=None, drain=No
                        streams=args.streams, n_primaries=max(len(w.primaries), 1 << 16))
     s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
     drain = args.drain_threshold if drain is None else drain
-    if drain > 0:
-        s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps)
+    reuse = args.reuse_parent_slot if reuse is None else reuse
+    if drain > 0 or reuse:
+        s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse))
     return s
 
 
@@ -168,8 +170,8 @@ def time_batch(s, primaries, events):
     return c, time.perf_counter() - t0
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None):
-    s = new_session(w, args, precision, policy, init_partition, drain=drain)
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None):
+    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse)
     events = np.unique(w.primaries["event"])
     tuned = None
     if tune is not None:
@@ -224,6 +226,35 @@ def cpu_baseline(w, n_events):
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "track-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_events} events of the workload ({steps} track-steps, {dt:.2f} s wall)"}
+
+
+def event_parallel_rate(w, args, precision, k, repeats=2):
+    """Event-parallel mode: k sessions of n_slots/k slots, each on its own
+    stream and host thread, events handed out in chunks; track-steps/s."""
+    import torch
+
+    from paper_2503_17608_amd import emstep, multistream
+    st = w.stack
+    chunk = max(1, w.n_events // (4 * k))
+    sessions = []
+    for _ in range(k):
+        s = emstep.Session(max(w.n_slots // k, 1024), precision=precision, max_events=chunk, max_slabs=st.n_slabs,
+                           max_materials=len(st.materials), seed=w.seed, sort_policy=args.policy,
+                           max_substeps=args.max_substeps, graph_iterations=args.graph, lds_tables=args.lds_tables,
+                           streams=1, stream=torch.cuda.Stream(), n_primaries=max(len(w.primaries), 1 << 16))
+        s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
+        if args.drain_threshold > 0:
+            s.set_tuning(drain_threshold=max(args.drain_threshold // k, 256), drain_steps=args.drain_steps)
+        sessions.append(s)
+    multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)     # warm-up
+    best = None
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        _, _, steps, wall = multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)
+        best = steps / wall if best is None else max(best, steps / wall)
+    for s in sessions:
+        s.close()
+    return best
 
 
 def path_roofline(work, steps, rate, precision):
@@ -347,6 +378,7 @@ def main():
                    "max_substeps": args.max_substeps, "graph_iterations": args.graph,
                    "lds_tables": args.lds_tables, "streams": args.streams,
                    "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
+                   "reuse_parent_slot": args.reuse_parent_slot,
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
@@ -362,7 +394,7 @@ def main():
         achieved = per_launch / avg_s / 1e9
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
-               "drain_threshold": args.drain_threshold}
+               "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot}
         t = committed_traffic(prof_kernel, key)
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -377,13 +409,17 @@ def main():
     out["path_roofline"] = path_roofline(r["work"], r["steps"], value, precision)
     if args.compare:
         var = {}
-        for pol, part, dr in [("none", 0, None), ("none", 1, None), ("partition", 0, None), ("partition", 1, None),
-                              ("radix", 0, None), ("queue", 0, None), ("none", 0, 0), ("partition", 0, 0)]:
-            if pol == args.policy and part == args.init_partition and dr is None:
+        for pol, part, dr, ru in [("none", 0, None, None), ("none", 1, None, None), ("partition", 0, None, None),
+                                  ("partition", 1, None, None), ("radix", 0, None, None), ("queue", 0, None, None),
+                                  ("none", 0, 0, None), ("partition", 0, 0, None), ("partition", 0, None, 1),
+                                  ("partition", 1, None, 1)]:
+            if pol == args.policy and part == args.init_partition and dr is None and ru is None:
                 continue
-            rv = run_variant(w, args, precision, pol, part, None, drain=dr)
-            tag = f"{pol}+part{part}" + ("+nodrain" if dr == 0 else "")
+            rv = run_variant(w, args, precision, pol, part, None, drain=dr, reuse=ru)
+            tag = f"{pol}+part{part}" + ("+nodrain" if dr == 0 else "") + ("+reuse" if ru else "")
             var[tag] = rv["steps"] / rv["seconds"]
+        for k in (4, 8):
+            var[f"event_parallel_{k}x{w.n_slots // k}"] = event_parallel_rate(w, args, precision, k)
         out["variants"] = var
     if args.layer_error:
         out["layer_error_vs_fp64_oracle"] = layer_error(w, r["edep"])

@@ -273,6 +273,11 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * (a private stack of 8; the rest go back to the initializer buffer) for up
  * to drain_steps steps (> 0).  It removes the per-iteration launch latency of
  * the last, nearly empty iterations; the physics is the same per-track code.
+ *
+ * reuse_parent_slot (0/1): a track that ends in a step hands its slot to its
+ * first secondary directly, instead of through the initializer buffer and the
+ * next iteration's fill (fewer initializer round trips; it mixes charged and
+ * neutral tracks in slots that init_partition would keep apart).
  * Setting the tuning re-captures graphs on the next run. */
 typedef struct {
     int32_t sort_policy;
@@ -280,6 +285,7 @@ typedef struct {
     int32_t block[16];
     uint32_t drain_threshold;
     uint32_t drain_steps;
+    uint32_t reuse_parent_slot;
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

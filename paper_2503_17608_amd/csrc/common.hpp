@@ -111,7 +111,7 @@ struct Counters {
 
 // work counter indices
 enum : int {
-    W_INIT = 1, W_PRE = 2, W_SORT = 3, W_NEUTRAL = 4, W_CHARGED = 5, W_FIELD = 6, W_PROC0 = 7,
+    W_REUSE = 0, W_INIT = 1, W_PRE = 2, W_SORT = 3, W_NEUTRAL = 4, W_CHARGED = 5, W_FIELD = 6, W_PROC0 = 7,
     W_PAUSED = 13, W_SUBSTEPS = 14, W_DRAIN = 15
 };
 // partial-counter slots: [0, 16) work per kernel, [16, 32) completed steps of

@@ -45,12 +45,20 @@ ems_status fail(ems_status s, const std::string& msg)
 
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+constexpr uint64_t kStagingCap = 1 << 16;   // primaries / row registrations per host-to-device copy
+
+// a new event row: {event id, row, registration generation}
+struct RowReg {
+    uint64_t ev;
+    uint32_t row, gen;
+};
+
 // Workspace layout: every region 256-byte aligned, offsets from the base.
 struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
-    uint64_t drain_stack;
+    uint64_t drain_stack, regs;
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads with a private stack)
     uint64_t total;
@@ -118,6 +126,7 @@ Layout make_layout(const ems_options& o)
     L.incr = take(8ull * o.max_materials * 2 * (kNodes - 1));
     L.drain_threads = (uint32_t)std::min<uint64_t>(kDrainThreadsMax, align_up(n, 256));
     L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
+    L.regs = take(sizeof(RowReg) * kStagingCap);
     L.total = off;
     return L;
 }
@@ -161,6 +170,8 @@ struct ems_ctx {
     uint64_t snap_seq = 0;
     Initializer* staging = nullptr;            // pinned primary staging
     uint64_t staging_cap = 0;
+    RowReg* reg_staging = nullptr;             // pinned staging of new row registrations (staging_cap entries)
+    std::vector<RowReg> reg_pending;           // rows assigned on the host, not yet cleared on the device
     hipEvent_t staging_ev;
     bool staging_busy = false;
     // concurrent branches
@@ -177,6 +188,7 @@ struct ems_ctx {
     uint32_t tail_threshold = 0;
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
+    uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -253,6 +265,7 @@ Dev<R> make_dev(const ems_ctx* c)
     d.sorted2 = c->policy == EMS_SORT_NONE ? 0 : (c->policy == EMS_SORT_QUEUE ? 2 : 1);
     d.tail_threshold = c->tail_threshold;
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
+    d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
 }
@@ -288,6 +301,21 @@ __global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double
         live[row] = 0u;
         row_gen[row] = gen;
         row_state[row] = ev != UINT64_MAX ? 1u : 0u;
+    }
+}
+
+// A batch of registrations {event, row, generation}: one block per row.
+__global__ void k_set_rows(const RowReg* regs, uint64_t* row_event, double* edep, Ledger* led, uint32_t n_slabs,
+                           unsigned int* live, unsigned int* row_gen, unsigned int* row_state)
+{
+    const RowReg g = regs[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)g.row * n_slabs + i] = 0.0;
+    if (threadIdx.x == 0) {
+        row_event[g.row] = g.ev;
+        led[g.row] = Ledger{};
+        live[g.row] = 0u;
+        row_gen[g.row] = g.gen;
+        row_state[g.row] = 1u;
     }
 }
 
@@ -648,12 +676,36 @@ ems_status assign_row(ems_ctx* c, uint64_t ev, uint32_t* row)
     c->row_of[ev] = r;
     c->row_event[r] = ev;
     c->row_gen[r] += 1;
-    hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), r, ev,
-                       (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs,
-                       (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[r],
-                       (unsigned int*)(c->ws + c->L.row_state));
-    HIP_TRY(hipGetLastError());
+    c->reg_pending.push_back(RowReg{ev, r, c->row_gen[r]});
     *row = r;
+    return EMS_OK;
+}
+
+// Clear and register on the device the rows assigned since the last flush
+// (one kernel); the caller guarantees the registration staging is free.
+ems_status flush_rows(ems_ctx* c)
+{
+    size_t done = 0;
+    while (done < c->reg_pending.size()) {
+        size_t k = std::min<size_t>(c->reg_pending.size() - done, c->staging_cap);
+        if (c->staging_busy) {
+            HIP_TRY(hipEventSynchronize(c->staging_ev));
+            c->staging_busy = false;
+        }
+        std::memcpy(c->reg_staging, c->reg_pending.data() + done, sizeof(RowReg) * k);
+        RowReg* dev = (RowReg*)(c->ws + c->L.regs);
+        HIP_TRY(hipMemcpyAsync(dev, c->reg_staging, sizeof(RowReg) * k, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_set_rows, dim3((uint32_t)k), dim3(256), 0, c->stream, (const RowReg*)dev,
+                           (uint64_t*)(c->ws + c->L.row_event), (double*)(c->ws + c->L.edep),
+                           (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs,
+                           (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen),
+                           (unsigned int*)(c->ws + c->L.row_state));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(c->staging_ev, c->stream));
+        c->staging_busy = true;
+        done += k;
+    }
+    c->reg_pending.clear();
     return EMS_OK;
 }
 
@@ -716,9 +768,11 @@ ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t b
     if (hipHostMalloc((void**)&c->snap, sizeof(Snapshot) * c->snap_slots, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc snapshot"));
     for (int i = 0; i < c->snap_slots; ++i) (void)hipEventCreateWithFlags(&c->snap_ev[i], hipEventDisableTiming);
-    c->staging_cap = 1 << 16;
+    c->staging_cap = kStagingCap;
     if (hipHostMalloc((void**)&c->staging, sizeof(Initializer) * c->staging_cap, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc staging"));
+    if (hipHostMalloc((void**)&c->reg_staging, sizeof(RowReg) * c->staging_cap, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(EMS_ERR_DEVICE, "hipHostMalloc registration staging"));
     (void)hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming);
     c->policy = opt->sort_policy;
     c->n_streams = opt->streams > 1 ? opt->streams : 1;
@@ -757,6 +811,7 @@ void ems_destroy(ems_ctx* c)
         (void)hipHostFree(c->snap);
         for (int i = 0; i < c->snap_slots; ++i) (void)hipEventDestroy(c->snap_ev[i]);
     }
+    if (c->reg_staging) (void)hipHostFree(c->reg_staging);
     if (c->staging) {
         (void)hipHostFree(c->staging);
         (void)hipEventDestroy(c->staging_ev);
@@ -918,6 +973,10 @@ ems_status ems_push_primaries(ems_ctx* c, const ems_primary* p, uint64_t n)
             r.type = (uint8_t)q.type;
             r.pad = 0;
         }
+        // rows first: clearing a row zeroes its live count, which the
+        // primaries below then raise
+        s = flush_rows(c);
+        if (s != EMS_OK) return s;
         // copy into the ring [prim_end, prim_end + chunk) modulo capacity
         uint64_t cap = c->opt.n_primaries;
         uint64_t at = c->prim_end % cap;
@@ -1126,7 +1185,9 @@ ems_status ems_release_event(ems_ctx* c, uint64_t event)
 ems_status ems_debug_register_event(ems_ctx* c, uint64_t event, uint32_t* row)
 {
     if (!c || !row) return fail(EMS_ERR_INVALID_ARG, "null");
-    return assign_row(c, event, row);
+    ems_status s = assign_row(c, event, row);
+    if (s != EMS_OK) return s;
+    return flush_rows(c);
 }
 
 ems_status ems_debug_inject(ems_ctx* c, const ems_track* t, uint64_t n)
@@ -1257,6 +1318,7 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
     c->tail_threshold = t->tail_threshold;
     c->drain_threshold = t->drain_threshold;
     c->drain_steps = t->drain_steps;
+    c->reuse_parent = t->reuse_parent_slot ? 1u : 0u;
     for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
     return drop_graph(c);
 }
@@ -1268,6 +1330,7 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     t->tail_threshold = c->tail_threshold;
     t->drain_threshold = c->drain_threshold;
     t->drain_steps = c->drain_steps;
+    t->reuse_parent_slot = c->reuse_parent;
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }

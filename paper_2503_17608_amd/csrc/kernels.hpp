@@ -73,6 +73,7 @@ struct Dev {
     int sorted2;            // interaction kernels: 0 masked, 1 sorted ranges, 2 lists filled by the along-step
     unsigned int tail_threshold;  // below this many live tracks an iteration runs masked (no reordering)
     int stage_tables;       // copy the tables into LDS at block start
+    int reuse_parent;       // a track that ends hands its slot to its first secondary
     int n_tab;              // table values (n_materials * 8 * 181)
 };
 
@@ -421,6 +422,34 @@ __device__ __forceinline__ void retire(const Dev<R>& d, uint32_t s, uint32_t row
     atomicAdd(&d.ledger[row].steps, (unsigned long long)steps);
 }
 
+// Parent-slot reuse: a track that ended in this step hands its slot to its
+// first secondary, which then skips the initializer buffer and the fill of
+// the next iteration.  The secondary is a new track in every other respect
+// (step 0, interaction length unset).  Returns 1 when the slot was reused.
+template <class R>
+__device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecBuf<R>& sb, uint32_t row,
+                                               uint16_t slab, const double r[3])
+{
+    if (!d.reuse_parent || sb.n == 0) return 0u;
+    const Sec<R> v = sb.get(0);
+    Initializer rec;
+    rec.T = (double)v.T;
+    rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
+    rec.u[0] = (double)v.u[0]; rec.u[1] = (double)v.u[1]; rec.u[2] = (double)v.u[2];
+    rec.key = v.key;
+    rec.row = row;
+    rec.slab = slab;
+    rec.type = (uint8_t)v.type;
+    rec.pad = 0;
+    init_slot(d, s, rec);
+    atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
+    atomicAdd(&d.live[row], 1u);
+    sb.s0 = sb.s1;
+    sb.s1 = sb.s2;
+    sb.n -= 1;
+    return 1u;
+}
+
 // Pre-step of one live, non-paused track (fields loaded by the caller):
 // interaction length, total cross section, physics step limit and the
 // along-step action, which it returns.
@@ -676,7 +705,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     const uint8_t A = CHARGED ? A_CHARGED : A_NEUTRAL;
     EMS_TRACK_RANGE(d, A)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0;
+    unsigned long long ret_acc = 0, reuse_acc = 0;
     EMS_FOR_TRACKS(d, A, s, act, CHARGED ? W_CHARGED : W_NEUTRAL)
     SecBuf<R> sb;
     sb.n = 0;
@@ -686,6 +715,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     uint8_t next = A_NONE;
     uint32_t retired = 0;
     if (act) along_straight_track<R, CHARGED>(d, tb, s, sb, r, row, slab0, next, retired);
+    if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab0, r);
     append_secondaries(d, sb, row, slab0, r);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
@@ -693,6 +723,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     EMS_END_TRACKS
     flush_count(d, CHARGED ? W_CHARGED : W_NEUTRAL, _work);
     flush_count(d, kStepsSlot + (CHARGED ? W_CHARGED : W_NEUTRAL), ret_acc);
+    flush_count(d, W_REUSE, reuse_acc);
 }
 
 // ---- along-step in a uniform field -------------------------------------------------
@@ -893,7 +924,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     extern __shared__ __align__(16) unsigned char ems_lds[];
     EMS_TRACK_RANGE(d, A_FIELD)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0;
+    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0, reuse_acc = 0;
     EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
     SecBuf<R> sb;
     sb.n = 0;
@@ -903,6 +934,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     uint8_t next = A_NONE;
     uint32_t retired = 0, att = 0, paused_n = 0;
     if (act) along_field_track<R>(d, tb, s, d.max_substeps, sb, r, row, slab0, next, retired, att, paused_n);
+    if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab0, r);
     append_secondaries(d, sb, row, slab0, r);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
@@ -914,6 +946,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
     flush_count(d, W_SUBSTEPS, sub_acc);
     flush_count(d, W_PAUSED, pause_acc);
+    flush_count(d, W_REUSE, reuse_acc);
 }
 
 // Discrete interaction PROC of one track at the end of its along-step.
@@ -969,7 +1002,7 @@ template <class R, int PROC>
 __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
 {
     EMS_TRACK_RANGE(d, (uint8_t)(A_PROC0 + PROC))
-    unsigned long long ret_acc = 0;
+    unsigned long long ret_acc = 0, reuse_acc = 0;
     EMS_FOR_TRACKS(d, (uint8_t)(A_PROC0 + PROC), s, act, W_PROC0 + PROC)
     SecBuf<R> sb;
     sb.n = 0;
@@ -978,12 +1011,14 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     uint16_t slab = 0;
     uint32_t retired = 0;
     if (act) interact_track<R, PROC>(d, s, sb, r, row, slab, retired);
+    if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
     append_secondaries(d, sb, row, slab, r);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
     EMS_END_TRACKS
     flush_count(d, W_PROC0 + PROC, _work);
     flush_count(d, kStepsSlot + W_PROC0 + PROC, ret_acc);
+    flush_count(d, W_REUSE, reuse_acc);
 }
 
 // ---- drain: history-mode stepping of the last tracks ---------------------------------

@@ -51,7 +51,7 @@ class Material(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16),
-                ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32)]
+                ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32), ("reuse_parent_slot", C.c_uint32)]
 
 
 class Counters(C.Structure):
@@ -65,7 +65,7 @@ class Counters(C.Structure):
         return d
 
 
-WORK_INDEX = {1: "init", 2: "pre_step", 4: "along_neutral", 5: "along_charged", 6: "along_field",
+WORK_INDEX = {0: "reused_slots", 1: "init", 2: "pre_step", 4: "along_neutral", 5: "along_charged", 6: "along_field",
               7: "compton", 8: "photoelectric", 9: "pair", 10: "moller", 11: "bhabha", 12: "bremsstrahlung",
               13: "field_paused", 14: "field_substeps", 15: "drain"}
 
@@ -313,9 +313,11 @@ class Session:
         _check(_lib.ems_get_tuning(self._h, C.byref(t)), "ems_get_tuning")
         return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
                 "drain_threshold": t.drain_threshold, "drain_steps": t.drain_steps,
+                "reuse_parent_slot": bool(t.reuse_parent_slot),
                 "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
 
-    def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None):
+    def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None,
+                   reuse_parent_slot=None):
         """Change knobs that affect speed only; block maps kernel role names to block sizes."""
         cur = Tuning()
         _check(_lib.ems_get_tuning(self._h, C.byref(cur)), "ems_get_tuning")
@@ -327,6 +329,8 @@ class Session:
             cur.drain_threshold = int(drain_threshold)
         if drain_steps is not None:
             cur.drain_steps = int(drain_steps)
+        if reuse_parent_slot is not None:
+            cur.reuse_parent_slot = 1 if reuse_parent_slot else 0
         if block is not None:
             for name, b in block.items():
                 cur.block[KERNEL_ROLES.index(name)] = int(b)

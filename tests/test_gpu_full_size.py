@@ -5,7 +5,8 @@ and rejected inputs.
 
 * 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event against
   the FP64 oracle (integer ledger equal, deposits to 1e-9 of the primary
-  energy), for the sort policies none / partition / radix / queue;
+  energy), for the sort policies none / partition / radix / queue and with
+  parent-slot reuse and the drain of the last tracks;
 * 10^4 mixed primaries in a 5 degree cone at 2^20 slots: FP64 per event
   against the oracle, and the mixed-precision run's per-layer mean deposit
   within 0.5 % of the FP64 oracle;
@@ -28,10 +29,12 @@ ME = 0.51099895
 BENCH = dict(sort_policy="partition", graph_iterations=8, lds_tables=1, streams=4, max_substeps=10)
 
 
-def _run(w, events=None, **kw):
+def _run(w, events=None, tuning=None, **kw):
     opts = dict(BENCH)
     opts.update(kw)
     s = session_for(w, **opts)
+    if tuning:
+        s.set_tuning(**tuning)
     s.push(w.primaries)
     c = s.run(max_iterations=1_000_000)
     ev = np.arange(w.n_events) if events is None else np.asarray(events)
@@ -73,8 +76,13 @@ def test_full_size_electron_showers_every_policy():
     w = workloads.electron_showers_1gev_field()
     assert w.n_events == 10_000 and w.n_slots == 1 << 20
     e_ref, l_ref, steps = run_oracle(w)
-    for policy in ("partition", "none", "radix", "queue"):
-        edep, led, c = _run(w, sort_policy=policy)
+    for policy in ("partition", "none", "radix", "queue", "partition+reuse+drain"):
+        if policy == "partition+reuse+drain":
+            edep, led, c = _run(w, sort_policy="partition", tuning=dict(reuse_parent_slot=True,
+                                                                        drain_threshold=65536))
+            assert c["work"]["reused_slots"] > 0 and c["work"]["drain"] > 0
+        else:
+            edep, led, c = _run(w, sort_policy=policy)
         assert c["overflow"] == 0, policy
         assert c["steps"] == steps, (policy, c["steps"], steps)
         _assert_events_match(w, edep, led, e_ref, l_ref, policy)

@@ -241,7 +241,9 @@ def test_tuning_does_not_change_results():
     s = session_for(w, sort_policy="partition", graph_iterations=4)
     for tuning in [dict(sort_policy="radix", tail_threshold=3000, block={"pre_step": 64, "along_field": 512}),
                    dict(sort_policy="queue", tail_threshold=0, block={"along_neutral": 128, "compton": 448}),
-                   dict(sort_policy="none", tail_threshold=100000, block={"bremsstrahlung": 64})]:
+                   dict(sort_policy="none", tail_threshold=100000, block={"bremsstrahlung": 64}),
+                   dict(sort_policy="partition", tail_threshold=0, reuse_parent_slot=True),
+                   dict(sort_policy="queue", reuse_parent_slot=True, drain_threshold=3000, drain_steps=50)]:
         s.set_tuning(**tuning)
         s.push(w.primaries)
         c = s.run()
