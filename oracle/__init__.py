@@ -61,7 +61,7 @@ class _Problem(C.Structure):
         ("z_planes", C.c_void_p), ("slab_material", C.c_void_p),
         ("half_width", C.c_double), ("B", C.c_double * 3),
         ("tables", C.c_void_p), ("ecut", C.c_double), ("seed", C.c_uint64),
-        ("no_discrete", C.c_int32), ("pad", C.c_int32),
+        ("no_discrete", C.c_int32), ("msc", C.c_int32), ("x0_cm", C.c_void_p),
     ]
 
 
@@ -105,6 +105,10 @@ def lib():
         L.orc_inverse_range.restype = C.c_double
         L.orc_xs.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int, C.c_double]
         L.orc_xs.restype = C.c_double
+        L.orc_msc_theta0.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_msc_theta0.restype = C.c_double
+        L.orc_msc_deflect.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int, C.c_double, C.c_double]
+        L.orc_msc_deflect.restype = None
         _lib = L
     return _lib
 
@@ -113,7 +117,7 @@ class Problem:
     """Geometry + materials + cut + seed, with the oracle's own FP64 tables."""
 
     def __init__(self, z_planes, slab_material, half_width, B, materials, ecut, seed,
-                 no_discrete=False, table_blob=None):
+                 no_discrete=False, table_blob=None, msc=False):
         self.z_planes = np.ascontiguousarray(z_planes, dtype=np.float64)
         self.slab_material = np.ascontiguousarray(slab_material, dtype=np.int32)
         self.materials = [m if isinstance(m, tables.Material) else tables.Material(*m) for m in materials]
@@ -133,6 +137,9 @@ class Problem:
         s.ecut = self.ecut
         s.seed = int(seed)
         s.no_discrete = int(bool(no_discrete))
+        self.x0_cm = np.array([m.X0_cm for m in self.materials], dtype=np.float64)
+        s.msc = int(bool(msc))
+        s.x0_cm = self.x0_cm.ctypes.data
         self._s = s
 
     # -- single step ----------------------------------------------------------
@@ -166,6 +173,16 @@ class Problem:
 
     def xs(self, mat, proc, T):
         return lib().orc_xs(C.byref(self._s), int(mat), int(proc), float(T))
+
+    def msc_deflect(self, track, mat, T_pre, s):
+        """Apply the multiple-scattering deflection of a step of length s to
+        each track (direction updated in place)."""
+        tr = np.atleast_1d(track)
+        assert tr.dtype == TRACK_DTYPE and tr.flags.c_contiguous
+        L = lib()
+        for i in range(len(tr)):
+            L.orc_msc_deflect(C.byref(self._s), tr[i:i + 1].ctypes.data, int(mat), float(T_pre), float(s))
+
 
     # -- whole events -----------------------------------------------------------
     def run_events(self, prims, rows, n_rows, n_threads=1):
@@ -228,3 +245,8 @@ def problem_for(workload, **kw):
     st = workload.stack
     return Problem(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, workload.ecut,
                    workload.seed, **kw)
+
+
+def msc_theta0(T, s, X0):
+    """Highland width of the projected scattering angle [rad] (0 for s = 0)."""
+    return lib().orc_msc_theta0(float(T), float(s), float(X0))

@@ -30,6 +30,8 @@
  *  S6  charged: T' = R^-1(R(T) - s); deposit T - T'.  Range exhausted or
  *      T' < Ec: deposit all of T and stop (positron: annihilate at rest).
  *  S7  n_lambda -= s * Sigma(T_pre).
+ *  S7b optional multiple scattering: a charged track that is still in the
+ *      stack after S6 is deflected (see msc_deflect).
  *  S8  boundary: slab +- 1 or escape.  Interaction: U_j * Sigma(T') against
  *      cumulative sigma_i(T'); sample; n_lambda unset.
  *  S9  particles below Ec after an interaction deposit locally; secondaries
@@ -40,7 +42,8 @@
  * (seed, event), counter = (track key, step, block, domain).  Uniform j of a
  * step is word j&3 of block j>>2 of domain 0, mapped to ((w>>12)+0.5)*2^-52.
  * Child keys: word 0 of domain 1 at counter (parent key, parent step,
- * ordinal).  Annihilation at rest: domain 4, block 0.
+ * ordinal).  Annihilation at rest: domain 4, block 0.  Multiple
+ * scattering: domain 5, block 0.
  *
  * Units: MeV, cm, tesla.
  */
@@ -81,7 +84,8 @@ typedef struct {
     double ecut;                   /* production = tracking cut [MeV] */
     uint64_t seed;
     int32_t no_discrete;           /* test hook: 1 = no discrete processes (CSDA) */
-    int32_t pad;
+    int32_t msc;                   /* 1 = multiple-scattering deflection (S7b) */
+    const double* x0_cm;           /* radiation length of each material [cm] */
 } orc_problem;
 
 typedef struct {
@@ -673,6 +677,49 @@ double orc_propagate_field(const orc_problem* pb, orc_track* t, double s_phys, i
 static int has_field(const orc_problem* pb) { return pb->B[0] != 0.0 || pb->B[1] != 0.0 || pb->B[2] != 0.0; }
 
 /* ------------------------------------------------------------------ one step */
+/* ------------------------------------------------------------------ multiple scattering
+ * Optional angular deflection of charged tracks after each along-step (no
+ * lateral displacement).  The projected scattering angles are taken as
+ * Gaussian with the Highland width (PDG review of particle properties,
+ * "Passage of particles through matter", multiple scattering through small
+ * angles) for a singly charged particle:
+ *     theta0 = 13.6 MeV / (beta c p) * sqrt(x) * (1 + 0.038 ln(x / beta^2)),
+ *     x = s / X0,
+ * at the pre-step kinetic energy.  Two independent Gaussian projections make
+ * the space angle Rayleigh distributed: theta = theta0 sqrt(-2 ln U_a), with
+ * a uniform azimuth 2 pi U_b.  U_a, U_b are words 0 and 1 of the Philox block
+ * at counter (key, step, 0, 5).  No deflection when s = 0 or when the bracket
+ * is not positive (x / beta^2 below about 4e-12). */
+double orc_msc_theta0(double T, double s, double X0)
+{
+    if (!(s > 0.0)) return 0.0;
+    double p = sqrt(T * (T + 2.0 * ORC_ME));
+    double beta = p / (T + ORC_ME);
+    double x = s / X0;
+    double bracket = 1.0 + 0.038 * log(x / (beta * beta));
+    if (!(bracket > 0.0)) return 0.0;
+    return 13.6 / (beta * p) * sqrt(x) * bracket;
+}
+
+static void msc_deflect(const orc_problem* pb, orc_track* t, int mat, double T_pre, double s)
+{
+    double theta0 = orc_msc_theta0(T_pre, s, pb->x0_cm[mat]);
+    if (theta0 == 0.0) return;
+    double ua = to_unit(philox_word(pb, t->event, t->key, t->step, 0, 5, 0));
+    double ub = to_unit(philox_word(pb, t->event, t->key, t->step, 0, 5, 1));
+    double theta = theta0 * sqrt(-2.0 * log(ua));
+    double out[3];
+    rotate(t->u, cos(theta), 2.0 * ORC_PI * ub, out);
+    normalize(out);
+    t->u[0] = out[0]; t->u[1] = out[1]; t->u[2] = out[2];
+}
+
+/* test hook: deflect t (material mat, pre-step energy T_pre, step s) */
+void orc_msc_deflect(const orc_problem* pb, orc_track* t, int mat, double T_pre, double s)
+{
+    msc_deflect(pb, t, mat, T_pre, s);
+}
+
 void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
 {
     memset(res, 0, sizeof(*res));
@@ -691,6 +738,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
         return;
     }
 
+    const double T_pre = t->T;
     /* S1 */
     if (t->nl < 0.0) {
         t->nl = -log(draw(pb, t, &j));
@@ -742,6 +790,15 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
     }
     /* S7 */
     t->nl = t->nl - s * sig;
+    /* S7b: not for a track leaving the stack */
+    if (charged && pb->msc) {
+        int leaving = 0;
+        if (face != F_NONE) {
+            int next = face == F_ZLO ? t->slab - 1 : (face == F_ZHI ? t->slab + 1 : -1);
+            leaving = next < 0 || next >= pb->n_slabs;
+        }
+        if (!leaving) msc_deflect(pb, t, mat, T_pre, s);
+    }
 
     /* S8, S9 */
     if (face != F_NONE) {
