@@ -178,8 +178,7 @@ def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=No
         tuned = tune(s)
     for _ in range(args.warmup):
         time_batch(s, w.primaries, events)
-        for e in events:
-            s.release(int(e))
+        s.release(events)
     c0 = s.counters()
     total_t = 0.0
     iters = 0
@@ -189,8 +188,7 @@ def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=No
         total_t += dt
         iters += c["iterations"] - c_before["iterations"]
         if k + 1 < args.steps or prof_kernel:
-            for e in events:
-                s.release(int(e))
+            s.release(events)
     c1 = s.counters()
     prof = {}
     work_prof = {}

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 2u
+#define EMS_ABI_VERSION 3u
 
 typedef enum {
     EMS_OK = 0,
@@ -100,6 +100,10 @@ typedef struct {
     int32_t streams;           /* 1..4: independent kernels of an iteration (the along-step kernels;
                                   the interaction kernels) run as concurrent branches on up to this
                                   many default-priority streams created by the library */
+    int32_t msc;               /* 1: charged tracks still in the stack after an along-step are deflected
+                                  by multiple scattering: Rayleigh-distributed space angle of Highland
+                                  width at the pre-step energy, uniform azimuth (Philox domain 5);
+                                  0: no scattering (the physics of the benchmark workloads) */
 } ems_options;
 
 typedef struct { double Z, A, density, I_eV; } ems_material;
@@ -231,6 +235,10 @@ ems_status ems_read_all_tallies(ems_ctx* ctx, double* edep, ems_ledger* ledgers,
 
 /* Free the tally row of a finished event and zero it for reuse. */
 ems_status ems_release_event(ems_ctx* ctx, uint64_t event);
+
+/* Release n events at once (one clearing kernel).  Errors: INVALID_ARG for an
+ * unknown or repeated event id (nothing is released then). */
+ems_status ems_release_events(ems_ctx* ctx, const uint64_t* events, uint64_t n);
 
 /* ---- test hooks ---------------------------------------------------------- */
 

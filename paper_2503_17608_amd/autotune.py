@@ -46,8 +46,7 @@ def _run(session, primaries, events):
     session.run()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    for e in events:
-        session.release(int(e))
+    session.release(events)
     return dt
 
 

@@ -58,7 +58,7 @@ struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
-    uint64_t drain_stack, regs;
+    uint64_t drain_stack, regs, x0;
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads with a private stack)
     uint64_t total;
@@ -127,6 +127,7 @@ Layout make_layout(const ems_options& o)
     L.drain_threads = (uint32_t)std::min<uint64_t>(kDrainThreadsMax, align_up(n, 256));
     L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
     L.regs = take(sizeof(RowReg) * kStagingCap);
+    L.x0 = take(8ull * o.max_materials);
     L.total = off;
     return L;
 }
@@ -266,6 +267,8 @@ Dev<R> make_dev(const ems_ctx* c)
     d.tail_threshold = c->tail_threshold;
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
+    d.msc = c->opt.msc ? 1 : 0;
+    d.x0 = (const double*)(c->ws + c->L.x0);
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
 }
@@ -290,20 +293,6 @@ __global__ void k_reset_queue(Counters* c)
     c->overflow = 0;
 }
 
-__global__ void k_set_row(uint64_t* row_event, uint32_t row, uint64_t ev, double* edep, Ledger* led, uint32_t n_slabs,
-                          unsigned int* live, unsigned int* row_gen, unsigned int gen, unsigned int* row_state)
-{
-    // register an event on a row and clear the row's tallies
-    for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)row * n_slabs + i] = 0.0;
-    if (threadIdx.x == 0) {
-        row_event[row] = ev;
-        led[row] = Ledger{};
-        live[row] = 0u;
-        row_gen[row] = gen;
-        row_state[row] = ev != UINT64_MAX ? 1u : 0u;
-    }
-}
-
 // A batch of registrations {event, row, generation}: one block per row.
 __global__ void k_set_rows(const RowReg* regs, uint64_t* row_event, double* edep, Ledger* led, uint32_t n_slabs,
                            unsigned int* live, unsigned int* row_gen, unsigned int* row_state)
@@ -315,7 +304,7 @@ __global__ void k_set_rows(const RowReg* regs, uint64_t* row_event, double* edep
         led[g.row] = Ledger{};
         live[g.row] = 0u;
         row_gen[g.row] = g.gen;
-        row_state[g.row] = 1u;
+        row_state[g.row] = g.ev != UINT64_MAX ? 1u : 0u;
     }
 }
 
@@ -732,6 +721,7 @@ static ems_status validate(const ems_options* o)
     if (bs != 0 && (bs < 64 || bs > 512 || (bs % 64) != 0)) return fail(EMS_ERR_INVALID_ARG, "block_size");
     if (o->graph_iterations < 0) return fail(EMS_ERR_INVALID_ARG, "graph_iterations");
     if (o->streams < 0 || o->streams > 4) return fail(EMS_ERR_INVALID_ARG, "streams must be in [0, 4]");
+    if (o->msc != 0 && o->msc != 1) return fail(EMS_ERR_INVALID_ARG, "msc must be 0 or 1");
     return EMS_OK;
 }
 
@@ -836,6 +826,9 @@ ems_status ems_load_materials(ems_ctx* c, const ems_material* m, uint32_t n)
         md[i] = MatDev{m[i].Z, m[i].A, m[i].density, m[i].I_eV};
     }
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.mats, md.data(), sizeof(MatDev) * n, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_material_x0, dim3((n + 63) / 64), dim3(64), 0, c->stream,
+                       (const MatDev*)(c->ws + c->L.mats), (int)n, (double*)(c->ws + c->L.x0));
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->mats.assign(m, m + n);
     c->n_materials = n;
@@ -1162,24 +1155,29 @@ ems_status ems_read_all_tallies(ems_ctx* c, double* edep, ems_ledger* ledgers, u
     return EMS_OK;
 }
 
-ems_status ems_release_event(ems_ctx* c, uint64_t event)
+ems_status ems_release_events(ems_ctx* c, const uint64_t* events, uint64_t n)
 {
-    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
-    auto it = c->row_of.find(event);
-    if (it == c->row_of.end()) return fail(EMS_ERR_INVALID_ARG, "unknown event");
-    uint32_t row = it->second;
-    c->row_of.erase(it);
-    c->row_event[row] = UINT64_MAX;
-    c->row_pending[row] = 0;
-    c->row_gen[row] += 1;
-    hipLaunchKernelGGL(k_set_row, dim3(1), dim3(256), 0, c->stream, (uint64_t*)(c->ws + c->L.row_event), row,
-                       (uint64_t)UINT64_MAX, (double*)(c->ws + c->L.edep), (Ledger*)(c->ws + c->L.ledger),
-                       (uint32_t)c->opt.max_slabs, (unsigned int*)(c->ws + c->L.live),
-                       (unsigned int*)(c->ws + c->L.row_gen), c->row_gen[row], (unsigned int*)(c->ws + c->L.row_state));
-    HIP_TRY(hipGetLastError());
-    c->free_rows.push_back(row);
-    return EMS_OK;
+    if (!c || (!events && n)) return fail(EMS_ERR_INVALID_ARG, "null");
+    // validate all first: nothing is released on error
+    std::unordered_map<uint64_t, int> seen;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (c->row_of.find(events[i]) == c->row_of.end()) return fail(EMS_ERR_INVALID_ARG, "unknown event");
+        if (!seen.emplace(events[i], 1).second) return fail(EMS_ERR_INVALID_ARG, "event listed twice");
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        auto it = c->row_of.find(events[i]);
+        uint32_t row = it->second;
+        c->row_of.erase(it);
+        c->row_event[row] = UINT64_MAX;
+        c->row_pending[row] = 0;
+        c->row_gen[row] += 1;
+        c->reg_pending.push_back(RowReg{UINT64_MAX, row, c->row_gen[row]});
+        c->free_rows.push_back(row);
+    }
+    return flush_rows(c);
 }
+
+ems_status ems_release_event(ems_ctx* c, uint64_t event) { return ems_release_events(c, &event, 1); }
 
 // ---------------------------------------------------------------- test hooks
 ems_status ems_debug_register_event(ems_ctx* c, uint64_t event, uint32_t* row)

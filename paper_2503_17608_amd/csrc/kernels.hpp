@@ -74,6 +74,8 @@ struct Dev {
     unsigned int tail_threshold;  // below this many live tracks an iteration runs masked (no reordering)
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
+    int msc;                // multiple-scattering deflection after charged along-steps
+    const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
 
@@ -559,6 +561,34 @@ __device__ __forceinline__ double straight_distance(const double r[3], const dou
     return dd;
 }
 
+// Multiple scattering (optional): a charged track still in the stack after
+// its along-step of length s is deflected by a space angle theta0 sqrt(-2 ln
+// U_a), azimuth 2 pi U_b, where theta0 is the Highland width of the
+// projected angle (PDG review, multiple scattering through small angles),
+//     theta0 = 13.6 MeV / (beta c p) sqrt(x) (1 + 0.038 ln(x / beta^2)),
+// x = s / X0, at the pre-step energy; no deflection for s = 0 or a
+// non-positive bracket.  U_a, U_b: words 0 and 1 of the Philox block at
+// counter (key, step, 0, 5).  Computed in FP64 in both precisions.
+__device__ __forceinline__ void msc_deflect(uint64_t seed, uint64_t event, uint64_t key, uint32_t step, double T_pre,
+                                            double s, double X0, double u[3])
+{
+    if (!(s > 0.0)) return;
+    const double p = sqrt(T_pre * (T_pre + 2.0 * kMe));
+    const double beta = p / (T_pre + kMe);
+    const double x = s / X0;
+    const double bracket = 1.0 + 0.038 * log(x / (beta * beta));
+    if (!(bracket > 0.0)) return;
+    const double theta0 = 13.6 / (beta * p) * sqrt(x) * bracket;
+    const U64x4 w = philox4x64_10(key, (uint64_t)step, 0, 5, seed, event);
+    const double theta = theta0 * sqrt(-2.0 * log(unit_from<double>(w.w[0])));
+    double sp, cp;
+    sincos(2.0 * kPi * unit_from<double>(w.w[1]), &sp, &cp);
+    double out[3];
+    rotate<double>(u, cos(theta), sp, cp, out);
+    normalize3<double>(out);
+    u[0] = out[0]; u[1] = out[1]; u[2] = out[2];
+}
+
 // Common end of an along-step (S6-S8) for a step of length s.  Returns true
 // when the track remains alive; sets the next action.
 template <class R, bool CHARGED>
@@ -682,9 +712,15 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     PhysParams pp = {d.seed, d.row_event[row], d.ecut};
     bool alive = true;
     uint8_t na = A_IDLE;
+    const uint32_t k0 = d.step[s];
+    const double T_pre = (double)T;
     finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
     record_tally(d, row, slab0, tl);
     d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+    if (CHARGED && d.msc && alive) {
+        msc_deflect(d.seed, pp.event, d.key[s], k0, T_pre, st, d.x0[mat], ud);
+        d.ux[s] = (R)ud[0]; d.uy[s] = (R)ud[1]; d.uz[s] = (R)ud[2];
+    }
     if (alive) {
         d.T[s] = T;
         d.nl[s] = nl;
@@ -897,8 +933,13 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
         PhysParams pp = {d.seed, d.row_event[row], d.ecut};
         bool alive = true;
         uint8_t na = A_IDLE;
+        const uint32_t k0 = d.step[s];
         finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
         record_tally(d, row, slab0, tl);
+        if (d.msc && alive) {
+            msc_deflect(d.seed, pp.event, d.key[s], k0, Td, s_done, d.x0[mat], u);
+            d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
+        }
         if (alive) {
             d.T[s] = T;
             d.nl[s] = nl;

@@ -119,6 +119,13 @@ __device__ double d_stopping(double T, double Ec, const MatDev& m, bool positron
     return d_scol(T, Ec, m, positron) + d_srad(T, Ec, x0_cm(m));
 }
 
+// radiation length of every material, for the multiple-scattering width
+__global__ void k_material_x0(const MatDev* mats, int n_mat, double* x0)
+{
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n_mat) x0[m] = x0_cm(mats[m]);
+}
+
 __global__ void k_build_xs(const MatDev* mats, int n_mat, double ecut, double ln_e0, double dlog, double* out)
 {
     int id = blockIdx.x * blockDim.x + threadIdx.x;

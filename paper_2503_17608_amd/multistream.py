@@ -48,12 +48,12 @@ def run_event_parallel(sessions, primaries, chunk_events=64, keep_results=True):
                 ev = np.array([e for e, _ in chunk], dtype=np.uint64)
                 s.push(np.concatenate([p for _, p in chunk]))
                 s.run()
-                e, led = s.tallies_by_event(ev)
-                for i, x in enumerate(ev):
-                    if keep_results:
+                if keep_results:
+                    e, led = s.tallies_by_event(ev)
+                    for i, x in enumerate(ev):
                         edep[int(x)] = e[i]
                         ledger[int(x)] = led[i]
-                    s.release(int(x))
+                s.release(ev)
         except Exception as exc:          # surfaced to the caller below
             errors.append(exc)
         steps[k] = s.counters()["steps"] - c0

@@ -75,12 +75,12 @@ def test_sort_permutation_bit_exact(n, policy, nb):
 
 
 # ----------------------------------------------------------------------------- one step
-def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0):
+def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc=False):
     rng = np.random.default_rng(seed)
     f32 = precision == "mixed"
     states = random_states(w, n, rng, types=types, e_max=e_max, f32=f32)
     s = session_for(w, n_slots=n, precision=precision, max_events=n, max_substeps=0,
-                    n_initializers=4 * n)
+                    n_initializers=4 * n, msc=msc)
     rows = np.array([s.register_event(int(e)) for e in states["event"]], dtype=np.uint32)
     s.inject(to_lib_tracks(states, rows))
     s.iterate(1, no_init=True)
@@ -89,7 +89,7 @@ def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0):
     edep, led, ev = s.read_all()
     s.close()
 
-    pb = oracle.problem_for(w)
+    pb = oracle.problem_for(w, msc=msc)
     ref_t = states.copy()
     res = pb.step(ref_t)
 
@@ -282,3 +282,38 @@ def test_drain_mode_matches_step_loop_and_oracle(precision):
         assert _ledger_equal_int(led, ref_l) is None, (tag, _ledger_equal_int(led, ref_l))
         scale = np.abs(ref_e).max(1, keepdims=True)
         assert np.all(np.abs(edep - ref_e) <= 1e-12 * scale + 1e-300), tag
+
+
+@pytest.mark.parametrize("precision,wl", [("f64", "nofield"), ("f64", "field"), ("mixed", "nofield"),
+                                          ("mixed", "field")])
+def test_single_step_parity_with_multiple_scattering(precision, wl):
+    w = workloads.small_electron_showers(1) if wl == "nofield" else workloads.electron_showers_1gev_field(1)
+    n = 20000
+    tol = 1e-12 if precision == "f64" else 1e-5
+    bad, worst = _step_compare(w, n, precision, seed=23, tol=tol, types=(1, 2), msc=True)
+    print("worst", worst, "mismatches", len(bad), bad[:5])
+    if precision == "f64":
+        assert not bad, bad[:10]
+    else:
+        assert len(bad) <= max(3, int(2e-3 * n)), bad[:10]
+
+
+def test_showers_with_multiple_scattering_match_oracle():
+    w = workloads.electron_showers_1gev_field(30, n_slots=1 << 15)
+    pb = oracle.problem_for(w, msc=True)
+    tr, rows = oracle.tracks_from_primaries(w.primaries)
+    e_ref, l_ref, steps = pb.run_events(tr, rows, w.n_events, 8)
+    e_off, _, steps_off = _run_oracle(w)
+    assert steps != steps_off
+    for policy, drain in (("partition", 0), ("none", 0), ("partition", 65536)):
+        s = session_for(w, sort_policy=policy, graph_iterations=4, msc=True)
+        if drain:
+            s.set_tuning(drain_threshold=drain)
+        s.push(w.primaries)
+        c = s.run()
+        edep, led = s.tallies_by_event(np.arange(w.n_events))
+        s.close()
+        assert c["steps"] == steps, (policy, drain, c["steps"], steps)
+        assert _ledger_equal_int(led, l_ref) is None, (policy, drain)
+        rel = np.abs(edep - e_ref).max(1) / w.primaries["T"]
+        assert rel.max() < 1e-7 and np.count_nonzero(rel > 1e-9) <= 1, (policy, drain, np.sort(rel)[-3:])
