@@ -9,8 +9,9 @@ region of each step; the timed region covers the device loop only.
 Default workload: 10^4 electrons of 1 GeV into a 50-layer Pb (2 mm) / liquid
 Ar (5 mm) stack, 40 x 40 cm, uniform 1 T field along x, 0.1 MeV cut, 2^20
 track slots, FP64, slots sorted by next action, iterations replayed from
-captured HIP graphs, the last tracks (below 65536 alive, queued or pending)
-stepped in history mode by the drain kernel.
+captured HIP graphs, the six interaction kernels fused into one launch, the
+last tracks (below 65536 alive, queued or pending) stepped in history mode by
+the drain kernel.
 
 The JSON line carries the dominant kernel's roofline: algorithmic bytes per
 launch (the kernel's work counter times its per-track field traffic) divided
@@ -118,6 +119,7 @@ def parse():
                     help="run the last tracks in history mode below this many live+queued+pending (0 = off)")
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
+    ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the six interaction kernels")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=4000, help="oracle sample (events); 0 = skip")
@@ -144,7 +146,7 @@ def make_workload(name, events, slots):
     return w
 
 
-def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None):
+def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
     s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
@@ -155,8 +157,10 @@ def new_session(w, args, precision, policy, init_partition, graph=None, drain=No
     s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
     drain = args.drain_threshold if drain is None else drain
     reuse = args.reuse_parent_slot if reuse is None else reuse
-    if drain > 0 or reuse:
-        s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse))
+    fuse = args.fuse_interactions if fuse is None else fuse
+    if drain > 0 or reuse or fuse:
+        s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse),
+                     fuse_interactions=bool(fuse))
     return s
 
 
@@ -170,8 +174,8 @@ def time_batch(s, primaries, events):
     return c, time.perf_counter() - t0
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None):
-    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse)
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None):
+    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse)
     events = np.unique(w.primaries["event"])
     tuned = None
     if tune is not None:
@@ -376,13 +380,14 @@ def main():
                    "max_substeps": args.max_substeps, "graph_iterations": args.graph,
                    "lds_tables": args.lds_tables, "streams": args.streams,
                    "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
-                   "reuse_parent_slot": args.reuse_parent_slot,
+                   "reuse_parent_slot": args.reuse_parent_slot, "fuse_interactions": args.fuse_interactions,
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
     }
     if r["tuned"] is not None:
-        out["config"]["autotuned"] = {k: r["tuned"][k] for k in ("sort_policy", "tail_threshold", "block")}
+        out["config"]["autotuned"] = {k: r["tuned"][k] for k in ("sort_policy", "tail_threshold", "block",
+                                                                 "fuse_interactions", "drain_threshold")}
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
         tracks = r["work_prof"][prof_kernel]
@@ -392,7 +397,8 @@ def main():
         achieved = per_launch / avg_s / 1e9
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
-               "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot}
+               "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot,
+               "fuse_interactions": args.fuse_interactions}
         t = committed_traffic(prof_kernel, key)
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -415,6 +421,11 @@ def main():
                 continue
             rv = run_variant(w, args, precision, pol, part, None, drain=dr, reuse=ru)
             tag = f"{pol}+part{part}" + ("+nodrain" if dr == 0 else "") + ("+reuse" if ru else "")
+            var[tag] = rv["steps"] / rv["seconds"]
+        for pol in ("partition", "radix", "none"):
+            fu = 0 if args.fuse_interactions else 1
+            rv = run_variant(w, args, precision, pol, 0, None, fuse=fu)
+            tag = f"{pol}+part0" + ("+fused" if fu else "+unfused")
             var[tag] = rv["steps"] / rv["seconds"]
         for k in (4, 8):
             var[f"event_parallel_{k}x{w.n_slots // k}"] = event_parallel_rate(w, args, precision, k)

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 3u
+#define EMS_ABI_VERSION 4u
 
 typedef enum {
     EMS_OK = 0,
@@ -270,7 +270,7 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * block[i] is the block size of kernel role i (role order as returned by
  * ems_profile_read: vacancies, init, pre_step, sort, along_neutral,
  * along_charged, along_field, compton, photoelectric, pair, moller, bhabha,
- * bremsstrahlung, drain); 0 keeps ems_options.block_size.  Below
+ * bremsstrahlung, drain, interactions); 0 keeps ems_options.block_size.  Below
  * tail_threshold live tracks an iteration skips the reordering and runs
  * masked (the device decides per iteration).
  *
@@ -286,6 +286,11 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * first secondary directly, instead of through the initializer buffer and the
  * next iteration's fill (fewer initializer round trips; it mixes charged and
  * neutral tracks in slots that init_partition would keep apart).
+ *
+ * fuse_interactions (0/1): run the six interaction kernels as one launch that
+ * walks the combined index range of the interaction actions (each wave holds
+ * one process except at range boundaries) instead of six launches on the
+ * library's streams; kernel role "interactions" in the block table.
  * Setting the tuning re-captures graphs on the next run. */
 typedef struct {
     int32_t sort_policy;
@@ -294,6 +299,7 @@ typedef struct {
     uint32_t drain_threshold;
     uint32_t drain_steps;
     uint32_t reuse_parent_slot;
+    uint32_t fuse_interactions;
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

@@ -9,7 +9,9 @@ tuner may try them on a sample of the real workload:
    role then keeps the size that minimised its own total time;
 2. sort policy: none / partition / radix / queue, timed end to end;
 3. tail threshold: the live-track count below which an iteration skips the
-   reordering and runs masked (the "per step phase" choice), timed end to end.
+   reordering and runs masked (the "per step phase" choice), timed end to end;
+4. fused or per-process interaction kernels, and the drain threshold below
+   which the last tracks run in history mode, timed end to end.
 
 Results can be cached in a JSON file keyed by a workload signature.
 """
@@ -26,7 +28,7 @@ from . import emstep
 
 BLOCK_CANDIDATES = (64, 128, 256, 512)
 STEP_ROLES = ("pre_step", "along_neutral", "along_charged", "along_field", "compton", "photoelectric", "pair",
-              "moller", "bhabha", "bremsstrahlung")
+              "moller", "bhabha", "bremsstrahlung", "interactions")
 
 
 def signature(n_slots, precision, stack, ecut, primaries):
@@ -52,14 +54,16 @@ def _run(session, primaries, events):
 
 def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
              thresholds=(0, 2048, 16384, 131072), blocks=BLOCK_CANDIDATES, repeats=1, cache=None, key=None,
-             log=None):
+             log=None, drains=(0, 16384, 65536)):
     """Tune `session` (an emstep.Session with geometry and tables loaded) on
     the primaries `sample`; applies and returns the chosen tuning."""
     if cache and key and os.path.exists(cache):
         db = json.load(open(cache))
         if key in db:
             t = db[key]
-            session.set_tuning(sort_policy=t["sort_policy"], tail_threshold=t["tail_threshold"], block=t["block"])
+            session.set_tuning(sort_policy=t["sort_policy"], tail_threshold=t["tail_threshold"], block=t["block"],
+                               fuse_interactions=t.get("fuse_interactions", False),
+                               drain_threshold=t.get("drain_threshold", 0))
             return t
     events = np.unique(sample["event"])
     say = log or (lambda *a: None)
@@ -100,8 +104,25 @@ def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
         best_th = 0
     say("thresholds", th_t)
     session.set_tuning(sort_policy=best_policy, tail_threshold=best_th, block=best_block)
+    # 4. interaction kernels fused or not, then the drain threshold
+    fuse_t = {}
+    for f in (False, True):
+        session.set_tuning(fuse_interactions=f, drain_threshold=0)
+        fuse_t[f] = min(_run(session, sample, events) for _ in range(repeats))
+    best_fuse = min(fuse_t, key=fuse_t.get)
+    drain_t = {}
+    for dth in drains:
+        session.set_tuning(fuse_interactions=best_fuse, drain_threshold=dth)
+        drain_t[dth] = min(_run(session, sample, events) for _ in range(repeats))
+    best_drain = min(drain_t, key=drain_t.get)
+    say("fuse", fuse_t, "drain", drain_t)
+    session.set_tuning(sort_policy=best_policy, tail_threshold=best_th, block=best_block,
+                       fuse_interactions=best_fuse, drain_threshold=best_drain)
     result = {"sort_policy": best_policy, "tail_threshold": int(best_th), "block": best_block,
+              "fuse_interactions": bool(best_fuse), "drain_threshold": int(best_drain),
               "policy_seconds": pol_t, "threshold_seconds": {str(k): v for k, v in th_t.items()},
+              "fuse_seconds": {str(k): v for k, v in fuse_t.items()},
+              "drain_seconds": {str(k): v for k, v in drain_t.items()},
               "block_ms": {r: {str(b): v for b, v in d.items()} for r, d in per_role.items()}}
     if cache and key:
         db = json.load(open(cache)) if os.path.exists(cache) else {}

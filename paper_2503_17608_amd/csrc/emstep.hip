@@ -134,11 +134,11 @@ Layout make_layout(const ems_options& o)
 
 enum Role {
     R_VAC = 0, R_INIT, R_PRE, R_SORT, R_ALONG_NEUTRAL, R_ALONG_CHARGED, R_ALONG_FIELD,
-    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_DRAIN, R_NUM
+    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_DRAIN, R_INTERACT_ALL, R_NUM
 };
 const char* kRoleNames[R_NUM] = {"vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged",
                                  "along_field", "compton", "photoelectric", "pair", "moller", "bhabha",
-                                 "bremsstrahlung", "drain"};
+                                 "bremsstrahlung", "drain", "interactions"};
 
 }  // namespace
 
@@ -190,6 +190,7 @@ struct ems_ctx {
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
     uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
+    uint32_t fuse_interactions = 0;   // one launch for the six interaction kernels
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -474,6 +475,12 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
                st, d);
     if (nw > 0) join(c, 0, 1);
     if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
+    if (c->fuse_interactions) {
+        // all six processes in one launch over the combined index range
+        ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
+        hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
+        return;
+    }
     // interactions: six independent branches spread over the streams
     if (nw > 0) fork(c, 1, nw);
     auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
@@ -1317,6 +1324,7 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
     c->drain_threshold = t->drain_threshold;
     c->drain_steps = t->drain_steps;
     c->reuse_parent = t->reuse_parent_slot ? 1u : 0u;
+    c->fuse_interactions = t->fuse_interactions ? 1u : 0u;
     for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
     return drop_graph(c);
 }
@@ -1329,6 +1337,7 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     t->drain_threshold = c->drain_threshold;
     t->drain_steps = c->drain_steps;
     t->reuse_parent_slot = c->reuse_parent;
+    t->fuse_interactions = c->fuse_interactions;
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }

@@ -1062,6 +1062,80 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     flush_count(d, W_REUSE, reuse_acc);
 }
 
+// ---- discrete interactions, all six processes in one launch ------------------------
+// After the reordering at sort point 2 the six interaction actions occupy
+// consecutive index ranges of the permutation (or six lists), so one launch
+// can walk all of them: each wave then holds one process except at the few
+// range boundaries.  The per-track code is that of the per-process kernels;
+// the launch count per iteration drops from six to one.  Unsorted, it masks
+// over all slots like the per-process kernels.
+template <class R>
+__global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
+{
+    const int mode = d.ctr->phase_sorted ? d.sorted2 : 0;
+    uint32_t n = d.n_slots, off = 0;
+    uint32_t lc0 = 0, lc1 = 0, lc2 = 0, lc3 = 0, lc4 = 0;
+    if (mode == 1) {
+        off = d.ctr->range_off[A_PROC0];
+        n = d.ctr->range_off[A_PROC0 + 5] + d.ctr->range_cnt[A_PROC0 + 5] - off;
+    } else if (mode == 2) {
+        lc0 = d.ctr->list_cnt[A_PROC0];
+        lc1 = lc0 + d.ctr->list_cnt[A_PROC0 + 1];
+        lc2 = lc1 + d.ctr->list_cnt[A_PROC0 + 2];
+        lc3 = lc2 + d.ctr->list_cnt[A_PROC0 + 3];
+        lc4 = lc3 + d.ctr->list_cnt[A_PROC0 + 4];
+        n = lc4 + d.ctr->list_cnt[A_PROC0 + 5];
+    }
+    if (blockIdx.x * blockDim.x >= n) return;
+    unsigned long long w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, ret_acc = 0, reuse_acc = 0;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        bool act = i < n;
+        uint32_t s = 0;
+        if (act) {
+            if (mode == 1) {
+                s = d.perm[off + i];
+            } else if (mode == 2) {
+                int p = i < lc0 ? 0 : (i < lc1 ? 1 : (i < lc2 ? 2 : (i < lc3 ? 3 : (i < lc4 ? 4 : 5))));
+                uint32_t lo = p == 0 ? 0u : (p == 1 ? lc0 : (p == 2 ? lc1 : (p == 3 ? lc2 : (p == 4 ? lc3 : lc4))));
+                s = d.lists[(size_t)(A_PROC0 + p) * d.n_slots + (i - lo)];
+            } else {
+                s = i;
+            }
+        }
+        const uint8_t a = act ? d.action[s] : (uint8_t)A_NONE;
+        act = act && a >= A_PROC0 && a < A_PROC0 + 6;
+        SecBuf<R> sb;
+        sb.n = 0;
+        double r[3] = {0.0, 0.0, 0.0};
+        uint32_t row = 0;
+        uint16_t slab = 0;
+        uint32_t retired = 0;
+        if (act) {
+            switch (a - A_PROC0) {
+            case P_COMPTON: interact_track<R, P_COMPTON>(d, s, sb, r, row, slab, retired); ++w0; break;
+            case P_PHOTO:   interact_track<R, P_PHOTO>(d, s, sb, r, row, slab, retired); ++w1; break;
+            case P_PAIR:    interact_track<R, P_PAIR>(d, s, sb, r, row, slab, retired); ++w2; break;
+            case P_MOLLER:  interact_track<R, P_MOLLER>(d, s, sb, r, row, slab, retired); ++w3; break;
+            case P_BHABHA:  interact_track<R, P_BHABHA>(d, s, sb, r, row, slab, retired); ++w4; break;
+            default:        interact_track<R, P_BREMS>(d, s, sb, r, row, slab, retired); ++w5; break;
+            }
+        }
+        if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
+        append_secondaries(d, sb, row, slab, r);
+        leave_event(d, retired != 0, row);
+        ret_acc += retired;
+    }
+    flush_count(d, W_PROC0 + P_COMPTON, w0);
+    flush_count(d, W_PROC0 + P_PHOTO, w1);
+    flush_count(d, W_PROC0 + P_PAIR, w2);
+    flush_count(d, W_PROC0 + P_MOLLER, w3);
+    flush_count(d, W_PROC0 + P_BHABHA, w4);
+    flush_count(d, W_PROC0 + P_BREMS, w5);
+    flush_count(d, kStepsSlot + W_PROC0, ret_acc);
+    flush_count(d, W_REUSE, reuse_acc);
+}
+
 // ---- drain: history-mode stepping of the last tracks ---------------------------------
 // When few tracks are left the step loop is bound by per-iteration launch
 // latency, not by work.  In a drain launch each thread takes one live slot and

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 FP64, MIXED = 0, 1
 SORT_NONE, SORT_PARTITION, SORT_RADIX, SORT_QUEUE = 0, 1, 2, 3
 SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX, "queue": SORT_QUEUE}
@@ -51,7 +51,8 @@ class Material(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16),
-                ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32), ("reuse_parent_slot", C.c_uint32)]
+                ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32), ("reuse_parent_slot", C.c_uint32),
+                ("fuse_interactions", C.c_uint32)]
 
 
 class Counters(C.Structure):
@@ -320,11 +321,11 @@ class Session:
         _check(_lib.ems_get_tuning(self._h, C.byref(t)), "ems_get_tuning")
         return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
                 "drain_threshold": t.drain_threshold, "drain_steps": t.drain_steps,
-                "reuse_parent_slot": bool(t.reuse_parent_slot),
+                "reuse_parent_slot": bool(t.reuse_parent_slot), "fuse_interactions": bool(t.fuse_interactions),
                 "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
 
     def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None,
-                   reuse_parent_slot=None):
+                   reuse_parent_slot=None, fuse_interactions=None):
         """Change knobs that affect speed only; block maps kernel role names to block sizes."""
         cur = Tuning()
         _check(_lib.ems_get_tuning(self._h, C.byref(cur)), "ems_get_tuning")
@@ -338,6 +339,8 @@ class Session:
             cur.drain_steps = int(drain_steps)
         if reuse_parent_slot is not None:
             cur.reuse_parent_slot = 1 if reuse_parent_slot else 0
+        if fuse_interactions is not None:
+            cur.fuse_interactions = 1 if fuse_interactions else 0
         if block is not None:
             for name, b in block.items():
                 cur.block[KERNEL_ROLES.index(name)] = int(b)
@@ -357,7 +360,7 @@ class Session:
 
 
 KERNEL_ROLES = ["vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged", "along_field",
-                "compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "drain"]
+                "compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "drain", "interactions"]
 
 
 def role_mask(*names):

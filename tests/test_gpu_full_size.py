@@ -1,12 +1,12 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
 configuration the benchmark times (partition policy, 8-iteration graph
-batches, LDS-staged tables, four streams, substep cap 10), plus degenerate
-and rejected inputs.
+batches, LDS-staged tables, four streams, substep cap 10, fused interaction
+kernel, drain below 65536 tracks), plus degenerate and rejected inputs.
 
 * 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event against
   the FP64 oracle (integer ledger equal, deposits to 1e-9 of the primary
-  energy), for the sort policies none / partition / radix / queue and with
-  parent-slot reuse and the drain of the last tracks;
+  energy), for the sort policies none / partition / radix / queue, with
+  parent-slot reuse, and with the six interaction kernels and no drain;
 * 10^4 mixed primaries in a 5 degree cone at 2^20 slots: FP64 per event
   against the oracle, and the mixed-precision run's per-layer mean deposit
   within 0.5 % of the FP64 oracle;
@@ -27,14 +27,16 @@ pytestmark = pytest.mark.gpu
 
 ME = 0.51099895
 BENCH = dict(sort_policy="partition", graph_iterations=8, lds_tables=1, streams=4, max_substeps=10)
+BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True)
 
 
 def _run(w, events=None, tuning=None, **kw):
     opts = dict(BENCH)
     opts.update(kw)
     s = session_for(w, **opts)
-    if tuning:
-        s.set_tuning(**tuning)
+    t = dict(BENCH_TUNING)
+    t.update(tuning or {})
+    s.set_tuning(**t)
     s.push(w.primaries)
     c = s.run(max_iterations=1_000_000)
     ev = np.arange(w.n_events) if events is None else np.asarray(events)
@@ -76,11 +78,13 @@ def test_full_size_electron_showers_every_policy():
     w = workloads.electron_showers_1gev_field()
     assert w.n_events == 10_000 and w.n_slots == 1 << 20
     e_ref, l_ref, steps = run_oracle(w)
-    for policy in ("partition", "none", "radix", "queue", "partition+reuse+drain"):
-        if policy == "partition+reuse+drain":
-            edep, led, c = _run(w, sort_policy="partition", tuning=dict(reuse_parent_slot=True,
-                                                                        drain_threshold=65536))
+    for policy in ("partition", "none", "radix", "queue", "partition+reuse", "partition+unfused+nodrain"):
+        if policy == "partition+reuse":
+            edep, led, c = _run(w, sort_policy="partition", tuning=dict(reuse_parent_slot=True))
             assert c["work"]["reused_slots"] > 0 and c["work"]["drain"] > 0
+        elif policy == "partition+unfused+nodrain":
+            edep, led, c = _run(w, sort_policy="partition", tuning=dict(fuse_interactions=False, drain_threshold=0))
+            assert c["work"]["drain"] == 0
         else:
             edep, led, c = _run(w, sort_policy=policy)
         assert c["overflow"] == 0, policy
@@ -118,6 +122,7 @@ def test_full_size_batched_events_sampled():
     assert w.n_events == 64 and w.n_slots == 1 << 22
     sample = np.array([0, 9, 17, 30, 41, 63])
     s = session_for(w, **BENCH)
+    s.set_tuning(**BENCH_TUNING)
     s.push(w.primaries)
     c = s.run(max_iterations=1_000_000)
     edep_all, led_all = s.tallies_by_event(np.arange(w.n_events))

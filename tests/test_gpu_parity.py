@@ -243,7 +243,11 @@ def test_tuning_does_not_change_results():
                    dict(sort_policy="queue", tail_threshold=0, block={"along_neutral": 128, "compton": 448}),
                    dict(sort_policy="none", tail_threshold=100000, block={"bremsstrahlung": 64}),
                    dict(sort_policy="partition", tail_threshold=0, reuse_parent_slot=True),
-                   dict(sort_policy="queue", reuse_parent_slot=True, drain_threshold=3000, drain_steps=50)]:
+                   dict(sort_policy="queue", reuse_parent_slot=True, drain_threshold=3000, drain_steps=50),
+                   dict(sort_policy="partition", reuse_parent_slot=False, fuse_interactions=True),
+                   dict(sort_policy="queue", fuse_interactions=True, drain_threshold=0),
+                   dict(sort_policy="none", fuse_interactions=True, block={"interactions": 128}),
+                   dict(sort_policy="radix", tail_threshold=2000, fuse_interactions=True, reuse_parent_slot=True)]:
         s.set_tuning(**tuning)
         s.push(w.primaries)
         c = s.run()
