@@ -114,7 +114,7 @@ def parse():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--graph", type=int, default=8, help="iterations per captured HIP graph (0 = plain launches)")
     ap.add_argument("--lds-tables", type=int, default=1)
-    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--drain-threshold", type=int, default=65536,
                     help="run the last tracks in history mode below this many live+queued+pending (0 = off)")
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
@@ -129,6 +129,8 @@ def parse():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-events", type=int, default=1000)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate / closed-batch event rate")
+    ap.add_argument("--extra-loads", type=float, nargs="*", default=[0.5, 0.9],
+                    help="further loads served (same arrival seed) after the main one")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size three times (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -301,33 +303,46 @@ def serve_mode(args):
     # closed-batch event rate on a sample, to set the arrival rate
     n_cal = min(64, len(events))
     cal = np.concatenate([p for _, p in events[:n_cal]])
+    cal_ev = np.array([e for e, _ in events[:n_cal]], dtype=np.uint64)
     s = new_session(w, args, precision, args.policy, args.init_partition)
-    time_batch(s, cal, [e for e, _ in events[:n_cal]])
-    for e, _ in events[:n_cal]:
-        s.release(e)
-    _, dt_cal = time_batch(s, cal, [e for e, _ in events[:n_cal]])
-    for e, _ in events[:n_cal]:
-        s.release(e)
-    rate = args.load * n_cal / dt_cal
-    arrivals = workloads.poisson_arrival_times(w.seed, rate, len(events))
-    torch.cuda.synchronize()
-    res = serving.serve(s, events, arrivals, track_budget=w.n_slots, iterations_per_poll=max(args.graph, 1),
-                        keep_results=False)
+    time_batch(s, cal, cal_ev)
+    s.release(cal_ev)
+    _, dt_cal = time_batch(s, cal, cal_ev)
+    s.release(cal_ev)
+    batch_rate = n_cal / dt_cal
+
+    def one(sess, load):
+        arrivals = workloads.poisson_arrival_times(w.seed, load * batch_rate, len(events))
+        torch.cuda.synchronize()
+        res = serving.serve(sess, events, arrivals, track_budget=w.n_slots, iterations_per_poll=max(args.graph, 1),
+                            keep_results=False)
+        return {"load": load, "arrival_rate_hz": load * batch_rate,
+                "value": res.steps / res.wall_s, "unit": "track-steps/s",
+                "latency_ms": {"p50": 1e3 * res.percentile(50), "p99": 1e3 * res.percentile(99),
+                               "max": 1e3 * max(res.latency_s.values())},
+                "serve_wall_s": res.wall_s, "max_events_in_flight": res.max_in_flight,
+                "iterations": res.iterations, "ms_per_iteration": 1e3 * res.wall_s / max(res.iterations, 1)}
+
+    main_run = one(s, args.load)
+    runs = {precision: [main_run]}
+    for load in args.extra_loads:
+        runs[precision].append(one(s, load))
     s.close()
-    # plain FP64 batch stepping of the same events
+    # the same arrivals served in plain FP64
     s64 = new_session(w, args, "f64", args.policy, args.init_partition)
+    runs["f64"] = [one(s64, load) for load in [args.load] + list(args.extra_loads)]
+    # plain FP64 batch stepping of the same events
     c64, dt64 = time_batch(s64, w.primaries, [e for e, _ in events])
     s64.close()
     out = {
         "metric": "event latency p50/p99 and track-steps/s, continuous batching",
-        "value": res.steps / res.wall_s, "unit": "track-steps/s", "n_gpus": 1,
+        "value": main_run["value"], "unit": "track-steps/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32+f64" if precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "events": len(events), "primaries": int(len(w.primaries)),
-                   "n_slots": w.n_slots, "arrival_rate_hz": rate, "load": args.load,
+                   "n_slots": w.n_slots, "closed_batch_event_rate_hz": batch_rate, "load": args.load,
                    "sort_policy": args.policy, "graph_iterations": args.graph},
-        "latency_ms": {"p50": 1e3 * res.percentile(50), "p99": 1e3 * res.percentile(99),
-                       "max": 1e3 * max(res.latency_s.values())},
-        "serve_wall_s": res.wall_s, "max_events_in_flight": res.max_in_flight,
+        "latency_ms": main_run["latency_ms"],
+        "runs": runs,
         "fp64_batch": {"value": c64["steps"] / dt64, "unit": "track-steps/s", "seconds": dt64},
     }
     print(json.dumps(out), flush=True)
