@@ -332,8 +332,10 @@ def serve_mode(args):
     s64 = new_session(w, args, "f64", args.policy, args.init_partition)
     runs["f64"] = [one(s64, load) for load in [args.load] + list(args.extra_loads)]
     # plain FP64 batch stepping of the same events
+    steps0 = s64.counters()["steps"]
     c64, dt64 = time_batch(s64, w.primaries, [e for e, _ in events])
     s64.close()
+    steps64 = c64["steps"] - steps0
     out = {
         "metric": "event latency p50/p99 and track-steps/s, continuous batching",
         "value": main_run["value"], "unit": "track-steps/s", "n_gpus": 1,
@@ -343,7 +345,7 @@ def serve_mode(args):
                    "sort_policy": args.policy, "graph_iterations": args.graph},
         "latency_ms": main_run["latency_ms"],
         "runs": runs,
-        "fp64_batch": {"value": c64["steps"] / dt64, "unit": "track-steps/s", "seconds": dt64},
+        "fp64_batch": {"value": steps64 / dt64, "unit": "track-steps/s", "seconds": dt64},
     }
     print(json.dumps(out), flush=True)
 

@@ -380,19 +380,16 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
     }
     __syncthreads();
     unsigned long long pos = bbase + wtot[w] + (unsigned long long)(x - n);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (k >= n) break;
-        const Sec<R> v = sb.get(k);
+    sb.each([&](const Sec<R>& v, int k) {
         unsigned long long q = pos + (unsigned long long)k;
         if (q >= d.queue_cap) {
             atomicOr(&d.ctr->overflow, 1u);
-            continue;
+            return;
         }
         Initializer rec;
         rec.T = (double)v.T;
         rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
-        rec.u[0] = (double)v.u[0]; rec.u[1] = (double)v.u[1]; rec.u[2] = (double)v.u[2];
+        rec.u[0] = (double)v.ux; rec.u[1] = (double)v.uy; rec.u[2] = (double)v.uz;
         rec.key = v.key;
         rec.row = row;
         rec.slab = slab;
@@ -401,7 +398,7 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
         d.queue[q] = rec;
         atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
         atomicAdd(&d.live[row], 1u);
-    }
+    });
     __syncthreads();                                  // wtot / bbase are reused by the next trip
 }
 
@@ -433,11 +430,11 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
                                                uint16_t slab, const double r[3])
 {
     if (!d.reuse_parent || sb.n == 0) return 0u;
-    const Sec<R> v = sb.get(0);
+    const Sec<R> v = sb.s0;
     Initializer rec;
     rec.T = (double)v.T;
     rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
-    rec.u[0] = (double)v.u[0]; rec.u[1] = (double)v.u[1]; rec.u[2] = (double)v.u[2];
+    rec.u[0] = (double)v.ux; rec.u[1] = (double)v.uy; rec.u[2] = (double)v.uz;
     rec.key = v.key;
     rec.row = row;
     rec.slab = slab;
@@ -1154,14 +1151,11 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
                                            const double r[3], Initializer* stack, uint32_t n_threads, uint32_t t,
                                            int depth, int& sp)
 {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (k >= sb.n) break;
-        const Sec<R> v = sb.get(k);
+    sb.each([&](const Sec<R>& v, int) {
         Initializer rec;
         rec.T = (double)v.T;
         rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
-        rec.u[0] = (double)v.u[0]; rec.u[1] = (double)v.u[1]; rec.u[2] = (double)v.u[2];
+        rec.u[0] = (double)v.ux; rec.u[1] = (double)v.uy; rec.u[2] = (double)v.uz;
         rec.key = v.key;
         rec.row = row;
         rec.slab = slab;
@@ -1177,7 +1171,7 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
             if (q < d.queue_cap) d.queue[q] = rec;
             else atomicOr(&d.ctr->overflow, 1u);
         }
-    }
+    });
 }
 
 template <class R>

@@ -143,7 +143,7 @@ __device__ __forceinline__ void normalize3(R v[3])
 template <class R>
 struct Sec {
     R T;
-    R u[3];
+    R ux, uy, uz;       // scalars, not an array: the buffer must stay in registers
     uint64_t key;
     int type;
 };
@@ -152,20 +152,33 @@ template <class R>
 struct SecBuf {
     int n;
     Sec<R> s0, s1, s2;
+    // every field of every slot is written through a value select: branches
+    // or whole-struct copies chosen at run time would be merged into stores
+    // through a selected pointer, which puts the buffer on the stack
+    __device__ __forceinline__ static void put(Sec<R>& s, bool here, int t, R e, const R d[3], uint64_t k)
+    {
+        s.T = here ? e : s.T;
+        s.ux = here ? d[0] : s.ux;
+        s.uy = here ? d[1] : s.uy;
+        s.uz = here ? d[2] : s.uz;
+        s.key = here ? k : s.key;
+        s.type = here ? t : s.type;
+    }
     __device__ __forceinline__ void add(int t, R e, const R d[3], uint64_t k)
     {
-        Sec<R> v;
-        v.T = e; v.u[0] = d[0]; v.u[1] = d[1]; v.u[2] = d[2]; v.key = k; v.type = t;
-        if (n == 0) s0 = v;
-        else if (n == 1) s1 = v;
-        else s2 = v;
+        put(s0, n == 0, t, e, d, k);
+        put(s1, n == 1, t, e, d, k);
+        put(s2, n >= 2, t, e, d, k);
         ++n;
     }
-    __device__ __forceinline__ Sec<R> get(int k) const
+    // Visit the stored secondaries in order, by name (no run-time index, so
+    // the buffer stays in registers): f(secondary, ordinal).
+    template <class F>
+    __device__ __forceinline__ void each(F&& f) const
     {
-        if (k == 0) return s0;
-        if (k == 1) return s1;
-        return s2;
+        if (n > 0) f(s0, 0);
+        if (n > 1) f(s1, 1);
+        if (n > 2) f(s2, 2);
     }
 };
 
