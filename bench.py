@@ -122,7 +122,7 @@ def parse():
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the six interaction kernels")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
-    ap.add_argument("--cpu-events", type=int, default=4000, help="oracle sample (events); 0 = skip")
+    ap.add_argument("--cpu-events", type=int, default=10000, help="oracle sample (events); 0 = skip")
     ap.add_argument("--compare", action="store_true", help="also time the other sort policies")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--layer-error", action="store_true")
