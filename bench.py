@@ -44,9 +44,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per processed track for each kernel (SoA fields read and
-# written for a participating track, plus 16 B of tally read-modify-write for
-# charged steps), FP64 / mixed.  Derivation in the design doc.
+# Algorithmic bytes per processed track for each kernel: the SoA fields a
+# participating track reads and writes (FP64 / mixed widths), plus 16 B of
+# tally read-modify-write for charged steps.  E.g. the field along-step reads
+# type, flags, search count (3), slab (2), row, step (8), key (8), T, n_lambda,
+# Sigma (24 / 12), s_phys, s_done, h_try (24), r (24) and u (24 / 12):
+# 117 / 93 B; it writes r, u, T, n_lambda, s_done, h_try, search, flags, slab,
+# action and step: 89 / 69 B; with the deposit 222 / 178 B.
 BYTES_PER_TRACK = {
     "f64": {"pre_step": 62, "along_neutral": 148, "along_charged": 164, "along_field": 222,
             "compton": 122, "photoelectric": 122, "pair": 122, "moller": 122, "bhabha": 122,
