@@ -327,8 +327,10 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
 
 // ---- work distribution ----------------------------------------------------------
 // Iterate the tracks of action `a`: masked over all slots, or the index range
-// of `a` in the sorted permutation.  The loop bound is block-uniform so every
-// wave reaches the converged point at the end of each trip.
+// of `a` in the sorted permutation (or its list), which holds exactly the
+// tracks of that action, so only the masked walk checks the action byte.  The
+// loop bound is block-uniform so every wave reaches the converged point at the
+// end of each trip.
 #define EMS_TRACK_RANGE(d, a)                                                              \
     unsigned long long _work = 0;                                                           \
     const int _mode = (d).ctr->phase_sorted ? ((a) >= A_PROC0 ? (d).sorted2 : (d).sorted) : 0; \
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
         uint32_t s = 0;                                                                     \
         if (act) s = _mode == 2 ? (d).lists[(size_t)(a) * (d).n_slots + _i]                 \
                      : (_mode ? (d).perm[_off + _i] : _i);                                  \
-        if (act && (d).action[s] != (a)) act = false;                                       \
+        if (act && _mode == 0 && (d).action[s] != (a)) act = false;                         \
         _work += act ? 1u : 0u;
 
 #define EMS_END_TRACKS }
@@ -1075,6 +1077,12 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
     if (mode == 1) {
         off = d.ctr->range_off[A_PROC0];
         n = d.ctr->range_off[A_PROC0 + 5] + d.ctr->range_cnt[A_PROC0 + 5] - off;
+        // ends of the first five process ranges, relative to the first
+        lc0 = d.ctr->range_off[A_PROC0 + 1] - off;
+        lc1 = d.ctr->range_off[A_PROC0 + 2] - off;
+        lc2 = d.ctr->range_off[A_PROC0 + 3] - off;
+        lc3 = d.ctr->range_off[A_PROC0 + 4] - off;
+        lc4 = d.ctr->range_off[A_PROC0 + 5] - off;
     } else if (mode == 2) {
         lc0 = d.ctr->list_cnt[A_PROC0];
         lc1 = lc0 + d.ctr->list_cnt[A_PROC0 + 1];
@@ -1089,18 +1097,22 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
         const uint32_t i = base + threadIdx.x;
         bool act = i < n;
         uint32_t s = 0;
+        uint8_t a = A_NONE;
         if (act) {
+            // sorted: the process follows from the position in the ranges
+            const int p = i < lc0 ? 0 : (i < lc1 ? 1 : (i < lc2 ? 2 : (i < lc3 ? 3 : (i < lc4 ? 4 : 5))));
             if (mode == 1) {
                 s = d.perm[off + i];
+                a = (uint8_t)(A_PROC0 + p);
             } else if (mode == 2) {
-                int p = i < lc0 ? 0 : (i < lc1 ? 1 : (i < lc2 ? 2 : (i < lc3 ? 3 : (i < lc4 ? 4 : 5))));
                 uint32_t lo = p == 0 ? 0u : (p == 1 ? lc0 : (p == 2 ? lc1 : (p == 3 ? lc2 : (p == 4 ? lc3 : lc4))));
                 s = d.lists[(size_t)(A_PROC0 + p) * d.n_slots + (i - lo)];
+                a = (uint8_t)(A_PROC0 + p);
             } else {
                 s = i;
+                a = d.action[s];
             }
         }
-        const uint8_t a = act ? d.action[s] : (uint8_t)A_NONE;
         act = act && a >= A_PROC0 && a < A_PROC0 + 6;
         SecBuf<R> sb;
         sb.n = 0;
