@@ -594,9 +594,11 @@ template <class R, bool CHARGED>
 __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int typ, R& T, R sig, double step_len,
                                              int face, uint8_t fl, int mat, uint16_t& slab, const double r[3],
                                              SecBuf<R>& sb, StepTally& tl, const PhysParams& pp, bool& alive,
-                                             uint8_t& next_action, R& nl)
+                                             uint8_t& next_action, R& nl, uint32_t& step, uint64_t key, uint32_t row)
 {
-    uint32_t step = d.step[s];
+    // step, key and row come in registers (loaded with the rest of the
+    // track up front); step leaves as the track's step count after this step
+    const uint32_t k = step;
     if (CHARGED) {
         const R* Rt = range_tab(tb, mat, typ);
         Loc<R> l = locate(tb, T);
@@ -614,12 +616,13 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         }
         if (stop) {
             Prim<R> p;
-            p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = d.key[s]; p.step = step; p.type = typ; p.alive = true;
+            p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = key; p.step = k; p.type = typ; p.alive = true;
             stop_lepton<R>(pp, p, sb, tl);
             T = R(0);
             alive = false;
             next_action = A_NONE;
-            d.step[s] = step + 1;
+            step = k + 1;
+            d.step[s] = step;
             return;
         }
     }
@@ -630,19 +633,21 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         else if (face == F_ZHI) next = slab + 1;
         else next = -1;
         if (next < 0 || next >= d.n_slabs) {
-            atomicAdd(&d.ledger[d.row[s]].escaped, (double)T);
+            atomicAdd(&d.ledger[row].escaped, (double)T);
             alive = false;
             next_action = A_NONE;
         } else {
             slab = (uint16_t)next;
             next_action = A_IDLE;
         }
-        d.step[s] = step + 1;
+        step = k + 1;
+        d.step[s] = step;
     } else if (fl & F_LOSS) {
         next_action = A_IDLE;
-        d.step[s] = step + 1;
+        step = k + 1;
+        d.step[s] = step;
     } else {
-        StepRng<R> rng(d.seed, pp.event, d.key[s], step, (fl & F_DREW) ? 1 : 0);
+        StepRng<R> rng(d.seed, pp.event, key, k, (fl & F_DREW) ? 1 : 0);
         R U1 = rng.next();
         R sig1;
         Loc<R> l1;
@@ -660,14 +665,15 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
             next_action = (uint8_t)(A_PROC0 + proc);
         } else {
             next_action = A_IDLE;
-            d.step[s] = step + 1;
+            step = k + 1;
+            d.step[s] = step;
         }
     }
-    if (alive && d.step[s] > kMaxSteps && next_action == A_IDLE) {
+    if (alive && step > kMaxSteps && next_action == A_IDLE) {
         // step guard
-        atomicAdd(&d.ledger[d.row[s]].n_guard, 1ull);
+        atomicAdd(&d.ledger[row].n_guard, 1ull);
         Prim<R> p;
-        p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = d.key[s]; p.step = d.step[s]; p.type = typ; p.alive = true;
+        p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = key; p.step = step; p.type = typ; p.alive = true;
         if (typ != kGamma) stop_lepton<R>(pp, p, sb, tl);
         else tl.edep += (double)T;
         T = R(0);
@@ -689,15 +695,18 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     row = d.row[s];
     uint16_t slab = d.slab[s];
     slab0 = slab;
-    int mat = d.smat[slab];
     R T = d.T[s];
     R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
-    double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
     r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
     double s_phys = d.sphys[s];
     uint8_t fl = d.flags[s];
     R sig = d.xs[s];
     R nl = d.nl[s];
+    uint32_t step = d.step[s];
+    const uint64_t key = d.key[s];
+    const uint64_t event = d.row_event[row];
+    int mat = d.smat[slab];
+    double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
     int face;
     double s_geo = straight_distance(r, ud, d.zp[slab], d.zp[slab + 1], d.W, &face);
     double st;
@@ -708,16 +717,17 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     r[2] = r[2] + st * ud[2];
     if (face != F_NONE) r[face_axis(face)] = face_plane(d.zp, slab, d.W, face);
     StepTally tl = {0.0, 0, 0, 0};
-    PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+    PhysParams pp = {d.seed, event, d.ecut};
     bool alive = true;
     uint8_t na = A_IDLE;
-    const uint32_t k0 = d.step[s];
+    const uint32_t k0 = step;
     const double T_pre = (double)T;
-    finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+    finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl, step, key,
+                             row);
     record_tally(d, row, slab0, tl);
     d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
     if (CHARGED && d.msc && alive) {
-        msc_deflect(d.seed, pp.event, d.key[s], k0, T_pre, st, d.x0[mat], ud);
+        msc_deflect(d.seed, pp.event, key, k0, T_pre, st, d.x0[mat], ud);
         d.ux[s] = (R)ud[0]; d.uy[s] = (R)ud[1]; d.uz[s] = (R)ud[2];
     }
     if (alive) {
@@ -727,7 +737,7 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
         d.action[s] = na;
         next = na;
     } else {
-        retired = d.step[s];
+        retired = step;
         retire(d, s, row, retired);
     }
 }
@@ -839,6 +849,13 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
     double h_try = d.htry[s];
     int n_search = d.nsearch[s];
     uint8_t fl = d.flags[s];
+    // fields used only at the end of the step, loaded with the rest so that
+    // no memory round trip is left for after the integration
+    const R sig = d.xs[s];
+    R nl = d.nl[s];
+    uint32_t step = d.step[s];
+    const uint64_t key = d.key[s];
+    const uint64_t event = d.row_event[row];
     double Td = (double)T;
     double q = typ == kPositron ? 1.0 : -1.0;
     double p = sqrt(Td * (Td + 2.0 * kMe));
@@ -926,17 +943,16 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
         d.htry[s] = 0.0;
         d.nsearch[s] = 0;
         d.flags[s] = fl & (uint8_t)~F_PAUSED;
-        R sig = d.xs[s];
-        R nl = d.nl[s];
         StepTally tl = {0.0, 0, 0, 0};
-        PhysParams pp = {d.seed, d.row_event[row], d.ecut};
+        PhysParams pp = {d.seed, event, d.ecut};
         bool alive = true;
         uint8_t na = A_IDLE;
-        const uint32_t k0 = d.step[s];
-        finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl);
+        const uint32_t k0 = step;
+        finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl, step,
+                              key, row);
         record_tally(d, row, slab0, tl);
         if (d.msc && alive) {
-            msc_deflect(d.seed, pp.event, d.key[s], k0, Td, s_done, d.x0[mat], u);
+            msc_deflect(d.seed, pp.event, key, k0, Td, s_done, d.x0[mat], u);
             d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
         }
         if (alive) {
@@ -946,7 +962,7 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
             d.action[s] = na;
             next = na;
         } else {
-            retired = d.step[s];
+            retired = step;
             retire(d, s, row, retired);
         }
     }

@@ -202,4 +202,13 @@ def test_empty_push_and_invalid_primaries_rejected():
     assert c["steps"] == steps
     edep, led = s.tallies_by_event(np.arange(w.n_events))
     _assert_events_match(w, edep, led, e_ref, l_ref, "after rejects")
+    # a batch release with an unknown or a repeated id releases nothing
+    for bad in ([0, 1, 999], [2, 2]):
+        with pytest.raises(emstep.EmsError):
+            s.release(np.array(bad, dtype=np.uint64))
+    e2, _ = s.tallies_by_event(np.arange(w.n_events))
+    assert np.array_equal(e2, edep)
+    s.release(np.arange(w.n_events, dtype=np.uint64))
+    _, _, rows = s.read_all()
+    assert np.all(rows == np.uint64(2 ** 64 - 1))
     s.close()
