@@ -69,3 +69,35 @@ def test_completion_reported_once_per_event():
     s.close()
     assert sorted(seen) == list(range(w.n_events))
     assert c["alive"] == 0 and c["queued"] == 0 and c["completed"] == w.n_events
+
+
+def test_full_size_serving_session_sampled():
+    """The serving workload's own configuration (2^23 slots, mixed precision,
+    events of 1-200 primaries up to 100 GeV, graph batches): events admitted
+    into the running loop give, for a sample of them, the same result as
+    alone, and every event's energy ledger closes."""
+    w = workloads.serving_events(24)
+    assert w.n_slots == 1 << 23 and w.precision == "mixed"
+    events = serving.split_events(w.primaries)
+    arrivals = workloads.poisson_arrival_times(w.seed, 200.0, len(events))
+    s = session_for(w, precision="mixed", max_events=64, sort_policy="partition", graph_iterations=8, streams=1)
+    s.set_tuning(fuse_interactions=True)
+    res = serving.serve(s, events, arrivals, track_budget=w.n_slots, iterations_per_poll=8)
+    s.close()
+    assert sorted(res.latency_s) == sorted(e for e, _ in events)
+    assert res.max_in_flight > 1
+    me = 0.51099895
+    for ev, prims in events:
+        led = res.ledger[ev]
+        tot = res.edep[ev].sum() + led["escaped"] + 2 * me * (float(led["n_pair"]) - float(led["n_annih"]))
+        assert abs(tot - prims["T"].sum()) <= 1e-4 * prims["T"].sum(), ev
+    for ev, prims in events[::6]:
+        s1 = session_for(w, n_slots=1 << 18, precision="mixed", max_events=1)
+        s1.push(prims)
+        s1.run()
+        e_one, l_one = s1.read_edep(ev)
+        s1.close()
+        scale = max(np.abs(e_one).max(), 1e-300)
+        assert np.abs(res.edep[ev] - e_one).max() <= 1e-12 * scale, ev
+        for f in ("n_pair", "n_annih", "steps"):
+            assert res.ledger[ev][f] == l_one[f], (ev, f)
