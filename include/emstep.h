@@ -17,7 +17,11 @@
  *   - a cap on field-propagation substeps per iteration after which a track's
  *     step is paused and resumed ("Reducing load imbalance");
  *   - stream-ordered memory operations only ("Asynchronous memory
- *     management").
+ *     management");
+ *   - on top of the paper's loop: FP32 energies and directions (mixed
+ *     precision), continuous batching of events (serving), run-time tuning,
+ *     one fused launch for the interaction kernels, and a history-mode drain
+ *     of the last tracks.
  *
  * The caller's sequence follows the statement of the problem: load geometry,
  * materials and physics tables; push primaries; step until the slots are

@@ -90,23 +90,19 @@ struct Counters {
     unsigned long long prim_next;      // next pending primary
     unsigned long long prim_end;       // end of pushed primaries
     unsigned long long iterations;
-    unsigned long long steps_done;     // completed steps of finished tracks
     unsigned int n_vac;                // vacancies found this iteration
     unsigned int n_alive;              // live tracks at the start of this iteration
     unsigned int overflow;
     unsigned int n_take_q;             // initializers taken from the queue this iteration
     unsigned int n_take_p;             // primaries taken this iteration
-    unsigned int n_charged_taken;      // for the partitioned fill
     unsigned long long q_base;         // first queue index taken (top - n_take_q)
     unsigned long long p_base;
     unsigned int range_off[16];        // sorted mode: start of each action's index range
     unsigned int range_cnt[16];
-    unsigned long long work[16];       // tracks processed per kernel role (see W_*)
     unsigned int list_cnt[16];         // queue policy: entries of each interaction list
     unsigned int alive_before;         // live tracks found by the vacancy pass (before the fill)
     unsigned int done_count;           // events completed so far (entries written to the ring)
     unsigned int phase_sorted;         // this iteration reorders tracks (occupancy above the tail threshold)
-    unsigned int pad2;
 };
 
 // work counter indices

@@ -4,11 +4,14 @@
 // algorithm"); each iteration launches, in stream order:
 //   vacancy count / scatter  -> initialization (optionally partitioned)
 //   -> pre-step -> [sort point 1] -> along-step (neutral, charged, field)
-//   -> [sort point 2] -> six interaction kernels.
-// Loop termination is read from device counters copied asynchronously to a
-// pinned host buffer after every batch of iterations; batches can be captured
-// once into a HIP graph and replayed.  No synchronous memory operation is
-// issued inside the loop (paper, "Asynchronous memory management").
+//   -> [sort point 2] -> six interaction kernels, or one fused launch
+//   -> completion scan.
+// Below a live-track threshold ems_run replaces the iteration by a fill and
+// one history-mode drain launch.  Loop termination is read from device
+// counters copied asynchronously to a pinned host buffer after every batch of
+// iterations; batches can be captured once into a HIP graph and replayed.  No
+// synchronous memory operation is issued inside the loop (paper,
+// "Asynchronous memory management").
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
