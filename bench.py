@@ -232,8 +232,16 @@ def cpu_baseline(w, n_events):
     t0 = time.perf_counter()
     _, _, steps = pb.run_events(tr, rows, n_events, threads)
     dt = time.perf_counter() - t0
+    # one thread on a smaller sample: the per-core rate
+    n1 = max(1, min(n_events, n_events // 20))
+    sel = sub.primaries["event"] < n1
+    t1 = time.perf_counter()
+    _, _, steps1 = pb.run_events(tr[sel], rows[sel], n1, 1)
+    dt1 = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "track-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_events} events of the workload ({steps} track-steps, {dt:.2f} s wall)"}
+            "sample": f"first {n_events} events of the workload ({steps} track-steps, {dt:.2f} s wall)",
+            "single_core": {"value": steps1 / dt1, "unit": "track-steps/s",
+                            "sample": f"first {n1} events ({steps1} track-steps, {dt1:.2f} s)"}}
 
 
 def event_parallel_rate(w, args, precision, k, repeats=2):
