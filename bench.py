@@ -9,7 +9,7 @@ region of each step; the timed region covers the device loop only.
 Default workload: 10^4 electrons of 1 GeV into a 50-layer Pb (2 mm) / liquid
 Ar (5 mm) stack, 40 x 40 cm, uniform 1 T field along x, 0.1 MeV cut, 2^20
 track slots, FP64, slots sorted by next action, iterations replayed from
-captured HIP graphs, the six interaction kernels fused into one launch, the
+captured HIP graphs, the interaction kernels fused into one launch, the
 last tracks (below 65536 alive, queued or pending) stepped in history mode by
 the drain kernel.
 
@@ -54,10 +54,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_TRACK = {
     "f64": {"pre_step": 62, "along_neutral": 148, "along_charged": 164, "along_field": 222,
             "compton": 122, "photoelectric": 122, "pair": 122, "moller": 122, "bhabha": 122,
-            "bremsstrahlung": 122, "init": 206},
+            "bremsstrahlung": 122, "annihilation": 122, "init": 206},
     "mixed": {"pre_step": 46, "along_neutral": 124, "along_charged": 140, "along_field": 178,
               "compton": 102, "photoelectric": 102, "pair": 102, "moller": 102, "bhabha": 102,
-              "bremsstrahlung": 102, "init": 174},
+              "bremsstrahlung": 102, "annihilation": 102, "init": 174},
 }
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -123,7 +123,8 @@ def parse():
                     help="run the last tracks in history mode below this many live+queued+pending (0 = off)")
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
-    ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the six interaction kernels")
+    ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")
+    ap.add_argument("--field-sort", type=int, default=0, help="first sort splits field tracks by cost class")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=10000, help="oracle sample (events); 0 = skip")
@@ -152,7 +153,8 @@ def make_workload(name, events, slots):
     return w
 
 
-def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None):
+def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None,
+                fsort=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
     s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
@@ -164,9 +166,9 @@ def new_session(w, args, precision, policy, init_partition, graph=None, drain=No
     drain = args.drain_threshold if drain is None else drain
     reuse = args.reuse_parent_slot if reuse is None else reuse
     fuse = args.fuse_interactions if fuse is None else fuse
-    if drain > 0 or reuse or fuse:
-        s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse),
-                     fuse_interactions=bool(fuse))
+    fsort = args.field_sort if fsort is None else fsort
+    s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse),
+                 fuse_interactions=bool(fuse), field_sort=bool(fsort))
     return s
 
 
@@ -180,8 +182,9 @@ def time_batch(s, primaries, events):
     return c, time.perf_counter() - t0
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None):
-    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse)
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None,
+                fsort=None):
+    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse, fsort=fsort)
     events = np.unique(w.primaries["event"])
     tuned = None
     if tune is not None:
@@ -410,6 +413,7 @@ def main():
                    "lds_tables": args.lds_tables, "streams": args.streams,
                    "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
                    "reuse_parent_slot": args.reuse_parent_slot, "fuse_interactions": args.fuse_interactions,
+                   "field_sort": args.field_sort,
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
@@ -427,7 +431,7 @@ def main():
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
                "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot,
-               "fuse_interactions": args.fuse_interactions}
+               "fuse_interactions": args.fuse_interactions, "field_sort": args.field_sort}
         t = committed_traffic(prof_kernel, key)
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -456,6 +460,9 @@ def main():
             rv = run_variant(w, args, precision, pol, 0, None, fuse=fu)
             tag = f"{pol}+part0" + ("+fused" if fu else "+unfused")
             var[tag] = rv["steps"] / rv["seconds"]
+        fs = 0 if args.field_sort else 1
+        rv = run_variant(w, args, precision, "partition", 0, None, fsort=fs)
+        var["partition+part0" + ("+fieldsort" if fs else "+nofieldsort")] = rv["steps"] / rv["seconds"]
         for k in (4, 8):
             var[f"event_parallel_{k}x{w.n_slots // k}"] = event_parallel_rate(w, args, precision, k)
         out["variants"] = var

@@ -11,6 +11,9 @@
  *     struct of arrays;
  *   - secondaries are pushed to a buffer of lightweight track initializers
  *     and vacant slots are filled from it at the start of every iteration;
+ *     only the interaction kernels create them (a positron that stops in its
+ *     along-step annihilates at rest in the interaction kernels of the same
+ *     iteration);
  *   - optional reordering of track slots by next action
  *     ("Reindexing track slots") and optional partitioning of new tracks into
  *     charged / neutral ends of the slot array ("Partitioning track data");
@@ -50,7 +53,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 4u
+#define EMS_ABI_VERSION 5u
 
 typedef enum {
     EMS_OK = 0,
@@ -152,11 +155,13 @@ typedef struct {
     uint64_t steps;            /* completed steps of tracks that have finished */
     uint32_t overflow;         /* nonzero: the initializer buffer overflowed (results invalid) */
     uint32_t completed;        /* events completed since creation */
-    /* cumulative tracks processed per kernel role: [1] init, [2] pre-step,
-     * [4] neutral, [5] charged, [6] field along-step (track-iterations),
-     * [7..12] Compton, photoelectric, pair, Moller, Bhabha, bremsstrahlung,
-     * [13] paused field steps, [14] field RK4 evaluations */
-    uint64_t work[16];
+    /* cumulative tracks processed per kernel role: [0] slots handed from a
+     * finished track to its secondary, [1] init, [2] pre-step, [4] neutral,
+     * [5] charged, [6] field along-step (track-iterations), [7..12] Compton,
+     * photoelectric, pair, Moller, Bhabha, bremsstrahlung, [13] annihilation
+     * at rest, [14] paused field steps, [15] field RK4 evaluations, [16]
+     * drain steps */
+    uint64_t work[24];
 } ems_counters;
 
 typedef struct ems_ctx ems_ctx;
@@ -274,9 +279,9 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * block[i] is the block size of kernel role i (role order as returned by
  * ems_profile_read: vacancies, init, pre_step, sort, along_neutral,
  * along_charged, along_field, compton, photoelectric, pair, moller, bhabha,
- * bremsstrahlung, drain, interactions); 0 keeps ems_options.block_size.  Below
- * tail_threshold live tracks an iteration skips the reordering and runs
- * masked (the device decides per iteration).
+ * bremsstrahlung, drain, interactions, annihilation); 0 keeps
+ * ems_options.block_size.  Below tail_threshold live tracks an iteration
+ * skips the reordering and runs masked (the device decides per iteration).
  *
  * Drain (ems_run only; 0 = off): once the latest counter snapshot shows fewer
  * than drain_threshold tracks alive, queued or pending, each further
@@ -291,10 +296,18 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * next iteration's fill (fewer initializer round trips; it mixes charged and
  * neutral tracks in slots that init_partition would keep apart).
  *
- * fuse_interactions (0/1): run the six interaction kernels as one launch that
- * walks the combined index range of the interaction actions (each wave holds
- * one process except at range boundaries) instead of six launches on the
- * library's streams; kernel role "interactions" in the block table.
+ * fuse_interactions (0/1): run the seven interaction kernels (six processes
+ * and annihilation at rest) as one launch that walks the combined index range
+ * of the interaction actions (each wave holds one action except at range
+ * boundaries) instead of seven launches on the library's streams; kernel role
+ * "interactions" in the block table.
+ *
+ * field_sort (0/1, default 0; PARTITION and QUEUE policies in a field): the
+ * sort after the pre-step splits the field tracks into cost classes (the RK4
+ * evaluations the step is expected to take, from its physics limit, momentum
+ * and distance to the next z plane), so that the tracks of a wave run their
+ * integration loop for similar counts; the field kernel still sees one index
+ * range.  The pre-step then also reads position and direction.
  * Setting the tuning re-captures graphs on the next run. */
 typedef struct {
     int32_t sort_policy;
@@ -304,6 +317,7 @@ typedef struct {
     uint32_t drain_steps;
     uint32_t reuse_parent_slot;
     uint32_t fuse_interactions;
+    uint32_t field_sort;
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

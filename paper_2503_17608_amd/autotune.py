@@ -28,7 +28,7 @@ from . import emstep
 
 BLOCK_CANDIDATES = (64, 128, 256, 512)
 STEP_ROLES = ("pre_step", "along_neutral", "along_charged", "along_field", "compton", "photoelectric", "pair",
-              "moller", "bhabha", "bremsstrahlung", "interactions")
+              "moller", "bhabha", "bremsstrahlung", "annihilation", "interactions")
 
 
 def signature(n_slots, precision, stack, ecut, primaries):

@@ -35,8 +35,9 @@ constexpr uint32_t kMaxSteps = 1000000u;
 enum : int { TB_COMPTON = 0, TB_PHOTO, TB_PAIR, TB_MOLLER, TB_BHABHA, TB_BREMS, TB_RANGE_EM, TB_RANGE_EP };
 // particle types stored in the state; kDead marks a vacant slot
 enum : uint8_t { kGamma = 0, kElectron = 1, kPositron = 2, kDead = 3 };
-// processes
-enum : int { P_COMPTON = 0, P_PHOTO, P_PAIR, P_MOLLER, P_BHABHA, P_BREMS, kNumProc };
+// discrete actions: the six sampled processes, then annihilation at rest (a
+// positron that stopped in its along-step; it is not chosen by cross section)
+enum : int { P_COMPTON = 0, P_PHOTO, P_PAIR, P_MOLLER, P_BHABHA, P_BREMS, P_ANNIH, kNumProc };
 
 // Next-action codes (the sort key).  Along-step actions are set by the
 // pre-step kernel, interaction actions by the along-step kernels.
@@ -46,6 +47,7 @@ enum : uint8_t {
     A_CHARGED = 2,     // straight-line along-step with continuous loss (no field)
     A_FIELD = 3,       // field propagation (also a paused step)
     A_PROC0 = 4,       // + process index: discrete interaction
+    A_ANNIH = A_PROC0 + P_ANNIH,
     A_NUM = A_PROC0 + kNumProc,
     A_NONE = 0xFF      // vacant slot
 };
@@ -55,7 +57,17 @@ enum : uint8_t {
     F_DREW = 1,        // the interaction-length uniform (index 0) was drawn this step
     F_LOSS = 2,        // the physics step limit is the energy-loss limit
     F_PAUSED = 4,      // field step paused at the substep cap
+    // bits 3-4: cost class of a field step (expected RK4 evaluations minus
+    // one, capped), set by the pre-step to order field tracks at the first sort
+    F_COST_SHIFT = 3,
+    F_COST_MASK = 3 << 3,
+    // the stop of a positron waiting for annihilation at rest was counted as
+    // a step already (step-guard stop): the annihilation adds no step
+    F_COUNTED = 32,
 };
+
+// field tracks form this many sub-bins (cost classes) at the first sort
+constexpr int kFieldCostBins = 4;
 
 // faces of a slab box
 enum : int { F_NONE = 0, F_ZLO, F_ZHI, F_XLO, F_XHI, F_YLO, F_YHI };
@@ -108,23 +120,26 @@ struct Counters {
 // work counter indices
 enum : int {
     W_REUSE = 0, W_INIT = 1, W_PRE = 2, W_SORT = 3, W_NEUTRAL = 4, W_CHARGED = 5, W_FIELD = 6, W_PROC0 = 7,
-    W_PAUSED = 13, W_SUBSTEPS = 14, W_DRAIN = 15
+    W_PAUSED = W_PROC0 + kNumProc, W_SUBSTEPS, W_DRAIN
 };
-// partial-counter slots: [0, 16) work per kernel, [16, 32) completed steps of
-// the tracks each kernel retired (one slot per kernel, since kernels of an
-// iteration may run concurrently and every slot has a single writer)
-constexpr int kNumW = 32;
+// partial-counter slots: [0, kNumWork) work per kernel, [kStepsSlot, kNumW)
+// completed steps of the tracks each kernel retired (one slot per kernel,
+// since kernels of an iteration may run concurrently and every slot has a
+// single writer)
+constexpr int kNumWork = W_DRAIN + 1;
+constexpr int kStepsSlot = kNumWork;
+constexpr int kNumW = 2 * kNumWork;
+static_assert(W_DRAIN < kNumWork, "work counter slots");
 constexpr uint32_t kDrainThreadsMax = 1u << 16;   // drain kernel threads (each with a private stack)
 constexpr int kDrainDepth = 8;                     // private secondary stack depth per drain thread
 constexpr uint32_t kDrainStepsDefault = 4096;      // steps per drain thread and launch
 constexpr int kDrainSubsteps = 1024;               // field substeps per drain trip before a pause
-constexpr int kStepsSlot = 16;
 
 // Host-visible snapshot copied to pinned memory after each batch
 struct Snapshot {
     unsigned long long queue_size, prim_next, prim_end, iterations, steps_done;
     unsigned int n_vac, n_alive, overflow, done_count;
-    unsigned long long work[16];
+    unsigned long long work[kNumWork];
 };
 
 // ---- Philox4x64-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers:

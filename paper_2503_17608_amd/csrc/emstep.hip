@@ -61,7 +61,7 @@ struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
-    uint64_t drain_stack, regs, x0;
+    uint64_t drain_stack, regs, x0, rowsum;
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads with a private stack)
     uint64_t total;
@@ -126,6 +126,7 @@ Layout make_layout(const ems_options& o)
     L.row_state = take(4 * (uint64_t)o.max_events);
     L.part_stride = (uint32_t)std::max<uint64_t>(2048, nvb);
     L.part = take(8ull * kNumW * L.part_stride);
+    L.rowsum = take(8ull * kNumW);
     L.incr = take(8ull * o.max_materials * 2 * (kNodes - 1));
     L.drain_threads = (uint32_t)std::min<uint64_t>(kDrainThreadsMax, align_up(n, 256));
     L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
@@ -137,11 +138,12 @@ Layout make_layout(const ems_options& o)
 
 enum Role {
     R_VAC = 0, R_INIT, R_PRE, R_SORT, R_ALONG_NEUTRAL, R_ALONG_CHARGED, R_ALONG_FIELD,
-    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_DRAIN, R_INTERACT_ALL, R_NUM
+    R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_DRAIN, R_INTERACT_ALL, R_ANNIH, R_NUM
 };
 const char* kRoleNames[R_NUM] = {"vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged",
                                  "along_field", "compton", "photoelectric", "pair", "moller", "bhabha",
-                                 "bremsstrahlung", "drain", "interactions"};
+                                 "bremsstrahlung", "drain", "interactions", "annihilation"};
+static_assert(R_NUM <= 16, "the tuning block table holds 16 roles");
 
 }  // namespace
 
@@ -194,6 +196,7 @@ struct ems_ctx {
     uint32_t drain_steps = kDrainStepsDefault;
     uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
     uint32_t fuse_interactions = 0;   // one launch for the six interaction kernels
+    uint32_t field_sort = 0;          // first sort splits field tracks by cost class
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -271,6 +274,12 @@ Dev<R> make_dev(const ems_ctx* c)
     d.tail_threshold = c->tail_threshold;
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
+    d.field_sort = (c->field_sort && d.has_field &&
+                    (c->policy == EMS_SORT_PARTITION || c->policy == EMS_SORT_QUEUE)) ? 1 : 0;
+    {
+        const double bm = sqrt(c->B[0] * c->B[0] + c->B[1] * c->B[1] + c->B[2] * c->B[2]);
+        d.hc_coef = bm > 0.0 ? (float)(8.0 * kDChord / (kCk * bm)) : 0.0f;
+    }
     d.msc = c->opt.msc ? 1 : 0;
     d.x0 = (const double*)(c->ws + c->L.x0);
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
@@ -321,20 +330,20 @@ __global__ void k_count_primaries(const Initializer* prims, uint64_t cap, uint64
     atomicAdd(&live[prims[(start + i) % cap].row], 1u);
 }
 
-// Copy the loop counters and sum the per-block partial counters (one block)
-__global__ void __launch_bounds__(1024) k_snapshot(const Counters* c, const unsigned long long* part, uint32_t stride,
-                                                   Snapshot* out)
+// Sum each row of the per-block partial counters: block w sums row w.
+__global__ void __launch_bounds__(256) k_sum_rows(const unsigned long long* part, uint32_t stride,
+                                                  unsigned long long* rowsum)
 {
-    __shared__ unsigned long long acc[kNumW];
-    if (threadIdx.x < kNumW) acc[threadIdx.x] = 0;
-    __syncthreads();
-    for (int w = 0; w < kNumW; ++w) {
-        unsigned long long v = 0;
-        for (uint32_t i = threadIdx.x; i < stride; i += blockDim.x) v += part[(size_t)w * stride + i];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if ((threadIdx.x & 63) == 0 && v) atomicAdd(&acc[w], v);
-    }
-    __syncthreads();
+    const unsigned long long* row = part + (size_t)blockIdx.x * stride;
+    unsigned long long v = 0;
+    for (uint32_t i = threadIdx.x; i < stride; i += blockDim.x) v += row[i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) rowsum[blockIdx.x] = v;
+}
+
+// Copy the loop counters and the row sums of the partial counters
+__global__ void k_snapshot(const Counters* c, const unsigned long long* acc, Snapshot* out)
+{
     if (threadIdx.x == 0) {
         Snapshot s;
         s.queue_size = c->queue_size;
@@ -348,7 +357,7 @@ __global__ void __launch_bounds__(1024) k_snapshot(const Counters* c, const unsi
         s.n_alive = c->n_alive;
         s.overflow = c->overflow;
         s.done_count = c->done_count;
-        for (int i = 0; i < 16; ++i) s.work[i] = acc[i];
+        for (int i = 0; i < kNumWork; ++i) s.work[i] = acc[i];
         *out = s;
     }
 }
@@ -415,20 +424,23 @@ void join(ems_ctx* c, int point, int k)
     }
 }
 
+// `first`: the sort after the pre-step, where field tracks may be split by
+// cost class (keymode 2); the sort after the along-step orders by action.
 template <class R>
-void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
+void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, bool first)
 {
     const int policy = c->policy;
+    const int km = first && d.field_sort ? 2 : 0;
     uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
     uint32_t* tot = (uint32_t*)(c->ws + c->L.bin_off);
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
     if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
-        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
+        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
              (const uint8_t*)nullptr, n, cnt, nt);
         ln.k(R_SORT, false, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
              tot);
-        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
+        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
     } else {
         ln.k(R_SORT, true, false, k_sort_hist<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1,
@@ -464,7 +476,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
     ln.one(R_PRE, k_pre_step<R>, dim3(G(R_PRE)), dim3(B(R_PRE)), lds, st, d);
-    if (d.sorted == 1) launch_sort<R>(c, d, ln);
+    if (d.sorted == 1) launch_sort<R>(c, d, ln, true);
     // along-step: photons and leptons are independent branches
     const int nw = c->n_streams - 1;
     hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
@@ -477,7 +489,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
                st, d);
     if (nw > 0) join(c, 0, 1);
-    if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
+    if (d.sorted2 == 1) launch_sort<R>(c, d, ln, false);
     if (c->fuse_interactions) {
         // all six processes in one launch over the combined index range
         ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
@@ -493,6 +505,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     ln.one(R_MOLLER, k_interact<R, P_MOLLER>, dim3(G(R_MOLLER)), dim3(B(R_MOLLER)), 0, on(3), d);
     ln.one(R_BHABHA, k_interact<R, P_BHABHA>, dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d);
     ln.one(R_BREMS, k_interact<R, P_BREMS>, dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d);
+    ln.one(R_ANNIH, k_interact<R, P_ANNIH>, dim3(G(R_ANNIH)), dim3(B(R_ANNIH)), 0, on(6), d);
     if (nw > 0) join(c, 1, nw);
     hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
 }
@@ -574,11 +587,20 @@ ems_status launch_batch(ems_ctx* c, int iters, bool no_init)
     return EMS_OK;
 }
 
+// counters snapshot into `out` (device-visible pinned memory), on the stream
+void launch_snapshot(ems_ctx* c, Snapshot* out)
+{
+    unsigned long long* rowsum = (unsigned long long*)(c->ws + c->L.rowsum);
+    hipLaunchKernelGGL(k_sum_rows, dim3(kNumW), dim3(256), 0, c->stream,
+                       (const unsigned long long*)(c->ws + c->L.part), c->L.part_stride, rowsum);
+    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(64), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
+                       (const unsigned long long*)rowsum, out);
+}
+
 ems_status snapshot_now(ems_ctx* c, Snapshot* out)
 {
     Snapshot* slot = &c->snap[0];
-    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1024), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
-                       (const unsigned long long*)(c->ws + c->L.part), c->L.part_stride, slot);
+    launch_snapshot(c, slot);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     *out = *slot;
@@ -595,7 +617,7 @@ void to_counters(const Snapshot& s, ems_counters* out)
     out->steps = s.steps_done;
     out->overflow = s.overflow;
     out->completed = s.done_count;
-    for (int i = 0; i < 16; ++i) out->work[i] = s.work[i];
+    for (int i = 0; i < kNumWork; ++i) out->work[i] = s.work[i];
 }
 
 template <class R>
@@ -1055,8 +1077,7 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
                 launched += batch;
             }
             int slot = (int)(seq % c->snap_slots);
-            hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(1024), 0, c->stream, (const Counters*)(c->ws + c->L.ctr),
-                               (const unsigned long long*)(c->ws + c->L.part), c->L.part_stride, &c->snap[slot]);
+            launch_snapshot(c, &c->snap[slot]);
             HIP_TRY(hipEventRecord(c->snap_ev[slot], c->stream));
             ++seq;
             ++in_flight;
@@ -1328,6 +1349,7 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
     c->drain_steps = t->drain_steps;
     c->reuse_parent = t->reuse_parent_slot ? 1u : 0u;
     c->fuse_interactions = t->fuse_interactions ? 1u : 0u;
+    c->field_sort = t->field_sort ? 1u : 0u;
     for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
     return drop_graph(c);
 }
@@ -1341,6 +1363,7 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     t->drain_steps = c->drain_steps;
     t->reuse_parent_slot = c->reuse_parent;
     t->fuse_interactions = c->fuse_interactions;
+    t->field_sort = c->field_sort;
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }

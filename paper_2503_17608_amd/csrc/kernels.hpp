@@ -75,6 +75,8 @@ struct Dev {
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
+    int field_sort;         // first sort orders field tracks by cost class
+    float hc_coef;          // squared chord-limited substep per MeV/c of momentum: 8 d_chord / (kCk |B|) [cm^2]
     const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
@@ -454,9 +456,32 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
 // Pre-step of one live, non-paused track (fields loaded by the caller):
 // interaction length, total cross section, physics step limit and the
 // along-step action, which it returns.
+// Cost class of a field step, for ordering only (the step never reads it):
+// the RK4 evaluations it is expected to take, minus one, capped at
+// kFieldCostBins - 1.  Expected: chord-limited substeps over the nearer of the
+// physics limit and the straight-line distance to the slab's z face ahead,
+// plus two for the boundary search when that face is the nearer.  Single
+// precision is enough for a class.
+template <class R>
+__device__ __forceinline__ uint32_t field_cost(const Dev<R>& d, uint32_t s, uint16_t slab, R T, R s_phys)
+{
+    const float uz = (float)d.uz[s];
+    const double z = d.z[s];
+    float dz = INFINITY;
+    if (uz > 0.0f) dz = (float)(d.zp[slab + 1] - z) / uz;
+    else if (uz < 0.0f) dz = (float)(d.zp[slab] - z) / uz;
+    const float Tf = (float)T, sp = (float)s_phys;
+    const float hc = sqrtf(d.hc_coef * sqrtf(Tf * (Tf + 2.0f * (float)kMe)));
+    const bool cross = dz < sp;
+    float n = ceilf(fminf(sp, fmaxf(dz, 0.0f)) / hc);
+    n = fmaxf(n, 1.0f) + (cross ? 2.0f : 0.0f);
+    return (uint32_t)fminf(n, (float)kFieldCostBins) - 1u;
+}
+
 template <class R>
 __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint8_t typ, R T, R nl,
-                                             uint16_t slab, uint32_t row, uint32_t step, uint64_t key)
+                                             uint16_t slab, uint32_t row, uint32_t step, uint64_t key,
+                                             bool cost_class)
 {
     int mat = d.smat[slab];
     uint8_t nf = 0;
@@ -478,10 +503,11 @@ __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& t
             nf |= F_LOSS;
         }
     }
+    uint8_t na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
+    if (na == A_FIELD && cost_class) nf |= (uint8_t)(field_cost(d, s, slab, T, s_phys) << F_COST_SHIFT);
     d.xs[s] = sig;
     d.sphys[s] = (double)s_phys;
     d.flags[s] = nf;
-    uint8_t na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
     d.action[s] = na;
     return na;
 }
@@ -521,7 +547,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
         bool paused = act && (fl & F_PAUSED) != 0;
         act = act && !paused;
         work += act ? 1u : 0u;
-        if (act) pre_track(d, tb, s, typ, T, nl, slab, row, step, key);
+        if (act) pre_track(d, tb, s, typ, T, nl, slab, row, step, key, d.field_sort != 0);
     }
     flush_count(d, W_PRE, work);
 }
@@ -588,13 +614,34 @@ __device__ __forceinline__ void msc_deflect(uint64_t seed, uint64_t event, uint6
     u[0] = out[0]; u[1] = out[1]; u[2] = out[2];
 }
 
-// Common end of an along-step (S6-S8) for a step of length s.  Returns true
-// when the track remains alive; sets the next action.
+// A lepton stops in its along-step: its kinetic energy is deposited in the
+// step's slab.  A positron annihilates at rest; when its photons are below the
+// production cut their energy is deposited here as well, otherwise the
+// positron keeps its slot and returns true: the interaction launch of this
+// iteration creates the photons (with the stopping step's index, so with the
+// same random numbers), and the along-step itself creates no tracks.
+template <class R>
+__device__ __forceinline__ bool stop_defers(const Dev<R>& d, int typ, R& T, StepTally& tl)
+{
+    tl.edep += (double)T;
+    T = R(0);
+    if (typ != kPositron) return false;
+    if (kMe >= d.ecut) return true;
+    tl.n_annih += 1;
+    tl.edep += 2.0 * kMe;
+    return false;
+}
+
+// Common end of an along-step (S6-S8) for a step of length step_len: energy
+// loss, the stop, boundary crossing or escape, the choice of the discrete
+// process, the step guard.  Clears `alive` when the track ends and sets the
+// next action; a positron that stops stays alive with A_ANNIH (annihilation
+// at rest, done by the interaction launch), so no along-step creates tracks.
 template <class R, bool CHARGED>
 __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int typ, R& T, R sig, double step_len,
-                                             int face, uint8_t fl, int mat, uint16_t& slab, const double r[3],
-                                             SecBuf<R>& sb, StepTally& tl, const PhysParams& pp, bool& alive,
-                                             uint8_t& next_action, R& nl, uint32_t& step, uint64_t key, uint32_t row)
+                                             int face, uint8_t fl, int mat, uint16_t& slab, StepTally& tl,
+                                             bool& alive, uint8_t& next_action, R& nl, uint32_t& step, uint64_t key,
+                                             uint64_t event, uint32_t row)
 {
     // step, key and row come in registers (loaded with the rest of the
     // track up front); step leaves as the track's step count after this step
@@ -615,14 +662,14 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
             }
         }
         if (stop) {
-            Prim<R> p;
-            p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = key; p.step = k; p.type = typ; p.alive = true;
-            stop_lepton<R>(pp, p, sb, tl);
-            T = R(0);
-            alive = false;
-            next_action = A_NONE;
-            step = k + 1;
-            d.step[s] = step;
+            if (stop_defers(d, typ, T, tl)) {
+                next_action = A_ANNIH;
+            } else {
+                alive = false;
+                next_action = A_NONE;
+                step = k + 1;
+                d.step[s] = step;
+            }
             return;
         }
     }
@@ -647,7 +694,7 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         step = k + 1;
         d.step[s] = step;
     } else {
-        StepRng<R> rng(d.seed, pp.event, key, k, (fl & F_DREW) ? 1 : 0);
+        StepRng<R> rng(d.seed, event, key, k, (fl & F_DREW) ? 1 : 0);
         R U1 = rng.next();
         R sig1;
         Loc<R> l1;
@@ -670,34 +717,39 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         }
     }
     if (alive && step > kMaxSteps && next_action == A_IDLE) {
-        // step guard
+        // step guard: the track stops after this (counted) step; a positron
+        // annihilates at rest with the counted step's index
         atomicAdd(&d.ledger[row].n_guard, 1ull);
-        Prim<R> p;
-        p.T = T; p.u[0] = p.u[1] = p.u[2] = R(0); p.key = key; p.step = step; p.type = typ; p.alive = true;
-        if (typ != kGamma) stop_lepton<R>(pp, p, sb, tl);
-        else tl.edep += (double)T;
-        T = R(0);
-        alive = false;
-        next_action = A_NONE;
+        if (typ == kGamma) {
+            tl.edep += (double)T;
+            T = R(0);
+            alive = false;
+            next_action = A_NONE;
+        } else if (stop_defers(d, typ, T, tl)) {
+            next_action = A_ANNIH;
+            d.flags[s] = (uint8_t)((fl & (uint8_t)~F_PAUSED) | F_COUNTED);
+        } else {
+            alive = false;
+            next_action = A_NONE;
+        }
     }
 }
 
-// Along-step of one straight-line track (photon, or charged without field).
-// Fills the secondaries, the point they start from, the tally row and the
-// slab of the step; `next` is the next action; `retired` the steps of a track
-// that finished (0 while it lives).
+// Along-step of one straight-line track (photon, or charged without field):
+// the new state goes back to the slot and the step's deposit to its tally
+// row; `row` is the track's row, `next` the next action, `retired` the steps
+// of a track that finished (0 while it lives).
 template <class R, bool CHARGED>
-__device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, SecBuf<R>& sb,
-                                                     double r[3], uint32_t& row, uint16_t& slab0, uint8_t& next,
-                                                     uint32_t& retired)
+__device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint32_t& row,
+                                                     uint8_t& next, uint32_t& retired)
 {
     int typ = d.type[s];
     row = d.row[s];
     uint16_t slab = d.slab[s];
-    slab0 = slab;
+    const uint16_t slab0 = slab;
     R T = d.T[s];
     R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
-    r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+    double r[3] = {d.x[s], d.y[s], d.z[s]};
     double s_phys = d.sphys[s];
     uint8_t fl = d.flags[s];
     R sig = d.xs[s];
@@ -717,17 +769,16 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     r[2] = r[2] + st * ud[2];
     if (face != F_NONE) r[face_axis(face)] = face_plane(d.zp, slab, d.W, face);
     StepTally tl = {0.0, 0, 0, 0};
-    PhysParams pp = {d.seed, event, d.ecut};
     bool alive = true;
     uint8_t na = A_IDLE;
     const uint32_t k0 = step;
     const double T_pre = (double)T;
-    finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl, step, key,
+    finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, tl, alive, na, nl, step, key, event,
                              row);
     record_tally(d, row, slab0, tl);
     d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-    if (CHARGED && d.msc && alive) {
-        msc_deflect(d.seed, pp.event, key, k0, T_pre, st, d.x0[mat], ud);
+    if (CHARGED && d.msc && alive && na != A_ANNIH) {
+        msc_deflect(d.seed, event, key, k0, T_pre, st, d.x0[mat], ud);
         d.ux[s] = (R)ud[0]; d.uy[s] = (R)ud[1]; d.uz[s] = (R)ud[2];
     }
     if (alive) {
@@ -750,25 +801,18 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     const uint8_t A = CHARGED ? A_CHARGED : A_NEUTRAL;
     EMS_TRACK_RANGE(d, A)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0, reuse_acc = 0;
+    unsigned long long ret_acc = 0;
     EMS_FOR_TRACKS(d, A, s, act, CHARGED ? W_CHARGED : W_NEUTRAL)
-    SecBuf<R> sb;
-    sb.n = 0;
-    double r[3] = {0.0, 0.0, 0.0};
     uint32_t row = 0;
-    uint16_t slab0 = 0;
     uint8_t next = A_NONE;
     uint32_t retired = 0;
-    if (act) along_straight_track<R, CHARGED>(d, tb, s, sb, r, row, slab0, next, retired);
-    if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab0, r);
-    append_secondaries(d, sb, row, slab0, r);
+    if (act) along_straight_track<R, CHARGED>(d, tb, s, row, next, retired);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
     if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
     flush_count(d, CHARGED ? W_CHARGED : W_NEUTRAL, _work);
     flush_count(d, kStepsSlot + (CHARGED ? W_CHARGED : W_NEUTRAL), ret_acc);
-    flush_count(d, W_REUSE, reuse_acc);
 }
 
 // ---- along-step in a uniform field -------------------------------------------------
@@ -833,17 +877,17 @@ __device__ __forceinline__ void normalize_d(double v[3])
 // whether the step paused (`paused_n`).
 template <class R>
 __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int max_sub,
-                                                  SecBuf<R>& sb, double r[3], uint32_t& row, uint16_t& slab0,
-                                                  uint8_t& next, uint32_t& retired, uint32_t& att, uint32_t& paused_n)
+                                                  uint32_t& row, uint8_t& next, uint32_t& retired, uint32_t& att,
+                                                  uint32_t& paused_n)
 {
     int typ = d.type[s];
     row = d.row[s];
     uint16_t slab = d.slab[s];
-    slab0 = slab;
+    const uint16_t slab0 = slab;
     int mat = d.smat[slab];
     R T = d.T[s];
     double u[3] = {(double)d.ux[s], (double)d.uy[s], (double)d.uz[s]};
-    r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+    double r[3] = {d.x[s], d.y[s], d.z[s]};
     double s_phys = d.sphys[s];
     double s_done = d.sdone[s];
     double h_try = d.htry[s];
@@ -944,15 +988,14 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
         d.nsearch[s] = 0;
         d.flags[s] = fl & (uint8_t)~F_PAUSED;
         StepTally tl = {0.0, 0, 0, 0};
-        PhysParams pp = {d.seed, event, d.ecut};
         bool alive = true;
         uint8_t na = A_IDLE;
         const uint32_t k0 = step;
-        finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, r, sb, tl, pp, alive, na, nl, step,
-                              key, row);
+        finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, tl, alive, na, nl, step, key, event,
+                              row);
         record_tally(d, row, slab0, tl);
-        if (d.msc && alive) {
-            msc_deflect(d.seed, pp.event, key, k0, Td, s_done, d.x0[mat], u);
+        if (d.msc && alive && na != A_ANNIH) {
+            msc_deflect(d.seed, event, key, k0, Td, s_done, d.x0[mat], u);
             d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
         }
         if (alive) {
@@ -980,18 +1023,12 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     extern __shared__ __align__(16) unsigned char ems_lds[];
     EMS_TRACK_RANGE(d, A_FIELD)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0, reuse_acc = 0;
+    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0;
     EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
-    SecBuf<R> sb;
-    sb.n = 0;
-    double r[3] = {0.0, 0.0, 0.0};
     uint32_t row = 0;
-    uint16_t slab0 = 0;
     uint8_t next = A_NONE;
     uint32_t retired = 0, att = 0, paused_n = 0;
-    if (act) along_field_track<R>(d, tb, s, d.max_substeps, sb, r, row, slab0, next, retired, att, paused_n);
-    if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab0, r);
-    append_secondaries(d, sb, row, slab0, r);
+    if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
     sub_acc += att;
@@ -1002,7 +1039,6 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
     flush_count(d, W_SUBSTEPS, sub_acc);
     flush_count(d, W_PAUSED, pause_acc);
-    flush_count(d, W_REUSE, reuse_acc);
 }
 
 // Discrete interaction PROC of one track at the end of its along-step.
@@ -1031,9 +1067,16 @@ __device__ __forceinline__ void interact_track(const Dev<R>& d, uint32_t s, SecB
     case P_PAIR:    sample_pair<R>(pp, p, rng, sb, tl); break;
     case P_MOLLER:  sample_moller<R>(pp, p, rng, sb, tl); break;
     case P_BHABHA:  sample_bhabha<R>(pp, p, rng, sb, tl); break;
-    default:        sample_brems<R>(pp, p, rng, sb, tl); break;
+    case P_BREMS:   sample_brems<R>(pp, p, rng, sb, tl); break;
+    default:
+        // at rest (the kinetic energy was deposited by the along-step)
+        annihilate<R>(pp, p.key, p.step, sb, tl);
+        p.T = R(0);
+        p.alive = false;
+        break;
     }
-    uint32_t steps = p.step + 1;
+    // a step-guard stop was counted by the along-step already
+    uint32_t steps = (PROC == P_ANNIH && (fl & F_COUNTED)) ? p.step : p.step + 1;
     d.step[s] = steps;
     if (p.alive && steps > kMaxSteps) {
         atomicAdd(&d.ledger[row].n_guard, 1ull);
@@ -1077,38 +1120,41 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     flush_count(d, W_REUSE, reuse_acc);
 }
 
-// ---- discrete interactions, all six processes in one launch ------------------------
-// After the reordering at sort point 2 the six interaction actions occupy
-// consecutive index ranges of the permutation (or six lists), so one launch
+// ---- discrete interactions, all seven actions in one launch ------------------------
+// After the reordering at sort point 2 the seven interaction actions (six
+// processes and annihilation at rest) occupy consecutive index ranges of the
+// permutation (or seven lists), so one launch
 // can walk all of them: each wave then holds one process except at the few
 // range boundaries.  The per-track code is that of the per-process kernels;
-// the launch count per iteration drops from six to one.  Unsorted, it masks
+// the launch count per iteration drops from seven to one.  Unsorted, it masks
 // over all slots like the per-process kernels.
 template <class R>
 __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
 {
     const int mode = d.ctr->phase_sorted ? d.sorted2 : 0;
     uint32_t n = d.n_slots, off = 0;
-    uint32_t lc0 = 0, lc1 = 0, lc2 = 0, lc3 = 0, lc4 = 0;
+    uint32_t lc0 = 0, lc1 = 0, lc2 = 0, lc3 = 0, lc4 = 0, lc5 = 0;
     if (mode == 1) {
         off = d.ctr->range_off[A_PROC0];
-        n = d.ctr->range_off[A_PROC0 + 5] + d.ctr->range_cnt[A_PROC0 + 5] - off;
-        // ends of the first five process ranges, relative to the first
+        n = d.ctr->range_off[A_ANNIH] + d.ctr->range_cnt[A_ANNIH] - off;
+        // ends of the first six action ranges, relative to the first
         lc0 = d.ctr->range_off[A_PROC0 + 1] - off;
         lc1 = d.ctr->range_off[A_PROC0 + 2] - off;
         lc2 = d.ctr->range_off[A_PROC0 + 3] - off;
         lc3 = d.ctr->range_off[A_PROC0 + 4] - off;
         lc4 = d.ctr->range_off[A_PROC0 + 5] - off;
+        lc5 = d.ctr->range_off[A_PROC0 + 6] - off;
     } else if (mode == 2) {
         lc0 = d.ctr->list_cnt[A_PROC0];
         lc1 = lc0 + d.ctr->list_cnt[A_PROC0 + 1];
         lc2 = lc1 + d.ctr->list_cnt[A_PROC0 + 2];
         lc3 = lc2 + d.ctr->list_cnt[A_PROC0 + 3];
         lc4 = lc3 + d.ctr->list_cnt[A_PROC0 + 4];
-        n = lc4 + d.ctr->list_cnt[A_PROC0 + 5];
+        lc5 = lc4 + d.ctr->list_cnt[A_PROC0 + 5];
+        n = lc5 + d.ctr->list_cnt[A_PROC0 + 6];
     }
     if (blockIdx.x * blockDim.x >= n) return;
-    unsigned long long w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, ret_acc = 0, reuse_acc = 0;
+    unsigned long long w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, w6 = 0, ret_acc = 0, reuse_acc = 0;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
         bool act = i < n;
@@ -1116,12 +1162,13 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
         uint8_t a = A_NONE;
         if (act) {
             // sorted: the process follows from the position in the ranges
-            const int p = i < lc0 ? 0 : (i < lc1 ? 1 : (i < lc2 ? 2 : (i < lc3 ? 3 : (i < lc4 ? 4 : 5))));
+            const int p = i < lc0 ? 0 : (i < lc1 ? 1 : (i < lc2 ? 2 : (i < lc3 ? 3 : (i < lc4 ? 4 : (i < lc5 ? 5 : 6)))));
             if (mode == 1) {
                 s = d.perm[off + i];
                 a = (uint8_t)(A_PROC0 + p);
             } else if (mode == 2) {
-                uint32_t lo = p == 0 ? 0u : (p == 1 ? lc0 : (p == 2 ? lc1 : (p == 3 ? lc2 : (p == 4 ? lc3 : lc4))));
+                uint32_t lo = p == 0 ? 0u
+                                     : (p == 1 ? lc0 : (p == 2 ? lc1 : (p == 3 ? lc2 : (p == 4 ? lc3 : (p == 5 ? lc4 : lc5)))));
                 s = d.lists[(size_t)(A_PROC0 + p) * d.n_slots + (i - lo)];
                 a = (uint8_t)(A_PROC0 + p);
             } else {
@@ -1129,7 +1176,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
                 a = d.action[s];
             }
         }
-        act = act && a >= A_PROC0 && a < A_PROC0 + 6;
+        act = act && a >= A_PROC0 && a < A_NUM;
         SecBuf<R> sb;
         sb.n = 0;
         double r[3] = {0.0, 0.0, 0.0};
@@ -1143,7 +1190,8 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
             case P_PAIR:    interact_track<R, P_PAIR>(d, s, sb, r, row, slab, retired); ++w2; break;
             case P_MOLLER:  interact_track<R, P_MOLLER>(d, s, sb, r, row, slab, retired); ++w3; break;
             case P_BHABHA:  interact_track<R, P_BHABHA>(d, s, sb, r, row, slab, retired); ++w4; break;
-            default:        interact_track<R, P_BREMS>(d, s, sb, r, row, slab, retired); ++w5; break;
+            case P_BREMS:   interact_track<R, P_BREMS>(d, s, sb, r, row, slab, retired); ++w5; break;
+            default:        interact_track<R, P_ANNIH>(d, s, sb, r, row, slab, retired); ++w6; break;
             }
         }
         if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
@@ -1157,6 +1205,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
     flush_count(d, W_PROC0 + P_MOLLER, w3);
     flush_count(d, W_PROC0 + P_BHABHA, w4);
     flush_count(d, W_PROC0 + P_BREMS, w5);
+    flush_count(d, W_PROC0 + P_ANNIH, w6);
     flush_count(d, kStepsSlot + W_PROC0, ret_acc);
     flush_count(d, W_REUSE, reuse_acc);
 }
@@ -1212,7 +1261,8 @@ __device__ __forceinline__ void drain_interact(const Dev<R>& d, int proc, uint32
     case P_PAIR:    interact_track<R, P_PAIR>(d, s, sb, r, row, slab, retired); break;
     case P_MOLLER:  interact_track<R, P_MOLLER>(d, s, sb, r, row, slab, retired); break;
     case P_BHABHA:  interact_track<R, P_BHABHA>(d, s, sb, r, row, slab, retired); break;
-    default:        interact_track<R, P_BREMS>(d, s, sb, r, row, slab, retired); break;
+    case P_BREMS:   interact_track<R, P_BREMS>(d, s, sb, r, row, slab, retired); break;
+    default:        interact_track<R, P_ANNIH>(d, s, sb, r, row, slab, retired); break;
     }
 }
 
@@ -1242,24 +1292,20 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
             if (d.flags[s] & F_PAUSED) {
                 a = A_FIELD;
             } else {
-                a = pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
+                a = pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s],
+                              false);
             }
-            SecBuf<R> sb;
-            sb.n = 0;
-            double r[3] = {0.0, 0.0, 0.0};
             uint32_t row = 0, retired = 0;
-            uint16_t slab0 = 0;
             uint8_t next = A_NONE;
             if (a == A_NEUTRAL) {
-                along_straight_track<R, false>(d, tb, s, sb, r, row, slab0, next, retired);
+                along_straight_track<R, false>(d, tb, s, row, next, retired);
             } else if (a == A_CHARGED) {
-                along_straight_track<R, true>(d, tb, s, sb, r, row, slab0, next, retired);
+                along_straight_track<R, true>(d, tb, s, row, next, retired);
             } else {
                 // a paused step resumes on the next trip (pausing does not change the result)
                 uint32_t att = 0, paused_n = 0;
-                along_field_track<R>(d, tb, s, kDrainSubsteps, sb, r, row, slab0, next, retired, att, paused_n);
+                along_field_track<R>(d, tb, s, kDrainSubsteps, row, next, retired, att, paused_n);
             }
-            drain_push(d, sb, row, slab0, r, stack, n_threads, t, depth, sp);
             if (next >= A_PROC0 && next < A_NUM) {
                 SecBuf<R> sb2;
                 sb2.n = 0;
@@ -1306,12 +1352,20 @@ __global__ void k_scan_completions(Dev<R> d)
 // Sort key of a slot at a sort point; 0xFF excludes the slot.
 //   keymode 0 (partition): the next action (< 16)
 //   keymode 1 (radix): action << 3 | type << 1 | (material & 1) (< 128)
+//   keymode 2 (partition, field split): the next action, field tracks
+//             replaced by A_FIELD + cost class (< 16)
 template <class R>
 __device__ __forceinline__ uint32_t sort_key(const Dev<R>& d, uint32_t s, int keymode)
 {
     uint8_t a = d.action[s];
     if (a == A_NONE || a == A_IDLE) return 0xFFu;
     if (keymode == 0) return a;
+    if (keymode == 2) {
+        // actions in order, field tracks split by cost class
+        if (a < A_FIELD) return a;
+        if (a > A_FIELD) return a + (kFieldCostBins - 1);
+        return A_FIELD + ((d.flags[s] & F_COST_MASK) >> F_COST_SHIFT);
+    }
     uint32_t t = d.type[s];
     uint32_t m = (uint32_t)d.smat[d.slab[s]] & 1u;
     return ((uint32_t)a << 3) | (t << 1) | m;
@@ -1399,8 +1453,13 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int key
     if (!ext_keys && blockIdx.x == 0 && threadIdx.x < 16) {
         // index range of each action in the sorted permutation
         uint32_t a = threadIdx.x;
-        uint32_t lo_bin = keymode == 0 ? a : a << 3;
-        uint32_t hi_bin = keymode == 0 ? a + 1 : (a + 1) << 3;
+        auto first_bin = [keymode](uint32_t x) -> uint32_t {
+            if (keymode == 1) return x << 3;
+            if (keymode == 2 && x > A_FIELD) return x + (kFieldCostBins - 1);
+            return x;
+        };
+        uint32_t lo_bin = first_bin(a);
+        uint32_t hi_bin = first_bin(a + 1);
         if (lo_bin >= (uint32_t)NB) {
             d.ctr->range_off[a] = bbase[NB];
             d.ctr->range_cnt[a] = 0;

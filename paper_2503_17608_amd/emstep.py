@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 FP64, MIXED = 0, 1
 SORT_NONE, SORT_PARTITION, SORT_RADIX, SORT_QUEUE = 0, 1, 2, 3
 SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX, "queue": SORT_QUEUE}
@@ -52,13 +52,13 @@ class Material(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16),
                 ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32), ("reuse_parent_slot", C.c_uint32),
-                ("fuse_interactions", C.c_uint32)]
+                ("fuse_interactions", C.c_uint32), ("field_sort", C.c_uint32)]
 
 
 class Counters(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("alive", C.c_uint64), ("queued", C.c_uint64),
                 ("pending_primaries", C.c_uint64), ("steps", C.c_uint64), ("overflow", C.c_uint32),
-                ("completed", C.c_uint32), ("work", C.c_uint64 * 16)]
+                ("completed", C.c_uint32), ("work", C.c_uint64 * 24)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "work"}
@@ -68,7 +68,7 @@ class Counters(C.Structure):
 
 WORK_INDEX = {0: "reused_slots", 1: "init", 2: "pre_step", 4: "along_neutral", 5: "along_charged", 6: "along_field",
               7: "compton", 8: "photoelectric", 9: "pair", 10: "moller", 11: "bhabha", 12: "bremsstrahlung",
-              13: "field_paused", 14: "field_substeps", 15: "drain"}
+              13: "annihilation", 14: "field_paused", 15: "field_substeps", 16: "drain"}
 
 
 PRIMARY_DTYPE = np.dtype([
@@ -322,10 +322,11 @@ class Session:
         return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
                 "drain_threshold": t.drain_threshold, "drain_steps": t.drain_steps,
                 "reuse_parent_slot": bool(t.reuse_parent_slot), "fuse_interactions": bool(t.fuse_interactions),
+                "field_sort": bool(t.field_sort),
                 "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
 
     def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None,
-                   reuse_parent_slot=None, fuse_interactions=None):
+                   reuse_parent_slot=None, fuse_interactions=None, field_sort=None):
         """Change knobs that affect speed only; block maps kernel role names to block sizes."""
         cur = Tuning()
         _check(_lib.ems_get_tuning(self._h, C.byref(cur)), "ems_get_tuning")
@@ -341,6 +342,8 @@ class Session:
             cur.reuse_parent_slot = 1 if reuse_parent_slot else 0
         if fuse_interactions is not None:
             cur.fuse_interactions = 1 if fuse_interactions else 0
+        if field_sort is not None:
+            cur.field_sort = 1 if field_sort else 0
         if block is not None:
             for name, b in block.items():
                 cur.block[KERNEL_ROLES.index(name)] = int(b)
@@ -360,7 +363,8 @@ class Session:
 
 
 KERNEL_ROLES = ["vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged", "along_field",
-                "compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "drain", "interactions"]
+                "compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "drain", "interactions",
+                "annihilation"]
 
 
 def role_mask(*names):

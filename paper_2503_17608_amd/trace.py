@@ -19,7 +19,7 @@ import argparse
 import json
 
 ROLE_ORDER = ("vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged", "along_field", "compton",
-              "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "interactions", "drain")
+              "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "annihilation", "interactions", "drain")
 
 
 def record(session, primaries, max_iterations=100_000):

@@ -18,8 +18,9 @@ def session_for(workload, n_slots=None, precision="f64", max_events=None, **kw):
     return s
 
 
-def random_states(workload, n, rng, types=(0, 1, 2), e_max=1000.0, f32=False):
-    """Random single-track states inside the stack (some on planes / near walls)."""
+def random_states(workload, n, rng, types=(0, 1, 2), e_max=1000.0, f32=False, steps=(0, 200)):
+    """Random single-track states inside the stack (some on planes / near walls);
+    step counts uniform in [steps[0], steps[1])."""
     st = workload.stack
     z = st.z_planes
     W = st.half_width
@@ -28,7 +29,7 @@ def random_states(workload, n, rng, types=(0, 1, 2), e_max=1000.0, f32=False):
     t["key"] = rng.integers(0, 2 ** 63, n)
     t["type"] = rng.choice(types, n)
     t["slab"] = rng.integers(0, st.n_slabs, n)
-    t["step"] = rng.integers(0, 200, n)
+    t["step"] = rng.integers(steps[0], steps[1], n)
     t["alive"] = 1
     t["T"] = np.exp(rng.uniform(math.log(workload.ecut * 1.0001), math.log(e_max), n))
     t["nl"] = np.where(rng.uniform(size=n) < 0.5, -1.0, rng.exponential(1.0, n))

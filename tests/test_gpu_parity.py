@@ -75,10 +75,10 @@ def test_sort_permutation_bit_exact(n, policy, nb):
 
 
 # ----------------------------------------------------------------------------- one step
-def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc=False):
+def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc=False, steps=(0, 200)):
     rng = np.random.default_rng(seed)
     f32 = precision == "mixed"
-    states = random_states(w, n, rng, types=types, e_max=e_max, f32=f32)
+    states = random_states(w, n, rng, types=types, e_max=e_max, f32=f32, steps=steps)
     s = session_for(w, n_slots=n, precision=precision, max_events=n, max_substeps=0,
                     n_initializers=4 * n, msc=msc)
     rows = np.array([s.register_event(int(e)) for e in states["event"]], dtype=np.uint32)
@@ -149,6 +149,17 @@ def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc
         if e > tol:
             bad.append((i, "tol", e, res[i]["outcome"], res[i]["process"]))
     return bad, worst
+
+
+@pytest.mark.parametrize("wl", ["nofield", "field"])
+def test_single_step_parity_at_the_step_guard(wl):
+    """Tracks whose step ends past the step limit (10^6): the guard stops them
+    after the along-step or after the interaction; a positron stopped by the
+    guard annihilates at rest with the counted step's index, adding no step."""
+    w = workloads.small_electron_showers(1) if wl == "nofield" else workloads.electron_showers_1gev_field(1)
+    bad, worst = _step_compare(w, 20000, "f64", seed=11, tol=1e-12, e_max=50.0, steps=(999_999, 1_000_001))
+    print("worst", worst, "mismatches", len(bad), bad[:5])
+    assert not bad, bad[:10]
 
 
 @pytest.mark.parametrize("wl", ["nofield", "field"])
@@ -245,6 +256,8 @@ def test_tuning_does_not_change_results():
                    dict(sort_policy="partition", tail_threshold=0, reuse_parent_slot=True),
                    dict(sort_policy="queue", reuse_parent_slot=True, drain_threshold=3000, drain_steps=50),
                    dict(sort_policy="partition", reuse_parent_slot=False, fuse_interactions=True),
+                   dict(sort_policy="partition", field_sort=False, tail_threshold=0),
+                   dict(sort_policy="queue", field_sort=True, tail_threshold=0, block={"along_field": 64}),
                    dict(sort_policy="queue", fuse_interactions=True, drain_threshold=0),
                    dict(sort_policy="none", fuse_interactions=True, block={"interactions": 128}),
                    dict(sort_policy="radix", tail_threshold=2000, fuse_interactions=True, reuse_parent_slot=True)]:
