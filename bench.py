@@ -124,7 +124,6 @@ def parse():
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")
-    ap.add_argument("--field-sort", type=int, default=0, help="first sort splits field tracks by cost class")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=10000, help="oracle sample (events); 0 = skip")
@@ -153,8 +152,7 @@ def make_workload(name, events, slots):
     return w
 
 
-def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None,
-                fsort=None):
+def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
     s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
@@ -166,9 +164,8 @@ def new_session(w, args, precision, policy, init_partition, graph=None, drain=No
     drain = args.drain_threshold if drain is None else drain
     reuse = args.reuse_parent_slot if reuse is None else reuse
     fuse = args.fuse_interactions if fuse is None else fuse
-    fsort = args.field_sort if fsort is None else fsort
     s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse),
-                 fuse_interactions=bool(fuse), field_sort=bool(fsort))
+                 fuse_interactions=bool(fuse))
     return s
 
 
@@ -182,9 +179,8 @@ def time_batch(s, primaries, events):
     return c, time.perf_counter() - t0
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None,
-                fsort=None):
-    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse, fsort=fsort)
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None):
+    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse)
     events = np.unique(w.primaries["event"])
     tuned = None
     if tune is not None:
@@ -413,7 +409,6 @@ def main():
                    "lds_tables": args.lds_tables, "streams": args.streams,
                    "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
                    "reuse_parent_slot": args.reuse_parent_slot, "fuse_interactions": args.fuse_interactions,
-                   "field_sort": args.field_sort,
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
@@ -431,7 +426,7 @@ def main():
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
                "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot,
-               "fuse_interactions": args.fuse_interactions, "field_sort": args.field_sort}
+               "fuse_interactions": args.fuse_interactions}
         t = committed_traffic(prof_kernel, key)
         out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -460,9 +455,6 @@ def main():
             rv = run_variant(w, args, precision, pol, 0, None, fuse=fu)
             tag = f"{pol}+part0" + ("+fused" if fu else "+unfused")
             var[tag] = rv["steps"] / rv["seconds"]
-        fs = 0 if args.field_sort else 1
-        rv = run_variant(w, args, precision, "partition", 0, None, fsort=fs)
-        var["partition+part0" + ("+fieldsort" if fs else "+nofieldsort")] = rv["steps"] / rv["seconds"]
         for k in (4, 8):
             var[f"event_parallel_{k}x{w.n_slots // k}"] = event_parallel_rate(w, args, precision, k)
         out["variants"] = var

@@ -301,13 +301,7 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * of the interaction actions (each wave holds one action except at range
  * boundaries) instead of seven launches on the library's streams; kernel role
  * "interactions" in the block table.
- *
- * field_sort (0/1, default 0; PARTITION and QUEUE policies in a field): the
- * sort after the pre-step splits the field tracks into cost classes (the RK4
- * evaluations the step is expected to take, from its physics limit, momentum
- * and distance to the next z plane), so that the tracks of a wave run their
- * integration loop for similar counts; the field kernel still sees one index
- * range.  The pre-step then also reads position and direction.
+
  * Setting the tuning re-captures graphs on the next run. */
 typedef struct {
     int32_t sort_policy;
@@ -317,7 +311,6 @@ typedef struct {
     uint32_t drain_steps;
     uint32_t reuse_parent_slot;
     uint32_t fuse_interactions;
-    uint32_t field_sort;
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

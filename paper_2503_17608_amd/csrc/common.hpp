@@ -57,17 +57,11 @@ enum : uint8_t {
     F_DREW = 1,        // the interaction-length uniform (index 0) was drawn this step
     F_LOSS = 2,        // the physics step limit is the energy-loss limit
     F_PAUSED = 4,      // field step paused at the substep cap
-    // bits 3-4: cost class of a field step (expected RK4 evaluations minus
-    // one, capped), set by the pre-step to order field tracks at the first sort
-    F_COST_SHIFT = 3,
-    F_COST_MASK = 3 << 3,
     // the stop of a positron waiting for annihilation at rest was counted as
     // a step already (step-guard stop): the annihilation adds no step
     F_COUNTED = 32,
 };
 
-// field tracks form this many sub-bins (cost classes) at the first sort
-constexpr int kFieldCostBins = 4;
 
 // faces of a slab box
 enum : int { F_NONE = 0, F_ZLO, F_ZHI, F_XLO, F_XHI, F_YLO, F_YHI };
@@ -146,14 +140,27 @@ struct Snapshot {
 // as easy as 1, 2, 3", SC'11) ----------------------------------------------------
 struct U64x4 { uint64_t w[4]; };
 
+// Full 64 x 64 -> 128-bit product from four 32 x 32 -> 64-bit partial
+// products (schoolbook), so that the low and high halves share them.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi)
+{
+    const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+    const uint64_t p00 = a0 * b0;
+    const uint64_t p10 = a1 * b0 + (p00 >> 32);          // < 2^64: no carry is lost
+    const uint64_t p01 = a0 * b1 + (uint32_t)p10;        // < 2^64
+    hi = a1 * b1 + (p10 >> 32) + (p01 >> 32);
+    lo = (p01 << 32) | (uint32_t)p00;
+}
+
 __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                                uint64_t k0, uint64_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
-        uint64_t lo0 = m0 * c0, hi0 = __umul64hi(m0, c0);
-        uint64_t lo1 = m1 * c2, hi1 = __umul64hi(m1, c2);
+        uint64_t lo0, hi0, lo1, hi1;
+        mulhilo64(m0, c0, lo0, hi0);
+        mulhilo64(m1, c2, lo1, hi1);
         uint64_t n0 = hi1 ^ c1 ^ k0;
         uint64_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;

@@ -196,7 +196,6 @@ struct ems_ctx {
     uint32_t drain_steps = kDrainStepsDefault;
     uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
     uint32_t fuse_interactions = 0;   // one launch for the six interaction kernels
-    uint32_t field_sort = 0;          // first sort splits field tracks by cost class
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -274,12 +273,6 @@ Dev<R> make_dev(const ems_ctx* c)
     d.tail_threshold = c->tail_threshold;
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
-    d.field_sort = (c->field_sort && d.has_field &&
-                    (c->policy == EMS_SORT_PARTITION || c->policy == EMS_SORT_QUEUE)) ? 1 : 0;
-    {
-        const double bm = sqrt(c->B[0] * c->B[0] + c->B[1] * c->B[1] + c->B[2] * c->B[2]);
-        d.hc_coef = bm > 0.0 ? (float)(8.0 * kDChord / (kCk * bm)) : 0.0f;
-    }
     d.msc = c->opt.msc ? 1 : 0;
     d.x0 = (const double*)(c->ws + c->L.x0);
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
@@ -424,23 +417,20 @@ void join(ems_ctx* c, int point, int k)
     }
 }
 
-// `first`: the sort after the pre-step, where field tracks may be split by
-// cost class (keymode 2); the sort after the along-step orders by action.
 template <class R>
-void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, bool first)
+void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
 {
     const int policy = c->policy;
-    const int km = first && d.field_sort ? 2 : 0;
     uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
     uint32_t* tot = (uint32_t*)(c->ws + c->L.bin_off);
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
     if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
-        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
+        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
              (const uint8_t*)nullptr, n, cnt, nt);
         ln.k(R_SORT, false, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
              tot);
-        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
+        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
     } else {
         ln.k(R_SORT, true, false, k_sort_hist<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1,
@@ -476,7 +466,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
     ln.one(R_PRE, k_pre_step<R>, dim3(G(R_PRE)), dim3(B(R_PRE)), lds, st, d);
-    if (d.sorted == 1) launch_sort<R>(c, d, ln, true);
+    if (d.sorted == 1) launch_sort<R>(c, d, ln);
     // along-step: photons and leptons are independent branches
     const int nw = c->n_streams - 1;
     hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
@@ -489,11 +479,10 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
                st, d);
     if (nw > 0) join(c, 0, 1);
-    if (d.sorted2 == 1) launch_sort<R>(c, d, ln, false);
+    if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
     if (c->fuse_interactions) {
         // all six processes in one launch over the combined index range
         ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
-        hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
         return;
     }
     // interactions: six independent branches spread over the streams
@@ -507,7 +496,6 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     ln.one(R_BREMS, k_interact<R, P_BREMS>, dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d);
     ln.one(R_ANNIH, k_interact<R, P_ANNIH>, dim3(G(R_ANNIH)), dim3(B(R_ANNIH)), 0, on(6), d);
     if (nw > 0) join(c, 1, nw);
-    hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
 }
 
 void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
@@ -534,13 +522,25 @@ void launch_drain(ems_ctx* c, uint32_t threads)
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
     ln.one(R_DRAIN, k_drain<R>, dim3((threads + 255) / 256), dim3(256), lds, st, d, (const uint32_t*)live_list,
            (Initializer*)(c->ws + c->L.drain_stack), threads, kDrainDepth, c->drain_steps);
-    hipLaunchKernelGGL((k_scan_completions<R>), dim3((d.n_rows + 255) / 256), dim3(256), 0, st, d);
 }
 
 void launch_drain_any(ems_ctx* c, uint32_t threads)
 {
     if (c->opt.precision == EMS_MIXED) launch_drain<float>(c, threads);
     else launch_drain<double>(c, threads);
+}
+
+// Record the events whose rows emptied in the iterations launched so far.
+// The host reads completions only between launch groups, so one scan after
+// each group (graph batch, iteration loop or drain launch) finds exactly what
+// a scan after every iteration would.
+void launch_completions(ems_ctx* c)
+{
+    const uint32_t nb = (c->opt.max_events + 255) / 256;
+    if (c->opt.precision == EMS_MIXED)
+        hipLaunchKernelGGL((k_scan_completions<float>), dim3(nb), dim3(256), 0, c->stream, make_dev<float>(c));
+    else
+        hipLaunchKernelGGL((k_scan_completions<double>), dim3(nb), dim3(256), 0, c->stream, make_dev<double>(c));
 }
 
 ems_status check_ready(ems_ctx* c)
@@ -573,6 +573,7 @@ ems_status launch_batch(ems_ctx* c, int iters, bool no_init)
             hipGraph_t g;
             HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             for (int i = 0; i < gi; ++i) launch_iteration_any(c, no_init, false);
+            launch_completions(c);
             HIP_TRY(hipStreamEndCapture(c->stream, &g));
             HIP_TRY(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
             HIP_TRY(hipGraphDestroy(g));
@@ -582,6 +583,7 @@ ems_status launch_batch(ems_ctx* c, int iters, bool no_init)
         HIP_TRY(hipGraphLaunch(c->graph, c->stream));
     } else {
         for (int i = 0; i < iters; ++i) launch_iteration_any(c, no_init, prof);
+        launch_completions(c);
         HIP_TRY(hipGetLastError());
     }
     return EMS_OK;
@@ -1069,6 +1071,7 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
             if (c->drain_threshold > 0 && left < c->drain_threshold) {
                 uint64_t want = align_up(std::max<uint64_t>(2 * left, 256), 256);
                 launch_drain_any(c, (uint32_t)std::min<uint64_t>(want, c->L.drain_threads));
+                launch_completions(c);
                 HIP_TRY(hipGetLastError());
                 launched += 1;
             } else {
@@ -1250,6 +1253,7 @@ ems_status ems_debug_iterate(ems_ctx* c, uint32_t iterations, int32_t no_init)
     ems_status s = check_ready(c);
     if (s != EMS_OK) return s;
     for (uint32_t i = 0; i < iterations; ++i) launch_iteration_any(c, no_init != 0, c->prof_mask != 0);
+    launch_completions(c);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     return EMS_OK;
@@ -1349,7 +1353,6 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
     c->drain_steps = t->drain_steps;
     c->reuse_parent = t->reuse_parent_slot ? 1u : 0u;
     c->fuse_interactions = t->fuse_interactions ? 1u : 0u;
-    c->field_sort = t->field_sort ? 1u : 0u;
     for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
     return drop_graph(c);
 }
@@ -1363,7 +1366,6 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     t->drain_steps = c->drain_steps;
     t->reuse_parent_slot = c->reuse_parent;
     t->fuse_interactions = c->fuse_interactions;
-    t->field_sort = c->field_sort;
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }

@@ -75,8 +75,6 @@ struct Dev {
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
-    int field_sort;         // first sort orders field tracks by cost class
-    float hc_coef;          // squared chord-limited substep per MeV/c of momentum: 8 d_chord / (kCk |B|) [cm^2]
     const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
@@ -456,32 +454,9 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
 // Pre-step of one live, non-paused track (fields loaded by the caller):
 // interaction length, total cross section, physics step limit and the
 // along-step action, which it returns.
-// Cost class of a field step, for ordering only (the step never reads it):
-// the RK4 evaluations it is expected to take, minus one, capped at
-// kFieldCostBins - 1.  Expected: chord-limited substeps over the nearer of the
-// physics limit and the straight-line distance to the slab's z face ahead,
-// plus two for the boundary search when that face is the nearer.  Single
-// precision is enough for a class.
-template <class R>
-__device__ __forceinline__ uint32_t field_cost(const Dev<R>& d, uint32_t s, uint16_t slab, R T, R s_phys)
-{
-    const float uz = (float)d.uz[s];
-    const double z = d.z[s];
-    float dz = INFINITY;
-    if (uz > 0.0f) dz = (float)(d.zp[slab + 1] - z) / uz;
-    else if (uz < 0.0f) dz = (float)(d.zp[slab] - z) / uz;
-    const float Tf = (float)T, sp = (float)s_phys;
-    const float hc = sqrtf(d.hc_coef * sqrtf(Tf * (Tf + 2.0f * (float)kMe)));
-    const bool cross = dz < sp;
-    float n = ceilf(fminf(sp, fmaxf(dz, 0.0f)) / hc);
-    n = fmaxf(n, 1.0f) + (cross ? 2.0f : 0.0f);
-    return (uint32_t)fminf(n, (float)kFieldCostBins) - 1u;
-}
-
 template <class R>
 __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint8_t typ, R T, R nl,
-                                             uint16_t slab, uint32_t row, uint32_t step, uint64_t key,
-                                             bool cost_class)
+                                             uint16_t slab, uint32_t row, uint32_t step, uint64_t key)
 {
     int mat = d.smat[slab];
     uint8_t nf = 0;
@@ -504,7 +479,6 @@ __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& t
         }
     }
     uint8_t na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
-    if (na == A_FIELD && cost_class) nf |= (uint8_t)(field_cost(d, s, slab, T, s_phys) << F_COST_SHIFT);
     d.xs[s] = sig;
     d.sphys[s] = (double)s_phys;
     d.flags[s] = nf;
@@ -547,7 +521,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
         bool paused = act && (fl & F_PAUSED) != 0;
         act = act && !paused;
         work += act ? 1u : 0u;
-        if (act) pre_track(d, tb, s, typ, T, nl, slab, row, step, key, d.field_sort != 0);
+        if (act) pre_track(d, tb, s, typ, T, nl, slab, row, step, key);
     }
     flush_count(d, W_PRE, work);
 }
@@ -1292,8 +1266,7 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
             if (d.flags[s] & F_PAUSED) {
                 a = A_FIELD;
             } else {
-                a = pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s],
-                              false);
+                a = pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
             }
             uint32_t row = 0, retired = 0;
             uint8_t next = A_NONE;
@@ -1352,20 +1325,12 @@ __global__ void k_scan_completions(Dev<R> d)
 // Sort key of a slot at a sort point; 0xFF excludes the slot.
 //   keymode 0 (partition): the next action (< 16)
 //   keymode 1 (radix): action << 3 | type << 1 | (material & 1) (< 128)
-//   keymode 2 (partition, field split): the next action, field tracks
-//             replaced by A_FIELD + cost class (< 16)
 template <class R>
 __device__ __forceinline__ uint32_t sort_key(const Dev<R>& d, uint32_t s, int keymode)
 {
     uint8_t a = d.action[s];
     if (a == A_NONE || a == A_IDLE) return 0xFFu;
     if (keymode == 0) return a;
-    if (keymode == 2) {
-        // actions in order, field tracks split by cost class
-        if (a < A_FIELD) return a;
-        if (a > A_FIELD) return a + (kFieldCostBins - 1);
-        return A_FIELD + ((d.flags[s] & F_COST_MASK) >> F_COST_SHIFT);
-    }
     uint32_t t = d.type[s];
     uint32_t m = (uint32_t)d.smat[d.slab[s]] & 1u;
     return ((uint32_t)a << 3) | (t << 1) | m;
@@ -1453,13 +1418,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int key
     if (!ext_keys && blockIdx.x == 0 && threadIdx.x < 16) {
         // index range of each action in the sorted permutation
         uint32_t a = threadIdx.x;
-        auto first_bin = [keymode](uint32_t x) -> uint32_t {
-            if (keymode == 1) return x << 3;
-            if (keymode == 2 && x > A_FIELD) return x + (kFieldCostBins - 1);
-            return x;
-        };
-        uint32_t lo_bin = first_bin(a);
-        uint32_t hi_bin = first_bin(a + 1);
+        uint32_t lo_bin = keymode == 0 ? a : a << 3;
+        uint32_t hi_bin = keymode == 0 ? a + 1 : (a + 1) << 3;
         if (lo_bin >= (uint32_t)NB) {
             d.ctr->range_off[a] = bbase[NB];
             d.ctr->range_cnt[a] = 0;

@@ -52,7 +52,7 @@ class Material(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16),
                 ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32), ("reuse_parent_slot", C.c_uint32),
-                ("fuse_interactions", C.c_uint32), ("field_sort", C.c_uint32)]
+                ("fuse_interactions", C.c_uint32)]
 
 
 class Counters(C.Structure):
@@ -322,11 +322,10 @@ class Session:
         return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
                 "drain_threshold": t.drain_threshold, "drain_steps": t.drain_steps,
                 "reuse_parent_slot": bool(t.reuse_parent_slot), "fuse_interactions": bool(t.fuse_interactions),
-                "field_sort": bool(t.field_sort),
                 "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
 
     def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None,
-                   reuse_parent_slot=None, fuse_interactions=None, field_sort=None):
+                   reuse_parent_slot=None, fuse_interactions=None):
         """Change knobs that affect speed only; block maps kernel role names to block sizes."""
         cur = Tuning()
         _check(_lib.ems_get_tuning(self._h, C.byref(cur)), "ems_get_tuning")
@@ -342,8 +341,6 @@ class Session:
             cur.reuse_parent_slot = 1 if reuse_parent_slot else 0
         if fuse_interactions is not None:
             cur.fuse_interactions = 1 if fuse_interactions else 0
-        if field_sort is not None:
-            cur.field_sort = 1 if field_sort else 0
         if block is not None:
             for name, b in block.items():
                 cur.block[KERNEL_ROLES.index(name)] = int(b)

@@ -6,8 +6,7 @@ kernel, drain below 65536 tracks), plus degenerate and rejected inputs.
 * 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event against
   the FP64 oracle (integer ledger equal, deposits to 1e-9 of the primary
   energy), for the sort policies none / partition / radix / queue, with
-  parent-slot reuse, and with the seven interaction kernels, no drain and
-  the field tracks split by cost class at the first sort;
+  parent-slot reuse, and with the seven interaction kernels and no drain;
 * 10^4 mixed primaries in a 5 degree cone at 2^20 slots: FP64 per event
   against the oracle, and the mixed-precision run's per-layer mean deposit
   within 0.5 % of the FP64 oracle;
@@ -28,7 +27,7 @@ pytestmark = pytest.mark.gpu
 
 ME = 0.51099895
 BENCH = dict(sort_policy="partition", graph_iterations=8, lds_tables=1, streams=4, max_substeps=10)
-BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True, field_sort=False)
+BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True)
 
 
 def _run(w, events=None, tuning=None, **kw):
@@ -80,13 +79,12 @@ def test_full_size_electron_showers_every_policy():
     assert w.n_events == 10_000 and w.n_slots == 1 << 20
     e_ref, l_ref, steps = run_oracle(w)
     for policy in ("partition", "none", "radix", "queue", "partition+reuse",
-                   "partition+unfused+nodrain+fieldsort"):
+                   "partition+unfused+nodrain"):
         if policy == "partition+reuse":
             edep, led, c = _run(w, sort_policy="partition", tuning=dict(reuse_parent_slot=True))
             assert c["work"]["reused_slots"] > 0 and c["work"]["drain"] > 0
-        elif policy == "partition+unfused+nodrain+fieldsort":
-            edep, led, c = _run(w, sort_policy="partition",
-                                tuning=dict(fuse_interactions=False, drain_threshold=0, field_sort=True))
+        elif policy == "partition+unfused+nodrain":
+            edep, led, c = _run(w, sort_policy="partition", tuning=dict(fuse_interactions=False, drain_threshold=0))
             assert c["work"]["drain"] == 0
         else:
             edep, led, c = _run(w, sort_policy=policy)

@@ -256,8 +256,7 @@ def test_tuning_does_not_change_results():
                    dict(sort_policy="partition", tail_threshold=0, reuse_parent_slot=True),
                    dict(sort_policy="queue", reuse_parent_slot=True, drain_threshold=3000, drain_steps=50),
                    dict(sort_policy="partition", reuse_parent_slot=False, fuse_interactions=True),
-                   dict(sort_policy="partition", field_sort=False, tail_threshold=0),
-                   dict(sort_policy="queue", field_sort=True, tail_threshold=0, block={"along_field": 64}),
+                   dict(sort_policy="queue", tail_threshold=0, block={"along_field": 64}),
                    dict(sort_policy="queue", fuse_interactions=True, drain_threshold=0),
                    dict(sort_policy="none", fuse_interactions=True, block={"interactions": 128}),
                    dict(sort_policy="radix", tail_threshold=2000, fuse_interactions=True, reuse_parent_slot=True)]:
