@@ -272,6 +272,24 @@ def event_parallel_rate(w, args, precision, k, repeats=2):
     return best
 
 
+def measured_copy_gbs(mib=1024, repeats=10):
+    """Device-to-device copy bandwidth on this GPU (bytes read + written per
+    second), the practical counterpart of the HBM peak."""
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(repeats):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    sec = t0.elapsed_time(t1) / 1e3
+    del src, dst
+    return 2.0 * repeats * (mib << 20) / sec / 1e9
+
+
 def path_roofline(work, steps, rate, precision):
     """Whole-path HBM roofline: algorithmic bytes per track-step (every step
     kernel's processed tracks times its per-track field traffic, summed over
@@ -439,6 +457,12 @@ def main():
                                      "(hipExtLaunchKernel) on every launch of the kernel, in one extra pass over "
                                      "the same batch (graph replay off for that pass)"}
     out["path_roofline"] = path_roofline(r["work"], r["steps"], value, precision)
+    copy_gbs = measured_copy_gbs()
+    out["path_roofline"]["measured_copy_gbs"] = copy_gbs
+    out["path_roofline"]["frac_of_measured_copy"] = out["path_roofline"]["achieved"] / copy_gbs
+    if "roofline" in out:
+        out["roofline"]["measured_copy_gbs"] = copy_gbs
+        out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / copy_gbs
     if args.compare:
         var = {}
         for pol, part, dr, ru in [("none", 0, None, None), ("none", 1, None, None), ("partition", 0, None, None),
@@ -455,7 +479,7 @@ def main():
             rv = run_variant(w, args, precision, pol, 0, None, fuse=fu)
             tag = f"{pol}+part0" + ("+fused" if fu else "+unfused")
             var[tag] = rv["steps"] / rv["seconds"]
-        for k in (4, 8):
+        for k in (2, 4, 8, 16):
             var[f"event_parallel_{k}x{w.n_slots // k}"] = event_parallel_rate(w, args, precision, k)
         out["variants"] = var
     if args.layer_error:
