@@ -1184,25 +1184,30 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
     flush_count(d, W_REUSE, reuse_acc);
 }
 
-// ---- drain: history-mode stepping of the last tracks ---------------------------------
+// ---- drain: block-local stepping of the last tracks ---------------------------------
 // When few tracks are left the step loop is bound by per-iteration launch
-// latency, not by work.  In a drain launch each thread takes one live slot and
-// steps its track to the end -- pre-step, along-step and interaction, through
-// the same per-track functions as the action kernels -- then continues with
-// its own secondaries, kept on a small private stack (LIFO, as in a
-// history-based transporter), and stops after `max_steps` steps.  Secondaries
-// that do not fit on the stack, and those left when the thread stops, go to
-// the initializer buffer for the step loop.  Random numbers are keyed by track
+// latency, not by work.  A drain launch steps them without further launches:
+// each block runs its own small step loop in rounds.  Half of a block's
+// threads own occupied slots, half own vacant ones; in every round each
+// thread with a track takes one step -- pre-step, along-step and interaction,
+// through the same per-track functions as the action kernels -- and the
+// secondaries go onto the block's stack (LIFO); at the start of the next round
+// the threads whose slot is vacant take the newest entries.  A sub-shower so
+// spreads over the block's threads instead of one thread stepping it alone.
+// After `max_steps` rounds, or when a block has neither tracks nor entries,
+// the block stops; its stack entries (and any that did not fit) go to the
+// initializer buffer for the step loop.  Random numbers are keyed by track
 // and step, so every track ends exactly as in the step loop.
 
-// Secondaries of one step: onto the private stack while it has room, else to
-// the initializer buffer (append-only while a drain runs).
+// Secondaries of one step onto the block's stack while it has room (`top`
+// counts its entries, in LDS), else to the initializer buffer.
 template <class R>
 __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row, uint16_t slab,
-                                           const double r[3], Initializer* stack, uint32_t n_threads, uint32_t t,
-                                           int depth, int& sp)
+                                           const double r[3], Initializer* bstack, int cap, int* top)
 {
-    sb.each([&](const Sec<R>& v, int) {
+    if (sb.n == 0) return;
+    const int pos = atomicAdd(top, sb.n);
+    sb.each([&](const Sec<R>& v, int k) {
         Initializer rec;
         rec.T = (double)v.T;
         rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
@@ -1214,15 +1219,31 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
         rec.pad = 0;
         atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
         atomicAdd(&d.live[row], 1u);
-        if (sp < depth) {
-            stack[(size_t)sp * n_threads + t] = rec;
-            ++sp;
+        if (pos + k < cap) {
+            bstack[pos + k] = rec;
         } else {
             unsigned long long q = atomicAdd(&d.ctr->queue_size, 1ull);
             if (q < d.queue_cap) d.queue[q] = rec;
             else atomicOr(&d.ctr->overflow, 1u);
         }
     });
+}
+
+// Exclusive rank of a true flag among the block's threads, and their total.
+// Contains a barrier (all threads of the block must call it).
+__device__ __forceinline__ uint32_t block_rank(bool f, uint32_t* wcnt, uint32_t& total)
+{
+    const uint64_t m = __ballot(f);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (lane_id() == 0) wcnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t r = rank_below(m), tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) r += wcnt[i];
+        tot += wcnt[i];
+    }
+    total = tot;
+    return r;
 }
 
 template <class R>
@@ -1240,28 +1261,51 @@ __device__ __forceinline__ void drain_interact(const Dev<R>& d, int proc, uint32
     }
 }
 
-// Thread t takes the t-th live slot: first the slots alive before this
-// iteration's fill (listed by the vacancy pass), then the slots just filled.
+// Slots: O = the occupied ones (listed by the vacancy pass, then the
+// vacancies just filled), E = the vacancies left empty.  In block b, thread i
+// < 128 owns O[128 b + i] and thread 128 + i owns E[128 b + i] (when they
+// exist), so every block has tracks and room for their secondaries.
 template <class R>
 __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_list, Initializer* stack,
                                                uint32_t n_threads, int depth, uint32_t max_steps)
 {
     extern __shared__ __align__(16) unsigned char ems_lds[];
+    __shared__ int top;
+    __shared__ uint32_t wcnt[4];
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n_old = d.ctr->alive_before;
-    const uint32_t n_new = d.ctr->n_take_q + d.ctr->n_take_p;
+    const uint32_t n_take = d.ctr->n_take_q + d.ctr->n_take_p;
+    const uint32_t n_occ = n_old + n_take;
+    const uint32_t n_empty = d.ctr->n_vac - n_take;
+    const int cap = depth * (int)blockDim.x;
+    Initializer* bstack = stack + (size_t)blockIdx.x * cap;
+    const uint32_t half = blockDim.x / 2;
+    const uint32_t j = blockIdx.x * half + (threadIdx.x % half);
+    bool owns = blockIdx.x * blockDim.x + threadIdx.x < n_threads;
+    uint32_t s = 0;
+    if (threadIdx.x < half) {
+        owns = owns && j < n_occ;
+        if (owns) s = j < n_old ? live_list[j] : d.vac[j - n_old];
+    } else {
+        owns = owns && j < n_empty;
+        if (owns) s = d.vac[n_take + j];
+    }
     unsigned long long ret_acc = 0, work = 0;
-    if (t < n_threads && t < n_old + n_new) {
-        const uint32_t s = t < n_old ? live_list[t] : d.vac[t - n_old];
-        int sp = 0;
-        for (uint32_t k = 0; k < max_steps; ++k) {
-            if (d.type[s] == kDead) {
-                if (sp == 0) break;
-                --sp;
-                const Initializer rec = stack[(size_t)sp * n_threads + t];
-                init_slot(d, s, rec);
-            }
+    if (threadIdx.x == 0) top = 0;
+    __syncthreads();
+    for (uint32_t k = 0; k < max_steps; ++k) {
+        // threads with a vacant slot take the newest entries of the stack
+        const bool idle = owns && d.type[s] == kDead;
+        uint32_t n_idle = 0;
+        const uint32_t rank = block_rank(idle, wcnt, n_idle);
+        const int avail = top;
+        if (idle && (int)rank < avail) init_slot(d, s, bstack[avail - 1 - (int)rank]);
+        __syncthreads();
+        if (threadIdx.x == 0) top = avail - ((int)n_idle < avail ? (int)n_idle : avail);
+        // no track left in the block: then its stack is empty too
+        const bool live = owns && d.type[s] != kDead;
+        if (!__syncthreads_or(live)) break;
+        if (live) {
             uint8_t a;
             if (d.flags[s] & F_PAUSED) {
                 a = A_FIELD;
@@ -1275,17 +1319,17 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
             } else if (a == A_CHARGED) {
                 along_straight_track<R, true>(d, tb, s, row, next, retired);
             } else {
-                // a paused step resumes on the next trip (pausing does not change the result)
+                // a paused step resumes in the next round (pausing does not change the result)
                 uint32_t att = 0, paused_n = 0;
                 along_field_track<R>(d, tb, s, kDrainSubsteps, row, next, retired, att, paused_n);
             }
             if (next >= A_PROC0 && next < A_NUM) {
-                SecBuf<R> sb2;
-                sb2.n = 0;
-                double r2[3] = {0.0, 0.0, 0.0};
-                uint16_t slab2 = 0;
-                drain_interact<R>(d, next - A_PROC0, s, sb2, r2, row, slab2, retired);
-                drain_push(d, sb2, row, slab2, r2, stack, n_threads, t, depth, sp);
+                SecBuf<R> sb;
+                sb.n = 0;
+                double r[3] = {0.0, 0.0, 0.0};
+                uint16_t slab = 0;
+                drain_interact<R>(d, next - A_PROC0, s, sb, r, row, slab, retired);
+                drain_push(d, sb, row, slab, r, bstack, cap, &top);
             }
             if (retired) {
                 leave_event(d, true, row);
@@ -1293,14 +1337,16 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
             }
             ++work;
         }
-        // what is left on the stack goes back to the step loop
-        while (sp > 0) {
-            --sp;
-            const Initializer rec = stack[(size_t)sp * n_threads + t];
-            unsigned long long q = atomicAdd(&d.ctr->queue_size, 1ull);
-            if (q < d.queue_cap) d.queue[q] = rec;
-            else atomicOr(&d.ctr->overflow, 1u);
-        }
+        __syncthreads();
+        if (threadIdx.x == 0 && top > cap) top = cap;     // the excess went to the initializer buffer
+        __syncthreads();
+    }
+    // what is left on the stack goes back to the step loop
+    const int left = top;
+    for (int i = threadIdx.x; i < left; i += blockDim.x) {
+        unsigned long long q = atomicAdd(&d.ctr->queue_size, 1ull);
+        if (q < d.queue_cap) d.queue[q] = bstack[i];
+        else atomicOr(&d.ctr->overflow, 1u);
     }
     flush_count(d, W_DRAIN, work);
     flush_count(d, kStepsSlot + W_DRAIN, ret_acc);
