@@ -457,12 +457,14 @@ def main():
                                      "(hipExtLaunchKernel) on every launch of the kernel, in one extra pass over "
                                      "the same batch (graph replay off for that pass)"}
     out["path_roofline"] = path_roofline(r["work"], r["steps"], value, precision)
-    copy_gbs = measured_copy_gbs()
-    out["path_roofline"]["measured_copy_gbs"] = copy_gbs
-    out["path_roofline"]["frac_of_measured_copy"] = out["path_roofline"]["achieved"] / copy_gbs
-    if "roofline" in out:
-        out["roofline"]["measured_copy_gbs"] = copy_gbs
-        out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / copy_gbs
+    if not args.no_roofline and args.calibrate_copy_mib == 0:
+        # (counter runs leave it out: their only copies are the calibration's)
+        copy_gbs = measured_copy_gbs()
+        out["path_roofline"]["measured_copy_gbs"] = copy_gbs
+        out["path_roofline"]["frac_of_measured_copy"] = out["path_roofline"]["achieved"] / copy_gbs
+        if "roofline" in out:
+            out["roofline"]["measured_copy_gbs"] = copy_gbs
+            out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / copy_gbs
     if args.compare:
         var = {}
         for pol, part, dr, ru in [("none", 0, None, None), ("none", 1, None, None), ("partition", 0, None, None),

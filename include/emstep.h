@@ -285,11 +285,13 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  *
  * Drain (ems_run only; 0 = off): once the latest counter snapshot shows fewer
  * than drain_threshold tracks alive, queued or pending, each further
- * iteration fills the vacant slots and then runs one history-mode kernel: a
- * thread per occupied slot steps its track and then that track's secondaries
- * (a private stack of 8; the rest go back to the initializer buffer) for up
- * to drain_steps steps (> 0).  It removes the per-iteration launch latency of
- * the last, nearly empty iterations; the physics is the same per-track code.
+ * iteration fills the vacant slots and then runs one kernel in which every
+ * block steps its own tracks in rounds, for up to drain_steps rounds (> 0):
+ * half of a block's threads own occupied slots and half vacant ones,
+ * secondaries go onto the block's stack of 2048 records and threads with a
+ * vacant slot take them (the rest go back to the initializer buffer).  It
+ * removes the per-iteration launch latency of the last, nearly empty
+ * iterations; the physics is the same per-track code.
  *
  * reuse_parent_slot (0/1): a track that ends in a step hands its slot to its
  * first secondary directly, instead of through the initializer buffer and the
