@@ -273,11 +273,13 @@ def test_tuning_does_not_change_results():
 
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
 def test_drain_mode_matches_step_loop_and_oracle(precision):
-    """History-mode drain of the last tracks gives the step loop's results:
-    every track is stepped by the same per-track code with the same keyed
-    random numbers, whatever the threshold, the per-launch step budget (small
-    budgets stop threads mid-shower and hand their stacks back) or the
-    slot count."""
+    """The block-local drain of the last tracks gives the step loop's
+    results: every track is stepped by the same per-track code with the same
+    keyed random numbers, whatever the threshold, the per-launch round budget
+    (small budgets stop blocks mid-shower and hand their stacks back) or the
+    slot count.  Draining from the start (threshold 2^30) puts whole 1 GeV
+    showers into one block, so its stack overflows into the initializer
+    buffer."""
     w = workloads.electron_showers_1gev_field(30, n_slots=1 << 15)
     ref_e, ref_l, ref_c = _run_lib(w, precision=precision, sort_policy="partition", graph_iterations=4)
     if precision == "f64":
