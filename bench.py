@@ -10,7 +10,7 @@ Default workload: 10^4 electrons of 1 GeV into a 50-layer Pb (2 mm) / liquid
 Ar (5 mm) stack, 40 x 40 cm, uniform 1 T field along x, 0.1 MeV cut, 2^20
 track slots, FP64, slots sorted by next action, iterations replayed from
 captured HIP graphs, the interaction kernels fused into one launch, the
-last tracks (below 65536 alive, queued or pending) stepped in history mode by
+last tracks (below 65536 alive, queued or pending) stepped in block-local loops by
 the drain kernel.
 
 The JSON line carries the dominant kernel's roofline: algorithmic bytes per
@@ -120,7 +120,7 @@ def parse():
     ap.add_argument("--lds-tables", type=int, default=1)
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--drain-threshold", type=int, default=65536,
-                    help="run the last tracks in history mode below this many live+queued+pending (0 = off)")
+                    help="drain the last tracks in block-local loops below this many live+queued+pending (0 = off)")
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")

@@ -23,7 +23,7 @@
  *     management");
  *   - on top of the paper's loop: FP32 energies and directions (mixed
  *     precision), continuous batching of events (serving), run-time tuning,
- *     one fused launch for the interaction kernels, and a history-mode drain
+ *     one fused launch for the interaction kernels, and a block-local drain
  *     of the last tracks.
  *
  * The caller's sequence follows the statement of the problem: load geometry,

@@ -11,7 +11,7 @@ tuner may try them on a sample of the real workload:
 3. tail threshold: the live-track count below which an iteration skips the
    reordering and runs masked (the "per step phase" choice), timed end to end;
 4. fused or per-process interaction kernels, and the drain threshold below
-   which the last tracks run in history mode, timed end to end.
+   which the last tracks are drained in block-local loops, timed end to end.
 
 Results can be cached in a JSON file keyed by a workload signature.
 """

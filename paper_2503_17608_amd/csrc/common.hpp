@@ -124,7 +124,7 @@ constexpr int kNumWork = W_DRAIN + 1;
 constexpr int kStepsSlot = kNumWork;
 constexpr int kNumW = 2 * kNumWork;
 static_assert(W_DRAIN < kNumWork, "work counter slots");
-constexpr uint32_t kDrainThreadsMax = 1u << 16;   // drain kernel threads (each with a private stack)
+constexpr uint32_t kDrainThreadsMax = 1u << 16;   // drain kernel threads (8 stack records each, per block)
 constexpr int kDrainDepth = 8;                     // private secondary stack depth per drain thread
 constexpr uint32_t kDrainStepsDefault = 4096;      // steps per drain thread and launch
 constexpr int kDrainSubsteps = 1024;               // field substeps per drain trip before a pause

@@ -4,10 +4,10 @@
 // algorithm"); each iteration launches, in stream order:
 //   vacancy count / scatter  -> initialization (optionally partitioned)
 //   -> pre-step -> [sort point 1] -> along-step (neutral, charged, field)
-//   -> [sort point 2] -> six interaction kernels, or one fused launch
-//   -> completion scan.
+//   -> [sort point 2] -> seven interaction kernels, or one fused launch;
+// after each launch group, a completion scan.
 // Below a live-track threshold ems_run replaces the iteration by a fill and
-// one history-mode drain launch.  Loop termination is read from device
+// one drain launch (block-local step loops).  Loop termination is read from device
 // counters copied asynchronously to a pinned host buffer after every batch of
 // iterations; batches can be captured once into a HIP graph and replayed.  No
 // synchronous memory operation is issued inside the loop (paper,
@@ -63,7 +63,7 @@ struct Layout {
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
     uint64_t drain_stack, regs, x0, rowsum;
     uint32_t part_stride;
-    uint32_t drain_threads;   // capacity of the drain kernel (threads with a private stack)
+    uint32_t drain_threads;   // capacity of the drain kernel (threads; 8 stack records each)
     uint64_t total;
     uint32_t n_tiles;
 };
@@ -195,7 +195,7 @@ struct ems_ctx {
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
     uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
-    uint32_t fuse_interactions = 0;   // one launch for the six interaction kernels
+    uint32_t fuse_interactions = 0;   // one launch for the seven interaction kernels
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -481,11 +481,11 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     if (nw > 0) join(c, 0, 1);
     if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
     if (c->fuse_interactions) {
-        // all six processes in one launch over the combined index range
+        // all seven actions in one launch over the combined index range
         ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
         return;
     }
-    // interactions: six independent branches spread over the streams
+    // interactions: seven independent branches spread over the streams
     if (nw > 0) fork(c, 1, nw);
     auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
     ln.one(R_COMPTON, k_interact<R, P_COMPTON>, dim3(G(R_COMPTON)), dim3(B(R_COMPTON)), 0, on(0), d);
@@ -505,8 +505,8 @@ void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
 }
 
 // One drain iteration: vacancies (and the list of occupied slots), fill from
-// the initializer buffer and the pending primaries, then one history-mode
-// launch over the occupied slots.
+// the initializer buffer and the pending primaries, then one drain launch in
+// which every block steps its share of the slots in rounds.
 template <class R>
 void launch_drain(ems_ctx* c, uint32_t threads)
 {
@@ -1065,7 +1065,7 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
     while (!finished) {
         if (launched < max_iterations) {
             // below the drain threshold (as of the latest snapshot) the rest
-            // of the work runs in history mode, one drain iteration at a time
+            // of the work is drained, one drain iteration at a time
             uint64_t left = have_done ? (uint64_t)done.n_alive + done.queue_size + (done.prim_end - done.prim_next)
                                       : UINT64_MAX;
             if (c->drain_threshold > 0 && left < c->drain_threshold) {
