@@ -2,7 +2,9 @@
 
 The knobs change speed only -- the physics results do not depend on them
 (random numbers are keyed by track, not by slot or launch shape) -- so the
-tuner may try them on a sample of the real workload:
+tuner may try them on the real workload, or on a sample that fills the slots
+as the real workload does (a small fraction of the events does not: at low
+occupancy masked stepping and no drain look best):
 
 1. block sizes: the sample runs once per candidate block size with every
    step kernel at that size and per-kernel HIP-event timing on; each kernel
