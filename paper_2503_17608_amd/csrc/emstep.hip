@@ -274,6 +274,9 @@ Dev<R> make_dev(const ems_ctx* c)
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.msc = c->opt.msc ? 1 : 0;
+    d.pre_hist = (d.sorted == 1 && (c->policy == EMS_SORT_PARTITION || c->policy == EMS_SORT_QUEUE)) ? 1 : 0;
+    d.tile_cnt = (uint32_t*)(b + L.sort_cnt);
+    d.n_tiles = L.n_tiles;
     d.x0 = (const double*)(c->ws + c->L.x0);
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
@@ -417,8 +420,10 @@ void join(ems_ctx* c, int point, int k)
     }
 }
 
+// `counted`: the per-tile histograms are already in place (the pre-step
+// writes those of the first sort)
 template <class R>
-void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
+void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, bool counted)
 {
     const int policy = c->policy;
     uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
@@ -426,9 +431,10 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln)
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
     if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
-        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
-             (const uint8_t*)nullptr, n, cnt, nt);
-        ln.k(R_SORT, false, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
+        if (!counted)
+            ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
+                 (const uint8_t*)nullptr, n, cnt, nt);
+        ln.k(R_SORT, counted, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
              tot);
         ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
@@ -465,8 +471,8 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         }
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
-    ln.one(R_PRE, k_pre_step<R>, dim3(G(R_PRE)), dim3(B(R_PRE)), lds, st, d);
-    if (d.sorted == 1) launch_sort<R>(c, d, ln);
+    ln.one(R_PRE, k_pre_step<R>, dim3(d.pre_hist ? d.n_tiles : G(R_PRE)), dim3(B(R_PRE)), lds, st, d);
+    if (d.sorted == 1) launch_sort<R>(c, d, ln, d.pre_hist != 0);
     // along-step: photons and leptons are independent branches
     const int nw = c->n_streams - 1;
     hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
@@ -479,7 +485,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
                st, d);
     if (nw > 0) join(c, 0, 1);
-    if (d.sorted2 == 1) launch_sort<R>(c, d, ln);
+    if (d.sorted2 == 1) launch_sort<R>(c, d, ln, false);
     if (c->fuse_interactions) {
         // all seven actions in one launch over the combined index range
         ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);

@@ -75,6 +75,9 @@ struct Dev {
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
+    int pre_hist;           // the pre-step walks the sort tiles and writes their action histograms
+    uint32_t* tile_cnt;     // per-tile counts of the first sort: [16 bins][n_tiles]
+    uint32_t n_tiles;
     const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
@@ -94,6 +97,8 @@ __device__ __forceinline__ Tables<R> block_tables(const Dev<R>& d, R* lds)
 }
 
 constexpr int kVacBlock = 1024;   // slots per block of the vacancy and init kernels
+constexpr int kSortThreads = 256;
+constexpr int kSortTile = 1024;      // slots per sort block (also a pre-step block when it counts for the sort)
 constexpr int kStepMaxBlock = 512;  // block-size bound of the step kernels (lets them keep state in VGPRs)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -487,17 +492,30 @@ __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& t
 }
 
 // ---- pre-step: interaction length, physics step limit, along-step action -----------
+// With pre_hist set, block b walks the slots of sort tile b (kSortTile slots)
+// and writes the tile's histogram of the new actions (the first sort's keys)
+// to tile_cnt, so that the first sort needs no counting pass of its own;
+// otherwise the blocks stride over all slots.
 template <class R>
 __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
 {
     extern __shared__ __align__(16) unsigned char ems_lds[];
+    __shared__ uint32_t h[16];
     const uint32_t n = d.n_slots;
-    if (blockIdx.x * blockDim.x >= n) return;
+    const bool tiles = d.pre_hist != 0;
+    if (!tiles && blockIdx.x * blockDim.x >= n) return;
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    const uint32_t first = tiles ? blockIdx.x * kSortTile : blockIdx.x * blockDim.x;
+    const uint32_t last = tiles ? (first + kSortTile < n ? first + kSortTile : n) : n;
+    const uint32_t stride = tiles ? blockDim.x : gridDim.x * blockDim.x;
+    if (tiles) {
+        if (threadIdx.x < 16) h[threadIdx.x] = 0;
+        __syncthreads();
+    }
     unsigned long long work = 0;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    for (uint32_t base = first; base < last; base += stride) {
         uint32_t i = base + threadIdx.x;
-        bool act = i < n;
+        bool act = i < last;
         uint32_t s = 0;
         if (act) s = i;
         // issue every load of the slot up front (all in bounds for a valid
@@ -521,7 +539,13 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
         bool paused = act && (fl & F_PAUSED) != 0;
         act = act && !paused;
         work += act ? 1u : 0u;
-        if (act) pre_track(d, tb, s, typ, T, nl, slab, row, step, key);
+        uint8_t a = paused ? (uint8_t)A_FIELD : (uint8_t)A_NONE;   // a paused step keeps its action
+        if (act) a = pre_track(d, tb, s, typ, T, nl, slab, row, step, key);
+        if (tiles && a != A_NONE) atomicAdd(&h[a], 1u);
+    }
+    if (tiles) {
+        __syncthreads();
+        if (threadIdx.x < 16) d.tile_cnt[threadIdx.x * d.n_tiles + blockIdx.x] = h[threadIdx.x];
     }
     flush_count(d, W_PRE, work);
 }
@@ -1382,8 +1406,6 @@ __device__ __forceinline__ uint32_t sort_key(const Dev<R>& d, uint32_t s, int ke
     return ((uint32_t)a << 3) | (t << 1) | m;
 }
 
-constexpr int kSortThreads = 256;
-constexpr int kSortTile = 1024;      // slots per sort block
 
 // Per-tile histogram: cnt[bin * n_tiles + tile]
 template <class R, int NB>
