@@ -1522,7 +1522,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int key
         if (valid) {
             uint32_t pos = run[key] + my_rank;
             for (int k = 0; k < w; ++k) pos += wc[k][key];
-            perm[pos] = i;
+            if (pos < n) perm[pos] = i;     // always in range when the tile counts match the keys
         }
         __syncthreads();
         for (int b = threadIdx.x; b < NB; b += kSortThreads) {
