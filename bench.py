@@ -46,16 +46,19 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per processed track for each kernel: the SoA fields a
 # participating track reads and writes (FP64 / mixed widths), plus 16 B of
-# tally read-modify-write for charged steps.  E.g. the field along-step reads
-# type, flags, search count (3), slab (2), row, step (8), key (8), T, n_lambda,
-# Sigma (24 / 12), s_phys, s_done, h_try (24), r (24) and u (24 / 12):
-# 117 / 93 B; it writes r, u, T, n_lambda, s_done, h_try, search, flags, slab,
-# action and step: 89 / 69 B; with the deposit 222 / 178 B.
+# tally read-modify-write for charged steps.  The along-step kernels run the
+# pre-step first: it reads fields the step reads anyway and writes n_lambda,
+# Sigma, s_phys, flags and action (26 / 18 B), which are counted here.  E.g.
+# the field along-step reads type, flags, search count (3), slab (2), row,
+# step (8), key (8), T, n_lambda, Sigma (24 / 12), s_phys, s_done, h_try (24),
+# r (24) and u (24 / 12): 117 / 93 B; it writes r, u, T, n_lambda, s_done,
+# h_try, search, flags, slab, action and step: 89 / 69 B; with the deposit
+# and the pre-step's writes 248 / 196 B.
 BYTES_PER_TRACK = {
-    "f64": {"pre_step": 62, "along_neutral": 148, "along_charged": 164, "along_field": 222,
+    "f64": {"along_neutral": 174, "along_charged": 190, "along_field": 248,
             "compton": 122, "photoelectric": 122, "pair": 122, "moller": 122, "bhabha": 122,
             "bremsstrahlung": 122, "annihilation": 122, "init": 206},
-    "mixed": {"pre_step": 46, "along_neutral": 124, "along_charged": 140, "along_field": 178,
+    "mixed": {"along_neutral": 142, "along_charged": 158, "along_field": 196,
               "compton": 102, "photoelectric": 102, "pair": 102, "moller": 102, "bhabha": 102,
               "bremsstrahlung": 102, "annihilation": 102, "init": 174},
 }
@@ -294,11 +297,11 @@ def path_roofline(work, steps, rate, precision):
     """Whole-path HBM roofline: algorithmic bytes per track-step (every step
     kernel's processed tracks times its per-track field traffic, summed over
     the batch, divided by the steps) times track-steps/s, against the HBM
-    peak.  A drain trip counts as a pre-step plus a field along-step (its
+    peak.  A drain trip counts as a field along-step with its pre-step (its
     interactions are not counted)."""
     bpt = BYTES_PER_TRACK[precision]
     total = sum(work.get(k, 0) * b for k, b in bpt.items())
-    total += work.get("drain", 0) * (bpt["pre_step"] + bpt["along_field"])
+    total += work.get("drain", 0) * bpt["along_field"]
     b_step = total / max(steps, 1)
     achieved = rate * b_step / 1e9
     return {"bound": "hbm", "bytes_per_step": b_step, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -277,7 +277,8 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
 
 /* Run-time tuning (the autotuner's knobs; results do not depend on them).
  * block[i] is the block size of kernel role i (role order as returned by
- * ems_profile_read: vacancies, init, pre_step, sort, along_neutral,
+ * ems_profile_read: vacancies, init, pre_step (unused: the along-step
+ * kernels run the pre-step), sort, along_neutral,
  * along_charged, along_field, compton, photoelectric, pair, moller, bhabha,
  * bremsstrahlung, drain, interactions, annihilation); 0 keeps
  * ems_options.block_size.  Below tail_threshold live tracks an iteration

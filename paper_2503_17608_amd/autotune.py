@@ -29,7 +29,7 @@ import numpy as np
 from . import emstep
 
 BLOCK_CANDIDATES = (64, 128, 256, 512)
-STEP_ROLES = ("pre_step", "along_neutral", "along_charged", "along_field", "compton", "photoelectric", "pair",
+STEP_ROLES = ("along_neutral", "along_charged", "along_field", "compton", "photoelectric", "pair",
               "moller", "bhabha", "bremsstrahlung", "annihilation", "interactions")
 
 

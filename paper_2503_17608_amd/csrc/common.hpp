@@ -39,8 +39,9 @@ enum : uint8_t { kGamma = 0, kElectron = 1, kPositron = 2, kDead = 3 };
 // positron that stopped in its along-step; it is not chosen by cross section)
 enum : int { P_COMPTON = 0, P_PHOTO, P_PAIR, P_MOLLER, P_BHABHA, P_BREMS, P_ANNIH, kNumProc };
 
-// Next-action codes (the sort key).  Along-step actions are set by the
-// pre-step kernel, interaction actions by the along-step kernels.
+// Next-action codes (the sort key).  The along-step action follows from the
+// particle type and the field; interaction actions are set by the along-step
+// kernels.
 enum : uint8_t {
     A_IDLE = 0,        // alive, no work this phase
     A_NEUTRAL = 1,     // straight-line along-step of a photon

@@ -3,7 +3,8 @@
 // The host runs the outer loop of step iterations (paper, "Stepping
 // algorithm"); each iteration launches, in stream order:
 //   vacancy count / scatter  -> initialization (optionally partitioned)
-//   -> pre-step -> [sort point 1] -> along-step (neutral, charged, field)
+//   -> [sort point 1, by the along-step action of each type]
+//   -> pre-step and along-step (neutral, charged, field; one kernel each)
 //   -> [sort point 2] -> seven interaction kernels, or one fused launch;
 // after each launch group, a completion scan.
 // Below a live-track threshold ems_run replaces the iteration by a fill and
@@ -137,7 +138,8 @@ Layout make_layout(const ems_options& o)
 }
 
 enum Role {
-    R_VAC = 0, R_INIT, R_PRE, R_SORT, R_ALONG_NEUTRAL, R_ALONG_CHARGED, R_ALONG_FIELD,
+    R_VAC = 0, R_INIT, R_PRE /* reserved: the pre-step runs in the along-step kernels */, R_SORT, R_ALONG_NEUTRAL,
+    R_ALONG_CHARGED, R_ALONG_FIELD,
     R_COMPTON, R_PHOTO, R_PAIR, R_MOLLER, R_BHABHA, R_BREMS, R_DRAIN, R_INTERACT_ALL, R_ANNIH, R_NUM
 };
 const char* kRoleNames[R_NUM] = {"vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged",
@@ -274,9 +276,6 @@ Dev<R> make_dev(const ems_ctx* c)
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.msc = c->opt.msc ? 1 : 0;
-    d.pre_hist = (d.sorted == 1 && (c->policy == EMS_SORT_PARTITION || c->policy == EMS_SORT_QUEUE)) ? 1 : 0;
-    d.tile_cnt = (uint32_t*)(b + L.sort_cnt);
-    d.n_tiles = L.n_tiles;
     d.x0 = (const double*)(c->ws + c->L.x0);
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
@@ -420,10 +419,10 @@ void join(ems_ctx* c, int point, int k)
     }
 }
 
-// `counted`: the per-tile histograms are already in place (the pre-step
-// writes those of the first sort)
+// km: the key mode of the partition (0: next action; 2: the along-step
+// action from the type, for the first sort); radix uses the matching 1 or 3
 template <class R>
-void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, bool counted)
+void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, int km)
 {
     const int policy = c->policy;
     uint32_t* cnt = (uint32_t*)(c->ws + c->L.sort_cnt);
@@ -431,19 +430,19 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, bool counted)
     uint32_t nt = c->L.n_tiles;
     uint32_t n = d.n_slots;
     if (policy == EMS_SORT_PARTITION || policy == EMS_SORT_QUEUE) {
-        if (!counted)
-            ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
-                 (const uint8_t*)nullptr, n, cnt, nt);
-        ln.k(R_SORT, counted, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
+        ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
+             (const uint8_t*)nullptr, n, cnt, nt);
+        ln.k(R_SORT, false, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
              tot);
-        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0,
+        ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
     } else {
-        ln.k(R_SORT, true, false, k_sort_hist<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1,
+        const int km1 = km == 2 ? 3 : 1;
+        ln.k(R_SORT, true, false, k_sort_hist<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km1,
              (const uint8_t*)nullptr, n, cnt, nt);
         ln.k(R_SORT, false, false, k_sort_scan<128>, dim3(128), dim3(256), 0, c->stream, cnt, nt,
              (const Counters*)d.ctr, tot);
-        ln.k(R_SORT, false, true, k_sort_scatter<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1,
+        ln.k(R_SORT, false, true, k_sort_scatter<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km1,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
     }
 }
@@ -471,8 +470,8 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         }
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
-    ln.one(R_PRE, k_pre_step<R>, dim3(d.pre_hist ? d.n_tiles : G(R_PRE)), dim3(B(R_PRE)), lds, st, d);
-    if (d.sorted == 1) launch_sort<R>(c, d, ln, d.pre_hist != 0);
+    // (the along-step kernels run the pre-step of their tracks)
+    if (d.sorted == 1) launch_sort<R>(c, d, ln, 2);
     // along-step: photons and leptons are independent branches
     const int nw = c->n_streams - 1;
     hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
@@ -485,7 +484,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
         ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
                st, d);
     if (nw > 0) join(c, 0, 1);
-    if (d.sorted2 == 1) launch_sort<R>(c, d, ln, false);
+    if (d.sorted2 == 1) launch_sort<R>(c, d, ln, 0);
     if (c->fuse_interactions) {
         // all seven actions in one launch over the combined index range
         ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);

@@ -75,9 +75,6 @@ struct Dev {
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
-    int pre_hist;           // the pre-step walks the sort tiles and writes their action histograms
-    uint32_t* tile_cnt;     // per-tile counts of the first sort: [16 bins][n_tiles]
-    uint32_t n_tiles;
     const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
@@ -98,7 +95,7 @@ __device__ __forceinline__ Tables<R> block_tables(const Dev<R>& d, R* lds)
 
 constexpr int kVacBlock = 1024;   // slots per block of the vacancy and init kernels
 constexpr int kSortThreads = 256;
-constexpr int kSortTile = 1024;      // slots per sort block (also a pre-step block when it counts for the sort)
+constexpr int kSortTile = 1024;      // slots per sort block
 constexpr int kStepMaxBlock = 512;  // block-size bound of the step kernels (lets them keep state in VGPRs)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -330,6 +327,19 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
     init_slot(d, slot, rec);
 }
 
+// The along-step action a live slot takes this iteration, from its type alone
+// (a paused field step resumes as a field step): the key of the first sort,
+// known before the pre-step, which the along-step kernels run themselves.
+template <class R>
+__device__ __forceinline__ uint8_t along_action(const Dev<R>& d, uint32_t s)
+{
+    const uint8_t t = d.type[s];
+    if (t == kDead) return A_NONE;
+    if (t == kGamma) return A_NEUTRAL;
+    if (!d.has_field) return A_CHARGED;
+    return A_FIELD;
+}
+
 // ---- work distribution ----------------------------------------------------------
 // Iterate the tracks of action `a`: masked over all slots, or the index range
 // of `a` in the sorted permutation (or its list), which holds exactly the
@@ -351,7 +361,8 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
         uint32_t s = 0;                                                                     \
         if (act) s = _mode == 2 ? (d).lists[(size_t)(a) * (d).n_slots + _i]                 \
                      : (_mode ? (d).perm[_off + _i] : _i);                                  \
-        if (act && _mode == 0 && (d).action[s] != (a)) act = false;                         \
+        if (act && _mode == 0 && ((a) < A_PROC0 ? along_action((d), s) : (d).action[s]) != (a)) \
+            act = false;                                                                    \
         _work += act ? 1u : 0u;
 
 #define EMS_END_TRACKS }
@@ -458,7 +469,9 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
 
 // Pre-step of one live, non-paused track (fields loaded by the caller):
 // interaction length, total cross section, physics step limit and the
-// along-step action, which it returns.
+// along-step action, which it returns.  The along-step kernels call it for
+// their tracks before the step (there is no separate pre-step launch), as
+// does the drain.
 template <class R>
 __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint8_t typ, R T, R nl,
                                              uint16_t slab, uint32_t row, uint32_t step, uint64_t key)
@@ -492,64 +505,6 @@ __device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& t
 }
 
 // ---- pre-step: interaction length, physics step limit, along-step action -----------
-// With pre_hist set, block b walks the slots of sort tile b (kSortTile slots)
-// and writes the tile's histogram of the new actions (the first sort's keys)
-// to tile_cnt, so that the first sort needs no counting pass of its own;
-// otherwise the blocks stride over all slots.
-template <class R>
-__global__ void __launch_bounds__(kStepMaxBlock) k_pre_step(Dev<R> d)
-{
-    extern __shared__ __align__(16) unsigned char ems_lds[];
-    __shared__ uint32_t h[16];
-    const uint32_t n = d.n_slots;
-    const bool tiles = d.pre_hist != 0;
-    if (!tiles && blockIdx.x * blockDim.x >= n) return;
-    const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    const uint32_t first = tiles ? blockIdx.x * kSortTile : blockIdx.x * blockDim.x;
-    const uint32_t last = tiles ? (first + kSortTile < n ? first + kSortTile : n) : n;
-    const uint32_t stride = tiles ? blockDim.x : gridDim.x * blockDim.x;
-    if (tiles) {
-        if (threadIdx.x < 16) h[threadIdx.x] = 0;
-        __syncthreads();
-    }
-    unsigned long long work = 0;
-    for (uint32_t base = first; base < last; base += stride) {
-        uint32_t i = base + threadIdx.x;
-        bool act = i < last;
-        uint32_t s = 0;
-        if (act) s = i;
-        // issue every load of the slot up front (all in bounds for a valid
-        // index), so that the chain of dependent accesses is short
-        uint8_t typ = kDead, fl = 0;
-        R T = R(0), nl = R(0);
-        uint16_t slab = 0;
-        uint32_t row = 0, step = 0;
-        uint64_t key = 0;
-        if (act) {
-            typ = d.type[s];
-            fl = d.flags[s];
-            T = d.T[s];
-            nl = d.nl[s];
-            slab = d.slab[s];
-            row = d.row[s];
-            step = d.step[s];
-            key = d.key[s];
-        }
-        act = act && typ != kDead;
-        bool paused = act && (fl & F_PAUSED) != 0;
-        act = act && !paused;
-        work += act ? 1u : 0u;
-        uint8_t a = paused ? (uint8_t)A_FIELD : (uint8_t)A_NONE;   // a paused step keeps its action
-        if (act) a = pre_track(d, tb, s, typ, T, nl, slab, row, step, key);
-        if (tiles && a != A_NONE) atomicAdd(&h[a], 1u);
-    }
-    if (tiles) {
-        __syncthreads();
-        if (threadIdx.x < 16) d.tile_cnt[threadIdx.x * d.n_tiles + blockIdx.x] = h[threadIdx.x];
-    }
-    flush_count(d, W_PRE, work);
-}
-
 // ---- geometry helpers -----------------------------------------------------------
 __device__ __forceinline__ double face_plane(const double* zp, int slab, double W, int face)
 {
@@ -799,18 +754,23 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     const uint8_t A = CHARGED ? A_CHARGED : A_NEUTRAL;
     EMS_TRACK_RANGE(d, A)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0;
+    unsigned long long ret_acc = 0, pre_acc = 0;
     EMS_FOR_TRACKS(d, A, s, act, CHARGED ? W_CHARGED : W_NEUTRAL)
     uint32_t row = 0;
     uint8_t next = A_NONE;
     uint32_t retired = 0;
-    if (act) along_straight_track<R, CHARGED>(d, tb, s, row, next, retired);
+    if (act) {
+        pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
+        ++pre_acc;
+        along_straight_track<R, CHARGED>(d, tb, s, row, next, retired);
+    }
     leave_event(d, retired != 0, row);
     ret_acc += retired;
     if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
     flush_count(d, CHARGED ? W_CHARGED : W_NEUTRAL, _work);
     flush_count(d, kStepsSlot + (CHARGED ? W_CHARGED : W_NEUTRAL), ret_acc);
+    flush_count(d, W_PRE, pre_acc);
 }
 
 // ---- along-step in a uniform field -------------------------------------------------
@@ -1021,11 +981,15 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     extern __shared__ __align__(16) unsigned char ems_lds[];
     EMS_TRACK_RANGE(d, A_FIELD)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0;
+    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0, pre_acc = 0;
     EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
     uint32_t row = 0;
     uint8_t next = A_NONE;
     uint32_t retired = 0, att = 0, paused_n = 0;
+    if (act && !(d.flags[s] & F_PAUSED)) {      // a paused step resumes with its step limit
+        pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
+        ++pre_acc;
+    }
     if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n);
     leave_event(d, retired != 0, row);
     ret_acc += retired;
@@ -1037,6 +1001,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
     flush_count(d, W_SUBSTEPS, sub_acc);
     flush_count(d, W_PAUSED, pause_acc);
+    flush_count(d, W_PRE, pre_acc);
 }
 
 // Discrete interaction PROC of one track at the end of its along-step.
@@ -1395,12 +1360,14 @@ __global__ void k_scan_completions(Dev<R> d)
 // Sort key of a slot at a sort point; 0xFF excludes the slot.
 //   keymode 0 (partition): the next action (< 16)
 //   keymode 1 (radix): action << 3 | type << 1 | (material & 1) (< 128)
+//   keymodes 2 and 3: as 0 and 1 with the along-step action from the type
+//   (the first sort, before the along-step kernels run the pre-step)
 template <class R>
 __device__ __forceinline__ uint32_t sort_key(const Dev<R>& d, uint32_t s, int keymode)
 {
-    uint8_t a = d.action[s];
+    uint8_t a = keymode >= 2 ? along_action(d, s) : d.action[s];
     if (a == A_NONE || a == A_IDLE) return 0xFFu;
-    if (keymode == 0) return a;
+    if (keymode == 0 || keymode == 2) return a;
     uint32_t t = d.type[s];
     uint32_t m = (uint32_t)d.smat[d.slab[s]] & 1u;
     return ((uint32_t)a << 3) | (t << 1) | m;
@@ -1486,8 +1453,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int key
     if (!ext_keys && blockIdx.x == 0 && threadIdx.x < 16) {
         // index range of each action in the sorted permutation
         uint32_t a = threadIdx.x;
-        uint32_t lo_bin = keymode == 0 ? a : a << 3;
-        uint32_t hi_bin = keymode == 0 ? a + 1 : (a + 1) << 3;
+        const bool by_action = keymode == 0 || keymode == 2;
+        uint32_t lo_bin = by_action ? a : a << 3;
+        uint32_t hi_bin = by_action ? a + 1 : (a + 1) << 3;
         if (lo_bin >= (uint32_t)NB) {
             d.ctr->range_off[a] = bbase[NB];
             d.ctr->range_cnt[a] = 0;

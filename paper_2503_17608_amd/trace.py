@@ -18,7 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 
-ROLE_ORDER = ("vacancies", "init", "pre_step", "sort", "along_neutral", "along_charged", "along_field", "compton",
+ROLE_ORDER = ("vacancies", "init", "sort", "along_neutral", "along_charged", "along_field", "compton",
               "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "annihilation", "interactions", "drain")
 
 

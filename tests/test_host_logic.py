@@ -195,7 +195,7 @@ def test_autotune_finds_the_cost_model_optimum(monkeypatch):
     assert res["sort_policy"] == "partition"
     assert res["tail_threshold"] == 2048
     assert res["fuse_interactions"] is True and res["drain_threshold"] == 16384
-    assert res["block"]["along_field"] == 256 and res["block"]["pre_step"] == 128
+    assert res["block"]["along_field"] == 256 and res["block"]["along_neutral"] == 128
 
 
 def _timed(sess, clock):
