@@ -116,7 +116,7 @@ def parse():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--precision", default="", choices=["", "f64", "mixed"])
     ap.add_argument("--policy", default="partition", choices=["none", "partition", "radix", "queue"])
-    ap.add_argument("--init-partition", type=int, default=0)
+    ap.add_argument("--init-partition", type=int, default=1)
     ap.add_argument("--max-substeps", type=int, default=10)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--graph", type=int, default=8, help="iterations per captured HIP graph (0 = plain launches)")
@@ -474,7 +474,7 @@ def main():
         var = {}
         for pol, part, dr, ru in [("none", 0, None, None), ("none", 1, None, None), ("partition", 0, None, None),
                                   ("partition", 1, None, None), ("radix", 0, None, None), ("queue", 0, None, None),
-                                  ("none", 0, 0, None), ("partition", 0, 0, None), ("partition", 0, None, 1),
+                                  ("none", 0, 0, None), ("partition", 1, 0, None), ("partition", 0, None, 1),
                                   ("partition", 1, None, 1)]:
             if pol == args.policy and part == args.init_partition and dr is None and ru is None:
                 continue
@@ -483,8 +483,9 @@ def main():
             var[tag] = rv["steps"] / rv["seconds"]
         for pol in ("partition", "radix", "none"):
             fu = 0 if args.fuse_interactions else 1
-            rv = run_variant(w, args, precision, pol, 0, None, fuse=fu)
-            tag = f"{pol}+part0" + ("+fused" if fu else "+unfused")
+            part = args.init_partition if pol == args.policy else 0
+            rv = run_variant(w, args, precision, pol, part, None, fuse=fu)
+            tag = f"{pol}+part{part}" + ("+fused" if fu else "+unfused")
             var[tag] = rv["steps"] / rv["seconds"]
         for k in (2, 4, 8, 16):
             var[f"event_parallel_{k}x{w.n_slots // k}"] = event_parallel_rate(w, args, precision, k)

@@ -1,12 +1,14 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
-configuration the benchmark times (partition policy, 8-iteration graph
-batches, LDS-staged tables, four streams, substep cap 10, fused interaction
-kernel, drain below 65536 tracks), plus degenerate and rejected inputs.
+configuration the benchmark times (partition policy, charged / neutral
+partitioned fill, 8-iteration graph batches, LDS-staged tables, one stream,
+substep cap 10, fused interaction kernel, drain below 65536 tracks), plus
+degenerate and rejected inputs.
 
 * 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event against
   the FP64 oracle (integer ledger equal, deposits to 1e-9 of the primary
-  energy), for the sort policies none / partition / radix / queue, with
-  parent-slot reuse, and with the seven interaction kernels and no drain;
+  energy), for the sort policies none / partition / radix / queue, with the
+  unpartitioned fill, with parent-slot reuse, and with the seven interaction
+  kernels on four streams and no drain;
 * 10^4 mixed primaries in a 5 degree cone at 2^20 slots: FP64 per event
   against the oracle, and the mixed-precision run's per-layer mean deposit
   within 0.5 % of the FP64 oracle;
@@ -26,7 +28,8 @@ from tests.gpu_helpers import layer_sums, ledger_int_mismatch, run_oracle, sessi
 pytestmark = pytest.mark.gpu
 
 ME = 0.51099895
-BENCH = dict(sort_policy="partition", graph_iterations=8, lds_tables=1, streams=4, max_substeps=10)
+BENCH = dict(sort_policy="partition", init_partition=True, graph_iterations=8, lds_tables=1, streams=1,
+             max_substeps=10)
 BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True)
 
 
@@ -78,13 +81,16 @@ def test_full_size_electron_showers_every_policy():
     w = workloads.electron_showers_1gev_field()
     assert w.n_events == 10_000 and w.n_slots == 1 << 20
     e_ref, l_ref, steps = run_oracle(w)
-    for policy in ("partition", "none", "radix", "queue", "partition+reuse",
+    for policy in ("partition", "none", "radix", "queue", "partition+fill0", "partition+reuse",
                    "partition+unfused+nodrain"):
-        if policy == "partition+reuse":
+        if policy == "partition+fill0":
+            edep, led, c = _run(w, sort_policy="partition", init_partition=False)
+        elif policy == "partition+reuse":
             edep, led, c = _run(w, sort_policy="partition", tuning=dict(reuse_parent_slot=True))
             assert c["work"]["reused_slots"] > 0 and c["work"]["drain"] > 0
         elif policy == "partition+unfused+nodrain":
-            edep, led, c = _run(w, sort_policy="partition", tuning=dict(fuse_interactions=False, drain_threshold=0))
+            edep, led, c = _run(w, sort_policy="partition", streams=4,
+                                tuning=dict(fuse_interactions=False, drain_threshold=0))
             assert c["work"]["drain"] == 0
         else:
             edep, led, c = _run(w, sort_policy=policy)

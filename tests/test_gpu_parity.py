@@ -222,7 +222,7 @@ def test_field_showers_parity_and_policy_invariance():
     for policy, part, sub, slots in [("none", False, 10, 1 << 15), ("partition", True, 10, 1 << 15),
                                      ("radix", False, 1, 1 << 13), ("none", True, 0, 1 << 16),
                                      ("partition", False, 3, 5000), ("queue", False, 10, 1 << 15),
-                                     ("queue", True, 2, 3000)]:
+                                     ("queue", True, 2, 3000), ("radix", True, 10, 1 << 14)]:
         edep, led, c = _run_lib(w, n_slots=slots, sort_policy=policy, init_partition=part, max_substeps=sub)
         tag = (policy, part, sub, slots)
         assert c["overflow"] == 0, tag
