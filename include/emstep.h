@@ -270,9 +270,11 @@ ems_status ems_debug_read_tracks(ems_ctx* ctx, ems_track* tracks, uint64_t n);
  * receives the number queued. */
 ems_status ems_debug_read_secondaries(ems_ctx* ctx, ems_track* out, uint64_t cap, uint64_t* n);
 
-/* Stable sort of n small keys (< 256) on the device with `policy`
- * (PARTITION: keys < 16; RADIX: keys < 256); perm[i] = index of the i-th
- * smallest key, equal keys in index order. */
+/* Stable sort of n small keys on the device with `policy` (PARTITION: keys
+ * < 16; RADIX: keys < 128; other keys are rejected with
+ * EMS_ERR_INVALID_ARG), through the same kernels as a sort point of the step
+ * loop; perm[i] = index of the i-th smallest key, equal keys in index order.
+ * Allocates and frees its own device buffers. */
 ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm);
 
 /* Run-time tuning (the autotuner's knobs; results do not depend on them).

@@ -1315,30 +1315,41 @@ ems_status ems_debug_sort(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t p
     uint32_t nt = (uint32_t)((n + kSortTile - 1) / kSortTile);
     uint8_t* dk = nullptr;
     uint32_t *dp = nullptr, *cnt = nullptr, *tot = nullptr;
-    HIP_TRY(hipMalloc(&dk, n));
-    HIP_TRY(hipMalloc(&dp, 4 * n));
-    HIP_TRY(hipMalloc(&cnt, 4ull * 128 * nt));
-    HIP_TRY(hipMalloc(&tot, 4ull * 128));
-    HIP_TRY(hipMemcpyAsync(dk, keys, n, hipMemcpyHostToDevice, c->stream));
+    auto release = [&]() {
+        (void)hipFree(dk);
+        (void)hipFree(dp);
+        (void)hipFree(cnt);
+        (void)hipFree(tot);
+    };
+    auto try_ = [&](hipError_t e) {
+        if (e != hipSuccess) release();
+        return e;
+    };
+    HIP_TRY(try_(hipMalloc(&dk, n)));
+    HIP_TRY(try_(hipMalloc(&dp, 4 * n)));
+    HIP_TRY(try_(hipMalloc(&cnt, 4ull * 128 * nt)));
+    HIP_TRY(try_(hipMalloc(&tot, 4ull * 128)));
+    HIP_TRY(try_(hipMemcpyAsync(dk, keys, n, hipMemcpyHostToDevice, c->stream)));
     Dev<double> d{};
+    // the same kernels as a sort point of the step loop
     if (nb == 16) {
-        hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk, (uint32_t)n, cnt, nt);
+        hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk, (uint32_t)n,
+                           cnt, nt);
         hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr, tot);
         hipLaunchKernelGGL((k_sort_scatter<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk,
                            (uint32_t)n, cnt, nt, (const uint32_t*)tot, dp);
     } else {
-        hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk, (uint32_t)n, cnt, nt);
+        hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk,
+                           (uint32_t)n, cnt, nt);
         hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
                            tot);
         hipLaunchKernelGGL((k_sort_scatter<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk,
                            (uint32_t)n, cnt, nt, (const uint32_t*)tot, dp);
     }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(perm, dp, 4 * n, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    (void)hipFree(dk);
-    (void)hipFree(dp);
-    (void)hipFree(cnt);
+    HIP_TRY(try_(hipGetLastError()));
+    HIP_TRY(try_(hipMemcpyAsync(perm, dp, 4 * n, hipMemcpyDeviceToHost, c->stream)));
+    HIP_TRY(try_(hipStreamSynchronize(c->stream)));
+    release();
     return EMS_OK;
 }
 

@@ -56,7 +56,7 @@ def test_device_tables_match_oracle(ecut):
 
 
 # ----------------------------------------------------------------------------- sort
-@pytest.mark.parametrize("n", [1, 63, 4096, 4097, 100_003, 1 << 20])
+@pytest.mark.parametrize("n", [1, 63, 4096, 4097, 100_003, 1 << 20, (1 << 20) + 1])
 @pytest.mark.parametrize("policy,nb", [("partition", 16), ("radix", 128)])
 def test_sort_permutation_bit_exact(n, policy, nb):
     w = workloads.small_electron_showers(1)
