@@ -370,15 +370,22 @@ __device__ __forceinline__ uint8_t along_action(const Dev<R>& d, uint32_t s)
 // ---- secondary append (block-aggregated) ------------------------------------------
 // One global atomic per block that has secondaries (none if it has none);
 // lanes get consecutive initializer records in lane order within each wave.
-// All threads of the block must call it (block-uniform control flow).
+// The event's counters change once per thread: one atomic per secondary
+// type created, and one on the live count for the secondaries pushed minus
+// the track itself when it ends in this step (`retiring`), none when they
+// cancel.  All threads of the block must call it (block-uniform control
+// flow).
 template <class R>
 __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row,
-                                                   uint16_t slab, const double r[3])
+                                                   uint16_t slab, const double r[3], bool retiring)
 {
     __shared__ unsigned int wtot[16];
     __shared__ unsigned long long bbase;
     const int n = sb.n;
-    if (__syncthreads_count(n) == 0) return;     // block-uniform
+    if (__syncthreads_count(n) == 0) {           // block-uniform
+        if (retiring) atomicSub(&d.live[row], 1u);
+        return;
+    }
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     int x = n;
     for (int o = 1; o < 64; o <<= 1) {
@@ -398,6 +405,7 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
     }
     __syncthreads();
     unsigned long long pos = bbase + wtot[w] + (unsigned long long)(x - n);
+    unsigned int n_gam = 0, n_ele = 0, n_pos = 0;
     sb.each([&](const Sec<R>& v, int k) {
         unsigned long long q = pos + (unsigned long long)k;
         if (q >= d.queue_cap) {
@@ -414,9 +422,15 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
         rec.type = (uint8_t)v.type;
         rec.pad = 0;
         d.queue[q] = rec;
-        atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
-        atomicAdd(&d.live[row], 1u);
+        n_gam += v.type == kGamma;
+        n_ele += v.type == kElectron;
+        n_pos += v.type == kPositron;
     });
+    if (n_gam) atomicAdd(&d.ledger[row].n_sec[kGamma], (unsigned long long)n_gam);
+    if (n_ele) atomicAdd(&d.ledger[row].n_sec[kElectron], (unsigned long long)n_ele);
+    if (n_pos) atomicAdd(&d.ledger[row].n_sec[kPositron], (unsigned long long)n_pos);
+    const int dlive = (int)(n_gam + n_ele + n_pos) - (retiring ? 1 : 0);
+    if (dlive != 0) atomicAdd(&d.live[row], (unsigned int)dlive);    // modulo 2^32: a decrement for -1
     __syncthreads();                                  // wtot / bbase are reused by the next trip
 }
 
@@ -1074,8 +1088,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     uint32_t retired = 0;
     if (act) interact_track<R, PROC>(d, s, sb, r, row, slab, retired);
     if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
-    append_secondaries(d, sb, row, slab, r);
-    leave_event(d, retired != 0, row);
+    append_secondaries(d, sb, row, slab, r, retired != 0);
     ret_acc += retired;
     EMS_END_TRACKS
     flush_count(d, W_PROC0 + PROC, _work);
@@ -1158,8 +1171,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
             }
         }
         if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
-        append_secondaries(d, sb, row, slab, r);
-        leave_event(d, retired != 0, row);
+        append_secondaries(d, sb, row, slab, r, retired != 0);
         ret_acc += retired;
     }
     flush_count(d, W_PROC0 + P_COMPTON, w0);
@@ -1192,10 +1204,14 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
 // counts its entries, in LDS), else to the initializer buffer.
 template <class R>
 __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row, uint16_t slab,
-                                           const double r[3], Initializer* bstack, int cap, int* top)
+                                           const double r[3], Initializer* bstack, int cap, int* top, bool retiring)
 {
+    // the event's counters change once per track, as in append_secondaries
+    const int dlive = sb.n - (retiring ? 1 : 0);
+    if (dlive != 0) atomicAdd(&d.live[row], (unsigned int)dlive);    // modulo 2^32: a decrement for -1
     if (sb.n == 0) return;
     const int pos = atomicAdd(top, sb.n);
+    unsigned int n_gam = 0, n_ele = 0, n_pos = 0;
     sb.each([&](const Sec<R>& v, int k) {
         Initializer rec;
         rec.T = (double)v.T;
@@ -1206,8 +1222,9 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
         rec.slab = slab;
         rec.type = (uint8_t)v.type;
         rec.pad = 0;
-        atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
-        atomicAdd(&d.live[row], 1u);
+        n_gam += v.type == kGamma;
+        n_ele += v.type == kElectron;
+        n_pos += v.type == kPositron;
         if (pos + k < cap) {
             bstack[pos + k] = rec;
         } else {
@@ -1216,6 +1233,9 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
             else atomicOr(&d.ctr->overflow, 1u);
         }
     });
+    if (n_gam) atomicAdd(&d.ledger[row].n_sec[kGamma], (unsigned long long)n_gam);
+    if (n_ele) atomicAdd(&d.ledger[row].n_sec[kElectron], (unsigned long long)n_ele);
+    if (n_pos) atomicAdd(&d.ledger[row].n_sec[kPositron], (unsigned long long)n_pos);
 }
 
 // Exclusive rank of a true flag among the block's threads, and their total.
@@ -1318,12 +1338,11 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
                 double r[3] = {0.0, 0.0, 0.0};
                 uint16_t slab = 0;
                 drain_interact<R>(d, next - A_PROC0, s, sb, r, row, slab, retired);
-                drain_push(d, sb, row, slab, r, bstack, cap, &top);
-            }
-            if (retired) {
+                drain_push(d, sb, row, slab, r, bstack, cap, &top, retired != 0);
+            } else if (retired) {
                 leave_event(d, true, row);
-                ret_acc += retired;
             }
+            ret_acc += retired;
             ++work;
         }
         __syncthreads();
