@@ -102,8 +102,9 @@ typedef struct {
     int32_t block_size;        /* threads per block for the step kernels (multiple of 64, <= 512); 0 = 256 */
     int32_t graph_iterations;  /* iterations captured per HIP graph in ems_run (needs a non-null
                                   stream); 0 = plain launches */
-    int32_t lds_tables;        /* 1: each block of the pre-step and along-step kernels stages the
-                                  physics tables in LDS; 0: tables are read through the caches */
+    int32_t lds_tables;        /* 1: each block of the along-step kernels (which run the pre-step)
+                                  and of the drain stages the physics tables in LDS; 0: tables are
+                                  read through the caches */
     int32_t streams;           /* 1..4: independent kernels of an iteration (the along-step kernels;
                                   the interaction kernels) run as concurrent branches on up to this
                                   many default-priority streams created by the library */
@@ -156,7 +157,8 @@ typedef struct {
     uint32_t overflow;         /* nonzero: the initializer buffer overflowed (results invalid) */
     uint32_t completed;        /* events completed since creation */
     /* cumulative tracks processed per kernel role: [0] slots handed from a
-     * finished track to its secondary, [1] init, [2] pre-step, [4] neutral,
+     * finished track to its secondary, [1] init, [2] pre-steps (run by the
+     * along-step kernels), [4] neutral,
      * [5] charged, [6] field along-step (track-iterations), [7..12] Compton,
      * photoelectric, pair, Moller, Bhabha, bremsstrahlung, [13] annihilation
      * at rest, [14] paused field steps, [15] field RK4 evaluations, [16]
