@@ -76,6 +76,7 @@ typedef enum { EMS_FP64 = 0, EMS_MIXED = 1 } ems_precision;
  *             interacting track's slot to its process list (wave-aggregated,
  *             ascending slot order within a wavefront), so no second sort
  *             pass runs. */
+/* Paper: "Stepping algorithm" (masking, NONE); "Reindexing track slots" (the others). */
 typedef enum { EMS_SORT_NONE = 0, EMS_SORT_PARTITION = 1, EMS_SORT_RADIX = 2, EMS_SORT_QUEUE = 3 } ems_sort_policy;
 typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_particle;
 
@@ -95,19 +96,24 @@ typedef struct {
     uint32_t max_events;       /* tally rows (events resident at once) */
     uint32_t max_slabs;        /* capacity for geometry slabs */
     uint32_t max_materials;    /* capacity for materials */
-    int32_t sort_policy;       /* ems_sort_policy, applied before the along-step and interaction kernels */
-    int32_t init_partition;    /* 1: new charged tracks fill vacancies from the low end, neutral from the high end */
-    int32_t max_substeps;      /* field substeps per track per iteration; <= 0 means unlimited */
+    int32_t sort_policy;       /* ems_sort_policy, applied before the along-step and interaction kernels
+                                  (paper: "Reindexing track slots") */
+    int32_t init_partition;    /* 1: new charged tracks fill vacancies from the low end, neutral from the high end
+                                  (paper: "Partitioning track data") */
+    int32_t max_substeps;      /* field substeps per track per iteration; <= 0 means unlimited
+                                  (paper: "Reducing load imbalance") */
     uint64_t seed;             /* Philox key word 0 */
     int32_t block_size;        /* threads per block for the step kernels (multiple of 64, <= 512); 0 = 256 */
     int32_t graph_iterations;  /* iterations captured per HIP graph in ems_run (needs a non-null
-                                  stream); 0 = plain launches */
+                                  stream); 0 = plain launches (paper: "Stepping algorithm", the
+                                  launch overhead of the outer loop) */
     int32_t lds_tables;        /* 1: each block of the along-step kernels (which run the pre-step)
                                   and of the drain stages the physics tables in LDS; 0: tables are
                                   read through the caches */
     int32_t streams;           /* 1..4: independent kernels of an iteration (the along-step kernels;
                                   the interaction kernels) run as concurrent branches on up to this
-                                  many default-priority streams created by the library */
+                                  many default-priority streams created by the library (paper:
+                                  "Asynchronous memory management", concurrent streams) */
     int32_t msc;               /* 1: charged tracks still in the stack after an along-step are deflected
                                   by multiple scattering: Rayleigh-distributed space angle of Highland
                                   width at the pre-step energy, uniform azimuth (Philox domain 5);
@@ -168,45 +174,62 @@ typedef struct {
 
 typedef struct ems_ctx ems_ctx;
 
-/* Library ABI version (EMS_ABI_VERSION). */
+/* Library ABI version (EMS_ABI_VERSION).
+ * Paper: no passage (interface versioning). */
 uint32_t ems_abi_version(void);
 
 /* Message for the calling thread's most recent failure ("" if none).  The
- * string is owned by the library and valid until the next call. */
+ * string is owned by the library and valid until the next call.
+ * Paper: no passage (error reporting). */
 const char* ems_last_error(void);
 
-/* Bytes of device workspace needed for `opt`.  Errors: INVALID_ARG. */
+/* Bytes of device workspace needed for `opt`.  Errors: INVALID_ARG.
+ * Paper: "Stepping algorithm" (a fixed array of track slots stored as a struct
+ * of arrays, plus the buffer of track initializers); "Asynchronous memory
+ * management" (the caller allocates once, stream-ordered). */
 ems_status ems_query_workspace(const ems_options* opt, uint64_t* bytes);
 
 /* Create a context on the current HIP device.  `device_workspace` (>= the
  * queried bytes, 256-byte aligned) and `hip_stream` (a hipStream_t, may be
- * NULL for the null stream) are borrowed.  Errors: INVALID_ARG, DEVICE. */
+ * NULL for the null stream) are borrowed.  Errors: INVALID_ARG, DEVICE.
+ * Paper: "Asynchronous memory management" (all device work ordered on one
+ * stream; pinned host buffers for the counters and the staging of primaries). */
 ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t bytes, void* hip_stream,
                       ems_ctx** out);
 
-/* Release the context (not the caller's workspace). */
+/* Release the context (not the caller's workspace).
+ * Paper: no passage (resource release). */
 void ems_destroy(ems_ctx* ctx);
 
-/* Materials (Z, A [g/mol], density, I [eV]); n <= max_materials. */
+/* Materials (Z, A [g/mol], density, I [eV]); n <= max_materials.
+ * Paper: "Stepping algorithm" (the step-limit and interaction actions read
+ * per-material data); the physics itself is this library's reading, the paper
+ * states none. */
 ems_status ems_load_materials(ems_ctx* ctx, const ems_material* m, uint32_t n);
 
 /* Slab stack along z: z_planes[n_slabs + 1] strictly increasing, material
  * index per slab, lateral half width (|x|, |y| <= half_width), uniform field
- * B[3] in tesla.  Outside the stack is a kill region (escape). */
+ * B[3] in tesla.  Outside the stack is a kill region (escape).
+ * Paper: "Stepping algorithm" (propagation to boundaries); "Reducing load
+ * imbalance" (uniform magnetic field, substepped propagation). */
 ems_status ems_load_geometry(ems_ctx* ctx, const double* z_planes, const int32_t* slab_material,
                              uint32_t n_slabs, double half_width, const double B[3]);
 
 /* Build the physics tables on the device from the loaded materials for the
  * production/tracking cut `ecut` [MeV] (the same cut applies to delta rays,
- * bremsstrahlung photons and all tracked particles).  Requires materials. */
+ * bremsstrahlung photons and all tracked particles).  Requires materials.
+ * Paper: "Stepping algorithm" (step limit from cross sections and range); the
+ * models are this library's reading, the paper states none. */
 ems_status ems_build_tables(ems_ctx* ctx, double ecut);
 
 /* Load caller-provided tables instead: `tables` holds
  * [n_materials][EMS_TABLES_PER_MATERIAL][EMS_TABLE_NODES] doubles in the
- * layout described above; copied to the device. */
+ * layout described above; copied to the device.
+ * Paper: "Stepping algorithm" (as ems_build_tables). */
 ems_status ems_load_tables(ems_ctx* ctx, const double* tables, uint32_t n_materials, double ecut);
 
-/* Copy the device tables (FP64) to host `out` (same layout). */
+/* Copy the device tables (FP64) to host `out` (same layout).
+ * Paper: no passage (inspection of the loaded tables). */
 ems_status ems_read_tables(ems_ctx* ctx, double* out, uint64_t n_doubles);
 
 /* Queue primaries (copied to device).  Each event id is given a tally row on
@@ -214,69 +237,100 @@ ems_status ems_read_tables(ems_ctx* ctx, double* out, uint64_t n_doubles);
  * energy below the cut or not finite, direction not unit, position outside
  * the given slab or the lateral walls), CAPACITY (primary buffer or event
  * rows full).  Nothing is queued when an error is returned.  n == 0 is a
- * no-op. */
+ * no-op.
+ * Paper: "Stepping algorithm" (track initializers, used to fill vacant slots
+ * at the start of each step iteration); "Asynchronous memory management"
+ * (pinned staging, stream-ordered copy). */
 ems_status ems_push_primaries(ems_ctx* ctx, const ems_primary* p, uint64_t n);
 
 /* Enqueue `iterations` step iterations (asynchronous; no host wait).  If
- * `out` is non-NULL, synchronizes and returns the counters after them. */
+ * `out` is non-NULL, synchronizes and returns the counters after them, and
+ * returns CAPACITY (counters filled) if the initializer buffer overflowed.
+ * Paper: "Stepping algorithm" (a step iteration is a sequence of action
+ * kernels over the track array); "Reindexing track slots" (the sort points,
+ * ems_options.sort_policy); "Partitioning track data"
+ * (ems_options.init_partition); "Reducing load imbalance"
+ * (ems_options.max_substeps). */
 ems_status ems_step(ems_ctx* ctx, uint32_t iterations, ems_counters* out);
 
 /* Step until no track is alive, queued or pending, or `max_iterations` is
  * reached (then returns STATE).  The host polls device counters through a
  * pinned buffer every `graph_iterations` (or 16) iterations.  Errors:
- * CAPACITY if the initializer buffer overflowed. */
+ * CAPACITY if the initializer buffer overflowed.
+ * Paper: "Stepping algorithm" (the host's outer loop of step iterations);
+ * "Asynchronous memory management" (termination read from counters copied to
+ * pinned memory, no synchronous copy inside the loop). */
 ems_status ems_run(ems_ctx* ctx, uint64_t max_iterations, ems_counters* out);
 
-/* Synchronize and read the counters. */
+/* Synchronize and read the counters.
+ * Paper: "Integration with Perfetto" (counters such as the active and queued
+ * tracks of each step iteration). */
 ems_status ems_read_counters(ems_ctx* ctx, ems_counters* out);
 
 /* Events whose tracks have all finished since the last poll (serving): an
  * event completes when its last pushed primary and last secondary have
  * retired.  Writes up to `cap` event ids to `events` (completion order) and
- * their count to *n; synchronizes the stream. */
+ * their count to *n; synchronizes the stream.  Errors: CAPACITY (and *n = 0)
+ * once the initializer buffer has overflowed, since secondaries were dropped
+ * and completed events may miss energy.
+ * Paper: "GPU thread scaling" (events mixed in one track array on one stream;
+ * an event ends when all its tracks have ended). */
 ems_status ems_poll_completed(ems_ctx* ctx, uint64_t* events, uint32_t cap, uint32_t* n);
 
-/* Energy deposited per slab (n_slabs values) and the ledger of `event`. */
+/* Energy deposited per slab (n_slabs values) and the ledger of `event`.
+ * Paper: "Asynchronous memory management" (scored energy stays on the device
+ * and is read back per event, not copied every iteration). */
 ems_status ems_read_edep(ems_ctx* ctx, uint64_t event, double* per_slab, uint32_t n_slabs, ems_ledger* ledger);
 
 /* Read all tally rows at once: edep[max_events][n_slabs], ledgers[max_events]
  * (either may be NULL), plus the event id of every row (row_event, may be
- * NULL; unused rows hold UINT64_MAX). */
+ * NULL; unused rows hold UINT64_MAX).
+ * Paper: "Asynchronous memory management" (as ems_read_edep). */
 ems_status ems_read_all_tallies(ems_ctx* ctx, double* edep, ems_ledger* ledgers, uint64_t* row_event);
 
-/* Free the tally row of a finished event and zero it for reuse. */
+/* Free the tally row of a finished event and zero it for reuse.
+ * Paper: "GPU thread scaling" (events mixed in one track array: a finished
+ * event's row is reused by the next). */
 ems_status ems_release_event(ems_ctx* ctx, uint64_t event);
 
 /* Release n events at once (one clearing kernel).  Errors: INVALID_ARG for an
- * unknown or repeated event id (nothing is released then). */
+ * unknown or repeated event id (nothing is released then).
+ * Paper: "GPU thread scaling" (as ems_release_event). */
 ems_status ems_release_events(ems_ctx* ctx, const uint64_t* events, uint64_t n);
 
 /* ---- test hooks ---------------------------------------------------------- */
 
-/* Give `event` a tally row (as ems_push_primaries would) and return it. */
+/* Give `event` a tally row (as ems_push_primaries would) and return it.
+ * Paper: no passage (test hook). */
 ems_status ems_debug_register_event(ems_ctx* ctx, uint64_t event, uint32_t* row);
 
 /* Overwrite slots [0, n) with `tracks` (rows from ems_debug_register_event,
  * energies >= the cut), mark every other slot vacant and discard queued
- * secondaries.  Errors: STATE, CAPACITY (n > n_slots), INVALID_ARG. */
+ * secondaries.  Errors: STATE, CAPACITY (n > n_slots), INVALID_ARG.
+ * Paper: "Stepping algorithm" (track state arrays; test hook for one step of
+ * given states). */
 ems_status ems_debug_inject(ems_ctx* ctx, const ems_track* tracks, uint64_t n);
 
 /* Run `iterations` step iterations, skipping the slot initialization phase
- * when `no_init` is nonzero (secondaries then stay in the initializer buffer). */
+ * when `no_init` is nonzero (secondaries then stay in the initializer buffer).
+ * Paper: "Stepping algorithm" (one step iteration; test hook). */
 ems_status ems_debug_iterate(ems_ctx* ctx, uint32_t iterations, int32_t no_init);
 
-/* Read slots [0, n) into `tracks`. */
+/* Read slots [0, n) into `tracks`.
+ * Paper: "Stepping algorithm" (track state arrays; test hook). */
 ems_status ems_debug_read_tracks(ems_ctx* ctx, ems_track* tracks, uint64_t n);
 
 /* Read the secondary initializer buffer (up to cap entries) as tracks; *n
- * receives the number queued. */
+ * receives the number queued.
+ * Paper: "Stepping algorithm" (the buffer of track initializers; test hook). */
 ems_status ems_debug_read_secondaries(ems_ctx* ctx, ems_track* out, uint64_t cap, uint64_t* n);
 
 /* Stable sort of n small keys on the device with `policy` (PARTITION: keys
  * < 16; RADIX: keys < 128; other keys are rejected with
  * EMS_ERR_INVALID_ARG), through the same kernels as a sort point of the step
  * loop; perm[i] = index of the i-th smallest key, equal keys in index order.
- * Allocates and frees its own device buffers. */
+ * Allocates and frees its own device buffers.
+ * Paper: "Reindexing track slots" (sorting the slot indices, not the state). */
 ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm);
 
 /* Run-time tuning (the autotuner's knobs; results do not depend on them).
@@ -309,7 +363,10 @@ ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t
  * boundaries) instead of seven launches on the library's streams; kernel role
  * "interactions" in the block table.
 
- * Setting the tuning re-captures graphs on the next run. */
+ * Setting the tuning re-captures graphs on the next run.
+ * Paper: "Reindexing track slots" (sort policy, tail threshold); "Partitioning
+ * track data" (parent-slot reuse); "Reducing load imbalance" (the drain of the
+ * last tracks); "Performance results" (launch shapes). */
 typedef struct {
     int32_t sort_policy;
     uint32_t tail_threshold;
@@ -324,7 +381,8 @@ ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);
 
 /* Average duration [ms] of each kernel over the iterations launched since the
  * last call, measured with HIP events around every launch on the library's
- * stream when `enable` was set; names are fixed kernel-role strings. */
+ * stream when `enable` was set; names are fixed kernel-role strings.
+ * Paper: "Integration with Perfetto" (time per action in each step iteration). */
 ems_status ems_profile_enable(ems_ctx* ctx, int32_t enable);
 ems_status ems_profile_read(ems_ctx* ctx, const char** names, double* total_ms, uint64_t* launches, uint32_t cap,
                             uint32_t* n);

@@ -119,8 +119,9 @@ enum : int {
 };
 // partial-counter slots: [0, kNumWork) work per kernel, [kStepsSlot, kNumW)
 // completed steps of the tracks each kernel retired (one slot per kernel,
-// since kernels of an iteration may run concurrently and every slot has a
-// single writer)
+// since kernels of an iteration may run concurrently: such a slot has a
+// single writer; the pre-step and slot-reuse roles, which concurrent
+// kernels share, are updated atomically)
 constexpr int kNumWork = W_DRAIN + 1;
 constexpr int kStepsSlot = kNumWork;
 constexpr int kNumW = 2 * kNumWork;

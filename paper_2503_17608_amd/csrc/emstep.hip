@@ -1051,6 +1051,7 @@ ems_status ems_step(ems_ctx* c, uint32_t iterations, ems_counters* out)
         s = snapshot_now(c, &sn);
         if (s != EMS_OK) return s;
         to_counters(sn, out);
+        if (sn.overflow) return fail(EMS_ERR_CAPACITY, "initializer buffer overflow: increase n_initializers");
     }
     return EMS_OK;
 }
@@ -1132,6 +1133,9 @@ ems_status ems_poll_completed(ems_ctx* c, uint64_t* events, uint32_t cap, uint32
     Snapshot sn;
     ems_status s = snapshot_now(c, &sn);
     if (s != EMS_OK) return s;
+    // secondaries beyond the initializer buffer were dropped: the events
+    // completing now may miss energy, so none is reported
+    if (sn.overflow) return fail(EMS_ERR_CAPACITY, "initializer buffer overflow: increase n_initializers");
     uint32_t rows_n = c->opt.max_events;
     uint32_t avail = sn.done_count - c->done_read;
     if (avail > rows_n) {

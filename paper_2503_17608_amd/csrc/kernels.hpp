@@ -130,6 +130,17 @@ __device__ __forceinline__ void flush_count(const Dev<R>& d, int role, unsigned 
     if (threadIdx.x == 0 && t) d.part[(size_t)role * d.part_stride + blockIdx.x] += t;
 }
 
+// The same for a role that kernels running concurrently on several streams
+// share (the pre-steps of the photon and lepton along-steps, the slot reuse
+// of the per-process interaction kernels): block b of two such kernels
+// writes the same entry, so the update is atomic (one per block and launch).
+template <class R>
+__device__ __forceinline__ void flush_count_shared(const Dev<R>& d, int role, unsigned long long v)
+{
+    unsigned long long t = block_sum(v);
+    if (threadIdx.x == 0 && t) atomicAdd(&d.part[(size_t)role * d.part_stride + blockIdx.x], t);
+}
+
 // A retired track leaves its event (no-return atomic); completion is detected
 // after the iteration by the row scan.
 template <class R>
@@ -784,7 +795,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     EMS_END_TRACKS
     flush_count(d, CHARGED ? W_CHARGED : W_NEUTRAL, _work);
     flush_count(d, kStepsSlot + (CHARGED ? W_CHARGED : W_NEUTRAL), ret_acc);
-    flush_count(d, W_PRE, pre_acc);
+    flush_count_shared(d, W_PRE, pre_acc);
 }
 
 // ---- along-step in a uniform field -------------------------------------------------
@@ -1015,7 +1026,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
     flush_count(d, W_SUBSTEPS, sub_acc);
     flush_count(d, W_PAUSED, pause_acc);
-    flush_count(d, W_PRE, pre_acc);
+    flush_count_shared(d, W_PRE, pre_acc);
 }
 
 // Discrete interaction PROC of one track at the end of its along-step.
@@ -1093,7 +1104,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     EMS_END_TRACKS
     flush_count(d, W_PROC0 + PROC, _work);
     flush_count(d, kStepsSlot + W_PROC0 + PROC, ret_acc);
-    flush_count(d, W_REUSE, reuse_acc);
+    flush_count_shared(d, W_REUSE, reuse_acc);
 }
 
 // ---- discrete interactions, all seven actions in one launch ------------------------
@@ -1182,7 +1193,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
     flush_count(d, W_PROC0 + P_BREMS, w5);
     flush_count(d, W_PROC0 + P_ANNIH, w6);
     flush_count(d, kStepsSlot + W_PROC0, ret_acc);
-    flush_count(d, W_REUSE, reuse_acc);
+    flush_count_shared(d, W_REUSE, reuse_acc);
 }
 
 // ---- drain: block-local stepping of the last tracks ---------------------------------

@@ -96,6 +96,9 @@ def serve(session, events, arrivals, track_budget, iterations_per_poll=8, keep_r
             session.release(ev)
             free_rows += 1
         c = session.counters()
+        if c["overflow"]:
+            # dropped secondaries: results of events in flight are incomplete
+            raise RuntimeError("initializer buffer overflow while serving: increase n_initializers")
         load = c["alive"] + c["queued"] + c["pending_primaries"]
         del admitted
     res.wall_s = clock() - t0

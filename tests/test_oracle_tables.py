@@ -58,12 +58,66 @@ def test_klein_nishina_thomson_limit():
 
 # ---------------------------------------------------------------- photoelectric
 def test_photoelectric_scaling():
-    # Z^5 E^-7/2 scaling and the Born K-shell prefactor 4 sqrt2 alpha^4 sigma_T
+    # Z^5 E^-7/2 scaling (the prefactor is pinned by the golden-rule test below)
     s1 = T.sigma_photoelectric(0.2, 82.0)
     assert T.sigma_photoelectric(0.4, 82.0) / s1 == pytest.approx(2 ** -3.5, rel=1e-14)
     assert T.sigma_photoelectric(0.2, 41.0) / s1 == pytest.approx(2 ** -5, rel=1e-14)
     born = 4 * math.sqrt(2) * T.ALPHA ** 4 * 82 ** 5 * T.SIGMA_THOMSON * (T.ME / 0.2) ** 3.5
     assert s1 == pytest.approx(1.25 * born, rel=1e-14)
+
+
+# Independent constants for the golden-rule pin below (CODATA 2018), so that
+# a wrong constant in the oracle does not cancel out.
+_ALPHA = 1.0 / 137.035999084
+_ME_MEV = 0.51099895000
+_HBARC_MEV_CM = 197.3269804e-13
+
+
+def _k_shell_born_golden_rule(omega, Z):
+    """K-shell photo-absorption cross section [cm^2] of a hydrogen-like atom of
+    charge Z at photon energy omega [MeV], from first principles:
+    Fermi's golden rule in the dipole approximation,
+        sigma = 4 pi^2 alpha / (m^2 omega) * sum_f |<f| eps.p |1s>|^2 delta(E_f - E_i - omega),
+    with a plane-wave final electron (Born approximation) and the 1s state
+    psi(r) = exp(-r/a) / sqrt(pi a^3), a = 1/(Z alpha m), two K electrons.
+    Natural units (hbar = c = 1, energies in MeV).  The momentum-space
+    wavefunction phi(p) = (4 pi / p) int r psi(r) sin(p r) dr and the angular
+    integral of (eps.p_hat)^2 are both done by quadrature here: nothing of the
+    Heitler closed form (prefactor, powers of alpha, Z or omega) is assumed."""
+    m = _ME_MEV
+    a = 1.0 / (Z * _ALPHA * m)
+    binding = 0.5 * (Z * _ALPHA) ** 2 * m
+    p = math.sqrt(2.0 * m * (omega - binding))        # final momentum, non-relativistic
+    kappa = p * a
+    radial = integrate.quad(lambda x: x * math.exp(-x), 0.0, np.inf, weight="sin", wvar=kappa)[0]
+    phi = 4.0 * math.pi / p * a * a * radial / math.sqrt(math.pi * a ** 3)
+    ang = 2.0 * math.pi * quad(lambda c: c * c, -1.0, 1.0)          # int (eps.p_hat)^2 dOmega
+    # sum over final plane waves: int d^3p/(2pi)^3 delta(p^2/2m - (omega - B)) = m p / (2 pi)^3 dOmega
+    per_electron = 4.0 * math.pi ** 2 * _ALPHA / (m * m * omega) * m * p / (2.0 * math.pi) ** 3 \
+        * p * p * ang * phi * phi
+    return 2.0 * per_electron * _HBARC_MEV_CM ** 2
+
+
+@pytest.mark.parametrize("Z", [1.0, 3.0, 8.0])
+def test_photoelectric_normalisation_from_the_golden_rule(Z):
+    """The oracle's K-shell term (its cross section divided by the all-shell
+    factor 5/4, which is this reading's stated convention) is the high-energy
+    limit of the non-relativistic Born K-shell cross section computed from the
+    golden rule.  At omega = 100 MeV the finite-energy corrections
+    (1 + 1/(pa)^2)^-4 and the binding energy are below 4e-5 for Z <= 8, so the
+    two agree to 2e-4: a wrong power of alpha or Z, a wrong energy exponent or
+    a wrong numerical prefactor in the oracle fails by orders of magnitude."""
+    for omega in (100.0, 300.0):
+        exact = _k_shell_born_golden_rule(omega, Z)
+        assert T.sigma_photoelectric(omega, Z) / 1.25 == pytest.approx(exact, rel=2e-4), omega
+    # and the approach to the limit is the expected one: with x = 1/(pa)^2 =
+    # B/omega (B the binding energy), the factor (1 + x)^-4 lowers the exact
+    # value by 4x and the binding, through p^-5 = (2 m (omega - B))^-5/2,
+    # raises it by 5x/2: at 1 MeV the exact value lies 3x/2 below the limit
+    m = _ME_MEV
+    x = (Z * _ALPHA * m) ** 2 / (2.0 * m * 1.0)
+    ratio = _k_shell_born_golden_rule(1.0, Z) / (T.sigma_photoelectric(1.0, Z) / 1.25)
+    assert 1.0 - ratio == pytest.approx(1.5 * x, rel=0.05)
 
 
 # ---------------------------------------------------------------- pair
