@@ -5,6 +5,7 @@ import collections
 import threading
 
 import numpy as np
+import pytest
 
 import workloads
 from paper_2503_17608_amd import autotune, multistream, serving
@@ -28,6 +29,7 @@ class FakeSession:
         self.released = []
         self.tuning_calls = []
         self.max_rows_seen = 0
+        self.overflow = 0
 
     def push(self, prims):
         for e in np.unique(prims["event"]):
@@ -57,7 +59,7 @@ class FakeSession:
 
     def counters(self):
         return {"alive": len(self.pending), "queued": 0, "pending_primaries": 0, "steps": self.steps,
-                "iterations": self.iterations}
+                "iterations": self.iterations, "overflow": self.overflow}
 
     def read_edep(self, ev):
         return np.full(3, float(ev)), {"event": ev}
@@ -96,6 +98,17 @@ def test_serve_completes_every_event_once_within_row_limit():
     for e, v in res.edep.items():
         assert np.all(v == float(e))
     assert res.iterations == s.iterations and res.steps == s.steps
+
+
+def test_serve_raises_on_initializer_overflow():
+    """Dropped secondaries leave events incomplete: the loop must not report
+    them as served."""
+    clock = Clock()
+    s = FakeSession(max_events=4, clock=clock)
+    s.overflow = 1
+    events = _events(3)
+    with pytest.raises(RuntimeError, match="overflow"):
+        serving.serve(s, events, np.zeros(len(events)), track_budget=10 ** 6, iterations_per_poll=2, clock=clock)
 
 
 def test_latency_is_completion_minus_arrival():
