@@ -48,6 +48,18 @@ RESULT_DTYPE = np.dtype([
 ], align=True)
 assert RESULT_DTYPE.itemsize == 448
 
+MARGIN_DTYPE = np.dtype([("margin", "<f8"), ("kind", "<i4"), ("n_notes", "<i4")], align=True)
+assert MARGIN_DTYPE.itemsize == 16
+# decision kinds of a margin (see note() in transport.c)
+MARGIN_KINDS = ["none", "cut at step start", "process threshold", "loss vs interaction limit",
+                "final range", "geometry vs physics limit", "face tie", "direction sign", "chord beyond plane",
+                "chord face tie", "chord at start", "near face (d_int)", "boundary search acceptance (d_int)",
+                "last substep", "cut after loss", "process selection", "rejection test", "sampling branch",
+                "secondary cut", "rotation pole branch"]
+TRACE_DTYPE = np.dtype([("pre", TRACK_DTYPE), ("post", TRACK_DTYPE), ("res", RESULT_DTYPE), ("m", MARGIN_DTYPE)],
+                       align=True)
+assert TRACE_DTYPE.itemsize == 96 + 96 + 448 + 16
+
 LEDGER_DTYPE = np.dtype([
     ("escaped", "<f8"), ("n_pair", "<u8"), ("n_annih", "<u8"), ("steps", "<u8"),
     ("n_sec", "<u8", (3,)), ("n_guard", "<u8"), ("n_reject_cap", "<u8"),
@@ -109,6 +121,10 @@ def lib():
         L.orc_msc_theta0.restype = C.c_double
         L.orc_msc_deflect.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int, C.c_double, C.c_double]
         L.orc_msc_deflect.restype = None
+        L.orc_step_margin.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_step_margin.restype = None
+        L.orc_trace_event.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64]
+        L.orc_trace_event.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -153,6 +169,32 @@ class Problem:
         for i in range(len(tr)):
             L.orc_step(C.byref(self._s), tr[i:i + 1].ctypes.data, res[i:i + 1].ctypes.data)
         return res
+
+    def step_margins(self, track):
+        """As step(), and also the smallest decision margin of each step
+        (MARGIN_DTYPE records: margin, kind index into MARGIN_KINDS)."""
+        tr = np.atleast_1d(track)
+        assert tr.dtype == TRACK_DTYPE and tr.flags.c_contiguous
+        res = np.zeros(len(tr), dtype=RESULT_DTYPE)
+        m = np.zeros(len(tr), dtype=MARGIN_DTYPE)
+        L = lib()
+        for i in range(len(tr)):
+            L.orc_step_margin(C.byref(self._s), tr[i:i + 1].ctypes.data, res[i:i + 1].ctypes.data,
+                              m[i:i + 1].ctypes.data)
+        return res, m
+
+    def trace_event(self, prims):
+        """Every step of one event's history (the primaries `prims`, one
+        event, TRACK_DTYPE), in history order: TRACE_DTYPE records."""
+        p = np.ascontiguousarray(prims, dtype=TRACK_DTYPE)
+        L = lib()
+        cap = 1 << 14
+        while True:
+            out = np.zeros(cap, dtype=TRACE_DTYPE)
+            n = L.orc_trace_event(C.byref(self._s), p.ctypes.data, len(p), out.ctypes.data, cap)
+            if n <= cap:
+                return out[:n]
+            cap = int(n)
 
     def interact(self, track, process, j0=1):
         tr = np.atleast_1d(track)

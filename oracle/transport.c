@@ -126,6 +126,53 @@ typedef struct {
     uint64_t n_guard, n_reject_cap;
 } orc_ledger;
 
+/* ------------------------------------------------------------------ decision margins
+ * Flip diagnosis (test infrastructure).  Every comparison that steers the
+ * control flow of a step notes how close its two sides were, |a - b| / scale,
+ * with a scale that matches how each side's rounding error grows (the larger
+ * operand; 1 for uniforms and direction components; max(|plane|, 1 cm) for
+ * positions against planes).  The smallest margin of a step and its kind say
+ * how far the step was from taking another discrete decision.  Recording is
+ * off (a null pointer) except in orc_step_margin and orc_trace_event; it reads
+ * values only and changes nothing that the step computes. */
+enum {
+    M_NONE = 0, M_CUT_START, M_THRESHOLD, M_LOSS_VS_INT, M_RANGE_FINAL, M_GEO_VS_PHYS, M_FACE_TIE, M_DIR_SIGN,
+    M_CHORD_BEYOND, M_CHORD_FACE_TIE, M_CHORD_AT_START, M_NEAR_FACE, M_SEARCH_ACCEPT, M_LAST_SUBSTEP,
+    M_CUT_AFTER_LOSS, M_PROCESS, M_REJECT, M_BRANCH, M_SECONDARY_CUT, M_ROTATE_POLE
+};
+typedef struct {
+    double margin;
+    int32_t kind;
+    int32_t n_notes;
+} orc_margin;
+
+static __thread orc_margin* g_margin = NULL;
+
+static void note(int kind, double a, double b, double scale)
+{
+    if (!g_margin) return;
+    g_margin->n_notes += 1;
+    double m = scale > 0.0 ? fabs(a - b) / scale : INFINITY;
+    if (m < g_margin->margin) {
+        g_margin->margin = m;
+        g_margin->kind = kind;
+    }
+}
+
+/* relative to the larger operand */
+static void note_rel(int kind, double a, double b)
+{
+    note(kind, a, b, fmax(fabs(a), fabs(b)));
+}
+
+/* a sign test of a value that is exactly zero only by construction (a
+ * direction component that the field never changes, a chord starting on the
+ * plane it was snapped to): an exact zero is the same on any machine */
+static void note_sign(int kind, double a, double scale)
+{
+    if (a != 0.0) note(kind, a, 0.0, scale);
+}
+
 /* ------------------------------------------------------------------ Philox */
 static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo)
 {
@@ -227,10 +274,14 @@ static double xs(const orc_problem* pb, int mat, int proc, double T)
     switch (proc) {
     case P_COMPTON: return lookup(tab(pb, mat, T_COMPTON), T);
     case P_PHOTO:   return lookup(tab(pb, mat, T_PHOTO), T);
-    case P_PAIR:    return T <= 2.0 * ORC_ME ? 0.0 : lookup(tab(pb, mat, T_PAIR), T);
-    case P_MOLLER:  return T <= 2.0 * pb->ecut ? 0.0 : lookup(tab(pb, mat, T_MOLLER), T);
-    case P_BHABHA:  return T <= pb->ecut ? 0.0 : lookup(tab(pb, mat, T_BHABHA), T);
-    case P_BREMS:   return T <= pb->ecut ? 0.0 : lookup(tab(pb, mat, T_BREMS), T);
+    case P_PAIR:    note_rel(M_THRESHOLD, T, 2.0 * ORC_ME);
+                    return T <= 2.0 * ORC_ME ? 0.0 : lookup(tab(pb, mat, T_PAIR), T);
+    case P_MOLLER:  note_rel(M_THRESHOLD, T, 2.0 * pb->ecut);
+                    return T <= 2.0 * pb->ecut ? 0.0 : lookup(tab(pb, mat, T_MOLLER), T);
+    case P_BHABHA:  note_rel(M_THRESHOLD, T, pb->ecut);
+                    return T <= pb->ecut ? 0.0 : lookup(tab(pb, mat, T_BHABHA), T);
+    case P_BREMS:   note_rel(M_THRESHOLD, T, pb->ecut);
+                    return T <= pb->ecut ? 0.0 : lookup(tab(pb, mat, T_BREMS), T);
     }
     return 0.0;
 }
@@ -263,6 +314,7 @@ static void rotate(const double u[3], double c, double phi, double out[3])
     double s = sqrt(1.0 - c * c);
     double cp = cos(phi), sp = sin(phi);
     double a = sqrt(1.0 - u[2] * u[2]);
+    note(M_ROTATE_POLE, a, 1.0e-10, 1.0);
     if (a > 1.0e-10) {
         out[0] = u[0] * c + s * (u[0] * u[2] * cp - u[1] * sp) / a;
         out[1] = u[1] * c + s * (u[1] * u[2] * cp + u[0] * sp) / a;
@@ -333,11 +385,13 @@ static void compton(const orc_problem* pb, orc_track* t, int* j, orc_step_result
     double eps = 1.0, omc = 0.0;
     for (int trial = 0; trial < ORC_MAX_TRIALS; ++trial) {
         double a = draw(pb, t, j), b = draw(pb, t, j), c = draw(pb, t, j);
+        note(M_BRANCH, a * (a1 + a2), a1, a1 + a2);
         if (a * (a1 + a2) < a1) eps = exp(-a1 * b);
         else eps = sqrt(e0sq + (1.0 - e0sq) * b);
         omc = (1.0 - eps) / (kap * eps);
         double sin2 = omc * (2.0 - omc);
         double g = 1.0 - eps * sin2 / (1.0 + eps * eps);
+        note(M_REJECT, c, g, 1.0);
         if (c <= g) break;
         if (trial == ORC_MAX_TRIALS - 1) res->reject_capped = 1;
     }
@@ -346,6 +400,8 @@ static void compton(const orc_problem* pb, orc_track* t, int* j, orc_step_result
     rotate(t->u, 1.0 - omc, phi, up);
     double Ep = eps * E;
     double Te = E - Ep;
+    note_rel(M_SECONDARY_CUT, Te, pb->ecut);
+    note_rel(M_SECONDARY_CUT, Ep, pb->ecut);
     if (Te >= pb->ecut) {
         double ue[3] = {E * t->u[0] - Ep * up[0], E * t->u[1] - Ep * up[1], E * t->u[2] - Ep * up[2]};
         normalize(ue);
@@ -366,6 +422,7 @@ static void compton(const orc_problem* pb, orc_track* t, int* j, orc_step_result
 static void photoelectric(const orc_problem* pb, orc_track* t, orc_step_result* res)
 {
     double Te = t->T;
+    note_rel(M_SECONDARY_CUT, Te, pb->ecut);
     if (Te >= pb->ecut) add_secondary(res, t, ELECTRON, Te, t->u, child_key(pb, t->event, t->key, t->step, 0));
     else deposit(res, Te);
     t->T = 0.0;
@@ -378,10 +435,13 @@ static void pair(const orc_problem* pb, orc_track* t, int* j, orc_step_result* r
     for (int trial = 0; trial < ORC_MAX_TRIALS; ++trial) {
         x = a + (1.0 - 2.0 * a) * draw(pb, t, j);
         double acc = draw(pb, t, j);
+        note(M_REJECT, acc, 1.0 - 4.0 / 3.0 * x * (1.0 - x), 1.0);
         if (acc <= 1.0 - 4.0 / 3.0 * x * (1.0 - x)) break;
         if (trial == ORC_MAX_TRIALS - 1) res->reject_capped = 1;
     }
     double Tp = x * E - ORC_ME, Tm = (1.0 - x) * E - ORC_ME;
+    note_rel(M_SECONDARY_CUT, Tm, pb->ecut);
+    note_rel(M_SECONDARY_CUT, Tp, pb->ecut);
     if (Tm >= pb->ecut) add_secondary(res, t, ELECTRON, Tm, t->u, child_key(pb, t->event, t->key, t->step, 0));
     else deposit(res, Tm);
     uint64_t kp = child_key(pb, t->event, t->key, t->step, 1);
@@ -410,6 +470,8 @@ static void delta_final_state(const orc_problem* pb, orc_track* t, double eps, i
     double p = sqrt(T * (T + 2.0 * ORC_ME)), pd = sqrt(Td * (Td + 2.0 * ORC_ME));
     double un[3] = {p * t->u[0] - pd * ud[0], p * t->u[1] - pd * ud[1], p * t->u[2] - pd * ud[2]};
     double Tn = T - Td;
+    note_rel(M_SECONDARY_CUT, Td, pb->ecut);
+    note_rel(M_SECONDARY_CUT, Tn, pb->ecut);
     if (Td >= pb->ecut) add_secondary(res, t, ELECTRON, Td, ud, child_key(pb, t->event, t->key, t->step, 0));
     else deposit(res, Td);
     if (Tn < pb->ecut) {
@@ -435,6 +497,7 @@ static void moller(const orc_problem* pb, orc_track* t, int* j, orc_step_result*
         double acc = draw(pb, t, j);
         double f = eps * eps * (C1 + 1.0 / (eps * eps) + 1.0 / ((1.0 - eps) * (1.0 - eps))
                                 - C2 / (eps * (1.0 - eps)));
+        note(M_REJECT, acc * bound, f, bound);
         if (acc * bound <= f) break;
         if (trial == ORC_MAX_TRIALS - 1) res->reject_capped = 1;
     }
@@ -456,6 +519,7 @@ static void bhabha(const orc_problem* pb, orc_track* t, int* j, orc_step_result*
         eps = xc / (1.0 - draw(pb, t, j) * (1.0 - xc));
         double acc = draw(pb, t, j);
         double f = 1.0 - b2 * (B1 * eps - B2 * eps * eps + B3 * eps * eps * eps - B4 * eps * eps * eps * eps);
+        note(M_REJECT, acc, f, 1.0);
         if (acc <= f) break;
         if (trial == ORC_MAX_TRIALS - 1) res->reject_capped = 1;
     }
@@ -471,10 +535,13 @@ static void brems(const orc_problem* pb, orc_track* t, int* j, orc_step_result* 
     for (int trial = 0; trial < ORC_MAX_TRIALS; ++trial) {
         y = yc * exp(draw(pb, t, j) * lr);
         double acc = draw(pb, t, j);
+        note(M_REJECT, acc, 1.0 - y + 0.75 * y * y, 1.0);
         if (acc <= 1.0 - y + 0.75 * y * y) break;
         if (trial == ORC_MAX_TRIALS - 1) res->reject_capped = 1;
     }
     double k = y * E;
+    note_rel(M_SECONDARY_CUT, k, pb->ecut);
+    note_rel(M_SECONDARY_CUT, T - k, pb->ecut);
     if (k >= pb->ecut) add_secondary(res, t, GAMMA, k, t->u, child_key(pb, t->event, t->key, t->step, 0));
     else deposit(res, k);
     double Tn = T - k;
@@ -506,6 +573,9 @@ static double straight_distance(const orc_problem* pb, const orc_track* t, int* 
     double W = pb->half_width;
     double dz = INFINITY, dx = INFINITY, dy = INFINITY;
     int fz = F_NONE, fx = F_NONE, fy = F_NONE;
+    note_sign(M_DIR_SIGN, t->u[0], 1.0);
+    note_sign(M_DIR_SIGN, t->u[1], 1.0);
+    note_sign(M_DIR_SIGN, t->u[2], 1.0);
     if (t->u[2] > 0.0) { dz = (zhi(pb, t->slab) - t->r[2]) / t->u[2]; fz = F_ZHI; }
     else if (t->u[2] < 0.0) { dz = (zlo(pb, t->slab) - t->r[2]) / t->u[2]; fz = F_ZLO; }
     if (t->u[0] > 0.0) { dx = (W - t->r[0]) / t->u[0]; fx = F_XHI; }
@@ -515,7 +585,9 @@ static double straight_distance(const orc_problem* pb, const orc_track* t, int* 
     dz = fmax(dz, 0.0); dx = fmax(dx, 0.0); dy = fmax(dy, 0.0);
     double d = dz;
     *face = fz;
+    if (isfinite(dx) && isfinite(d)) note_rel(M_FACE_TIE, dx, d);
     if (dx < d) { d = dx; *face = fx; }
+    if (isfinite(dy) && isfinite(d)) note_rel(M_FACE_TIE, dy, d);
     if (dy < d) { d = dy; *face = fy; }
     return d;
 }
@@ -567,10 +639,13 @@ static int chord_crossing(const orc_problem* pb, int slab, const double r[3], co
         int ax = face_axis(face);
         double p = face_plane(pb, slab, face);
         int beyond = (face == F_ZLO || face == F_XLO || face == F_YLO) ? (r1[ax] < p) : (r1[ax] > p);
+        note(M_CHORD_BEYOND, r1[ax], p, fmax(fabs(p), 1.0));
         if (!beyond) continue;
         double fr = (p - r[ax]) / (r1[ax] - r[ax]);
+        note_sign(M_CHORD_AT_START, fr, 1.0);
         if (fr < 0.0) fr = 0.0;
         if (fr > 1.0) fr = 1.0;
+        if (isfinite(bf)) note(M_CHORD_FACE_TIE, fr, bf, 1.0);
         if (fr < bf) { bf = fr; best = face; }
     }
     (void)W;
@@ -599,6 +674,7 @@ static int near_face(const orc_problem* pb, int slab, const double r[3])
     double bd = ORC_DINT;
     for (int face = F_ZLO; face <= F_YHI; ++face) {
         double d = fabs(r[face_axis(face)] - face_plane(pb, slab, face));
+        note(M_NEAR_FACE, d, bd, ORC_DINT);
         if (d <= bd && (best == F_NONE || d < bd)) { bd = d; best = face; }
     }
     return best;
@@ -627,6 +703,7 @@ double orc_propagate_field(const orc_problem* pb, orc_track* t, double s_phys, i
     for (;;) {
         double rem = s_phys - s_done;
         double h = h_try > 0.0 ? h_try : fmin(rem, h_chord);
+        if (h_try == 0.0) note_rel(M_LAST_SUBSTEP, rem, h_chord);
         int last = (h_try == 0.0 && h == rem);
         double r1[3], u1[3];
         orc_rk4(t->r, t->u, h, kf, pb->B, r1, u1);
@@ -650,6 +727,7 @@ double orc_propagate_field(const orc_problem* pb, orc_track* t, double s_phys, i
             n_search = 0;
             continue;
         }
+        if (f == 0.0) note_sign(M_DIR_SIGN, t->u[face_axis(fc)], 1.0);
         if (f == 0.0 && points_out(t->u, fc)) {
             /* already on the plane and heading out: leave without moving */
             t->r[face_axis(fc)] = face_plane(pb, t->slab, fc);
@@ -658,6 +736,7 @@ double orc_propagate_field(const orc_problem* pb, orc_track* t, double s_phys, i
         }
         double ch[3] = {r1[0] - t->r[0], r1[1] - t->r[1], r1[2] - t->r[2]};
         double clen = sqrt(ch[0] * ch[0] + ch[1] * ch[1] + ch[2] * ch[2]);
+        if (n_search < ORC_MAX_SEARCH) note(M_SEARCH_ACCEPT, (1.0 - f) * clen, ORC_DINT, ORC_DINT);
         if ((1.0 - f) * clen <= ORC_DINT || n_search >= ORC_MAX_SEARCH) {
             for (int c = 0; c < 3; ++c) t->r[c] = t->r[c] + f * ch[c];
             t->r[face_axis(fc)] = face_plane(pb, t->slab, fc);
@@ -730,6 +809,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
     int j = 0;
 
     /* a track below the tracking cut is stopped at the start of its step */
+    note_rel(M_CUT_START, t->T, pb->ecut);
     if (t->T < pb->ecut) {
         if (charged) stop_track(pb, t, res);
         else { deposit(res, t->T); t->T = 0.0; t->alive = 0; }
@@ -753,6 +833,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
     if (charged) {
         R = lookup(range_tab(pb, mat, t->type), t->T);
         double s_loss = R <= ORC_R_FINAL ? R : fmax(ORC_R_FINAL, ORC_RHO_RANGE * R);
+        if (isfinite(s_int)) note_rel(M_LOSS_VS_INT, s_loss, s_int);
         if (s_loss < s_int) { s_phys = s_loss; loss_limited = 1; }
     }
     /* S4, S5 */
@@ -760,6 +841,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
     int face = F_NONE;
     if (!charged || !has_field(pb)) {
         double s_geo = straight_distance(pb, t, &face);
+        if (isfinite(s_geo) && isfinite(s_phys)) note_rel(M_GEO_VS_PHYS, s_geo, s_phys);
         if (s_geo <= s_phys) s = s_geo;
         else { s = s_phys; face = F_NONE; }
         for (int c = 0; c < 3; ++c) t->r[c] = t->r[c] + s * t->u[c];
@@ -772,6 +854,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
 
     /* S6 */
     if (charged) {
+        if (face == F_NONE && loss_limited) note_rel(M_RANGE_FINAL, R, ORC_R_FINAL);
         if (face == F_NONE && loss_limited && R <= ORC_R_FINAL) {
             stop_track(pb, t, res);
             res->outcome = OUT_STOP;
@@ -779,6 +862,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
             return;
         }
         double Tn = inverse_range(range_tab(pb, mat, t->type), R - s);
+        note_rel(M_CUT_AFTER_LOSS, Tn, pb->ecut);
         if (Tn < pb->ecut) {
             stop_track(pb, t, res);
             res->outcome = OUT_STOP;
@@ -826,6 +910,7 @@ void orc_step(const orc_problem* pb, orc_track* t, orc_step_result* res)
             int proc = proc_of(t->type, n_procs(t->type) - 1);
             for (int n = 0; n < n_procs(t->type); ++n) {
                 cum += xs(pb, mat, proc_of(t->type, n), t->T);
+                if (n < n_procs(t->type) - 1) note(M_PROCESS, target, cum, sig1);
                 if (target < cum) { proc = proc_of(t->type, n); break; }
             }
             res->process = proc;
@@ -949,6 +1034,54 @@ uint64_t orc_run_events(const orc_problem* pb, const orc_track* prims, const uin
     free(args);
     free(order);
     free(row_start);
+    return steps;
+}
+
+/* ------------------------------------------------------------------ flip diagnosis
+ * One step with its decision margins recorded (see note()). */
+void orc_step_margin(const orc_problem* pb, orc_track* t, orc_step_result* res, orc_margin* m)
+{
+    m->margin = INFINITY;
+    m->kind = M_NONE;
+    m->n_notes = 0;
+    g_margin = m;
+    orc_step(pb, t, res);
+    g_margin = NULL;
+}
+
+/* one recorded step of an event history: the track before and after it, the
+ * step's result and the smallest decision margin of the step */
+typedef struct {
+    orc_track pre;
+    orc_track post;
+    orc_step_result res;
+    orc_margin m;
+} orc_trace_rec;
+
+/* Transport the n primaries of one event exactly as orc_run_events does (LIFO
+ * over secondaries) and record every step in history order: a step's
+ * ancestors (its track's earlier steps, the step that created the track)
+ * always come before it.  Writes up to `cap` records and returns the number
+ * of steps. */
+uint64_t orc_trace_event(const orc_problem* pb, const orc_track* prims, uint64_t n, orc_trace_rec* out, uint64_t cap)
+{
+    stack_t_ st = {0, 0, 0};
+    for (uint64_t i = 0; i < n; ++i) push(&st, &prims[i]);
+    uint64_t steps = 0;
+    orc_trace_rec rec;
+    while (st.n > 0) {
+        orc_track t = st.v[--st.n];
+        t.alive = 1;
+        while (t.alive) {
+            rec.pre = t;
+            orc_step_margin(pb, &t, &rec.res, &rec.m);
+            rec.post = t;
+            if (steps < cap) out[steps] = rec;
+            steps += 1;
+            for (int k = 0; k < rec.res.n_sec; ++k) push(&st, &rec.res.sec[k]);
+        }
+    }
+    free(st.v);
     return steps;
 }
 

@@ -247,3 +247,55 @@ def test_single_step_brute_force():
                 expect = procs[int(b["type"])][int(np.argmax(target < cum))]
                 assert r["process"] == expect, i
     assert n_inter > 20
+
+
+# ---------------------------------------------------------------- flip diagnosis hooks
+def test_margin_recording_changes_nothing_and_trace_equals_run():
+    """Recording decision margins reads values only: single steps and whole
+    event histories are bit-identical with and without it, and the trace of
+    an event sums to orc_run_events' deposits, ledger and step count."""
+    import numpy as np
+    from tests.gpu_helpers import random_states
+    w = workloads.electron_showers_1gev_field(2)
+    pb = oracle.problem_for(w)
+    st = random_states(w, 2000, np.random.default_rng(3))
+    a, b = st.copy(), st.copy()
+    ra = pb.step(a)
+    rb, m = pb.step_margins(b)
+    assert np.array_equal(a, b) and np.array_equal(ra, rb)
+    assert np.all(m["margin"] >= 0) and np.all(m["n_notes"] > 0)
+    tr, rows = oracle.tracks_from_primaries(w.primaries[:1])
+    t = pb.trace_event(tr)
+    e, led, steps = pb.run_events(tr, rows[:1] * 0, 1, 1)
+    assert len(t) == steps == led["steps"][0]
+    dep = np.zeros(pb.n_slabs)
+    np.add.at(dep, t["res"]["dep_slab"], t["res"]["edep"])
+    assert np.array_equal(dep, e[0])
+    assert t["res"]["escaped"].sum() == led["escaped"][0]
+    assert t["res"]["n_pair"].sum() == led["n_pair"][0]
+    # history order: every step's track was created by an earlier step
+    seen = {int(tr["key"][0])}
+    for r in t:
+        assert int(r["pre"]["key"]) in seen
+        for k in range(int(r["res"]["n_sec"])):
+            seen.add(int(r["res"]["sec"][k]["key"]))
+
+
+def test_margin_of_a_step_at_a_threshold():
+    """A positron 1e-9 above the cut: the smallest margin of its step is the
+    cut / process-threshold decision, at 1e-9 relative; a step far from every
+    threshold has a much larger margin."""
+    import numpy as np
+    w = workloads.small_electron_showers(1)
+    pb = oracle.problem_for(w)
+    t = np.zeros(2, dtype=oracle.TRACK_DTYPE)
+    t["type"] = oracle.POSITRON
+    t["T"] = [w.ecut * (1 + 1e-9), 5.0]
+    t["nl"] = [-1.0, 0.3]
+    t["r"] = [(0.1, 0.2, 0.05), (0.1, 0.2, 0.05)]
+    t["u"] = [(0.0, 0.6, 0.8), (0.0, 0.6, 0.8)]
+    t["alive"] = 1
+    _, m = pb.step_margins(t)
+    assert m["margin"][0] == pytest.approx(1e-9, rel=1e-3)
+    assert oracle.MARGIN_KINDS[m["kind"][0]] in ("cut at step start", "process threshold")
+    assert m["margin"][1] > 1e-6
