@@ -333,6 +333,24 @@ ems_status ems_debug_read_secondaries(ems_ctx* ctx, ems_track* out, uint64_t cap
  * Paper: "Reindexing track slots" (sorting the slot indices, not the state). */
 ems_status ems_debug_sort(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm);
 
+/* Allocation-free variant of ems_debug_sort, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same stable counting sort of n small
+ * keys (PARTITION: keys < 16; RADIX: keys < 128) through the same kernels,
+ * with `keys` (n bytes) and `perm` (n uint32) in DEVICE memory owned by the
+ * caller, enqueued on the context's stream without any host wait, copy,
+ * memset or allocation.  perm[i] = index of the i-th smallest key, equal keys
+ * in index order; keys at or above the policy's bin count are left out (perm
+ * then holds the valid keys' order in its first entries, the rest untouched).
+ * The per-tile histograms live in a fixed device array of the library (4 MiB
+ * + 512 B per device, held until the process ends); every word a call reads
+ * is written by that call first, so nothing is cleared between calls.  Calls
+ * that overlap on one GPU (other streams, other contexts, other threads)
+ * share that array and race: serialize them.  The context's device must be
+ * current.  Errors: INVALID_ARG (null pointer, policy), CAPACITY (n > 2^23),
+ * STATE (another device current), DEVICE. */
+ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm);
+
 /* Run-time tuning (the autotuner's knobs; results do not depend on them).
  * block[i] is the block size of kernel role i (role order as returned by
  * ems_profile_read: vacancies, init, pre_step (unused: the along-step

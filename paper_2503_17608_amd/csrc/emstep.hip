@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -548,6 +549,42 @@ void launch_completions(ems_ctx* c)
         hipLaunchKernelGGL((k_scan_completions<double>), dim3(nb), dim3(256), 0, c->stream, make_dev<double>(c));
 }
 
+// ---- fixed scratch for the allocation-free sort entry point --------------------
+// The per-tile histograms and bin totals of one sort of up to kNoAllocMaxKeys
+// keys with up to 128 bins: 128 * 8192 + 128 words = 4 MiB + 512 B, held by
+// every device the library runs on until the process ends.  Host code never
+// uses the array's name as an address: each device's copy has its own
+// address, taken once per device with hipGetSymbolAddress.
+constexpr uint64_t kNoAllocMaxKeys = 1ull << 23;
+constexpr uint64_t kNoAllocTiles = kNoAllocMaxKeys / kSortTile;
+constexpr uint64_t kNoAllocWords = 128 * kNoAllocTiles + 128;
+__device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (taken on first use per
+// device, with that device current).  Returns null with the error set.
+uint32_t* scratch_on_device(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        fail(EMS_ERR_DEVICE, "device index beyond the scratch table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            fail(EMS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (uint32_t*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 ems_status check_ready(ems_ctx* c)
 {
     if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
@@ -789,6 +826,10 @@ ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t b
     c->ln_e0 = std::log(kEmin);
     c->dlog = std::log(10.0) / 20.0;
     (void)hipGetDevice(&c->device);
+    if (!scratch_on_device(c->device)) {
+        delete c;
+        return EMS_ERR_DEVICE;
+    }
     c->row_event.assign(opt->max_events, UINT64_MAX);
     c->row_pending.assign(opt->max_events, 0);
     c->row_gen.assign(opt->max_events, 0);
@@ -1354,6 +1395,45 @@ ems_status ems_debug_sort(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t p
     HIP_TRY(try_(hipMemcpyAsync(perm, dp, 4 * n, hipMemcpyDeviceToHost, c->stream)));
     HIP_TRY(try_(hipStreamSynchronize(c->stream)));
     release();
+    return EMS_OK;
+}
+
+ems_status ems_sort_keys_noalloc(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t policy, uint32_t* perm)
+{
+    if (!c) return fail(EMS_ERR_INVALID_ARG, "null context");
+    if (policy != EMS_SORT_PARTITION && policy != EMS_SORT_RADIX) return fail(EMS_ERR_INVALID_ARG, "policy");
+    if (n == 0) return EMS_OK;
+    if (!keys || !perm) return fail(EMS_ERR_INVALID_ARG, "null keys or perm");
+    if (n > kNoAllocMaxKeys)
+        return fail(EMS_ERR_CAPACITY, "ems_sort_keys_noalloc sorts at most 2^23 keys (fixed scratch of 4 MiB)");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device) return fail(EMS_ERR_STATE, "the context's device must be current");
+    uint32_t* ptr = scratch_on_device(dev);
+    if (!ptr) return EMS_ERR_DEVICE;
+    const uint32_t nt = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    // counts [bin][tile] and the bin totals after them; every word the sort
+    // reads is written by this call's histogram and scan kernels first, so
+    // nothing needs clearing between calls
+    uint32_t* cnt = ptr;
+    uint32_t* tot = ptr + 128 * kNoAllocTiles;
+    Dev<double> d{};
+    if (policy == EMS_SORT_PARTITION) {
+        hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, keys,
+                           (uint32_t)n, cnt, nt);
+        hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
+                           tot);
+        hipLaunchKernelGGL((k_sort_scatter<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, keys,
+                           (uint32_t)n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, perm);
+    } else {
+        hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, keys,
+                           (uint32_t)n, cnt, nt);
+        hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
+                           tot);
+        hipLaunchKernelGGL((k_sort_scatter<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, keys,
+                           (uint32_t)n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, perm);
+    }
+    HIP_TRY(hipGetLastError());
     return EMS_OK;
 }
 

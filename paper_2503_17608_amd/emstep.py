@@ -112,6 +112,7 @@ _sigs = {
     "ems_debug_read_tracks": (C.c_int, [_P, _P, C.c_uint64]),
     "ems_debug_read_secondaries": (C.c_int, [_P, _P, C.c_uint64, C.POINTER(C.c_uint64)]),
     "ems_debug_sort": (C.c_int, [_P, _P, C.c_uint64, C.c_int32, _P]),
+    "ems_sort_keys_noalloc": (C.c_int, [_P, _P, C.c_uint64, C.c_int32, _P]),
     "ems_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
     "ems_get_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
     "ems_profile_enable": (C.c_int, [_P, C.c_int32]),
@@ -315,6 +316,16 @@ class Session:
         perm = np.zeros(len(k), dtype=np.uint32)
         _check(_lib.ems_debug_sort(self._h, _ptr(k), len(k), SORT_POLICIES[policy], _ptr(perm)), "ems_debug_sort")
         return perm
+
+    def sort_device(self, keys, perm, policy="partition"):
+        """Allocation-free sort of device keys (torch uint8 tensor) into the
+        device permutation `perm` (torch int32/uint32 tensor of the same
+        length), enqueued on the session's stream."""
+        assert keys.is_cuda and perm.is_cuda and keys.dtype == torch.uint8 and perm.element_size() == 4
+        assert keys.is_contiguous() and perm.is_contiguous() and perm.numel() >= keys.numel()
+        _check(_lib.ems_sort_keys_noalloc(self._h, C.c_void_p(keys.data_ptr()), keys.numel(),
+                                          SORT_POLICIES[policy], C.c_void_p(perm.data_ptr())),
+               "ems_sort_keys_noalloc")
 
     def tuning(self):
         t = Tuning()
