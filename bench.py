@@ -4,7 +4,8 @@ One benchmark step is one pass of the whole hot path over one batch: every
 primary of the workload transported until no track is alive, queued or
 pending (vacancy compaction, initialization, pre-step, sort, along-step,
 interactions, tallies).  Primaries are copied to the device before the timed
-region of each step; the timed region covers the device loop only.
+region of each step; `value` times the device loop only (inputs resident in
+HBM), and `io_inclusive` times push + loop + readback of every tally.
 
 Default workload: 10^4 electrons of 1 GeV into a 50-layer Pb (2 mm) / liquid
 Ar (5 mm) stack, 40 x 40 cm, uniform 1 T field along x, 0.1 MeV cut, 2^20
@@ -14,20 +15,28 @@ last tracks (below 65536 alive, queued or pending) stepped in block-local loops 
 the drain kernel.
 
 The JSON line carries the dominant kernel's roofline: algorithmic bytes per
-launch (the kernel's work counter times its per-track field traffic) divided
-by its average launch duration, measured with HIP start/stop events stamped by
-the kernel's own dispatch packets in one extra pass over the same batch (graph
-replay off for that pass); `traffic` is the calibrated hardware byte count per
-launch from a committed counter summary, when one was taken on the current
-kernel sources and this configuration,
-and the oracle's throughput on the host cores for a bounded sample of the same
-events.
+launch (the kernel's units of work times the bytes per unit fixed from the
+state's field widths) divided by its average launch duration, measured with
+HIP start/stop events stamped by the kernel's own dispatch packets in one
+extra pass over the same batch (graph replay off for that pass); `traffic`
+is the calibrated hardware byte count per launch from a committed counter
+summary, when one was taken on the current kernel sources and this
+configuration; and the oracle's throughput on the host cores for a bounded
+sample of the same events.
+
+The rest of the metric comes in the same line (skip with --no-extras):
+`unsorted` (the same run with sort policy none), `precision_pair` (mixed
+precision against FP64 on 10^4 mixed-species primaries in a 5 degree cone,
+with the mixed run's per-layer error against the FP64 oracle) and `serving`
+(continuous batching of 1000 events of 1-200 primaries at Poisson arrival
+rates 0.5 / 0.7 / 0.9 x the sustained event rate of the closed FP64 batch of
+the same events, p50/p99 latency in mixed precision and FP64, and the mixed
+serving run's per-layer error against the FP64 oracle on a subsample).
 
 Other modes: --autotune (tune policy / tail threshold / block sizes /
 fusion / drain on the workload first), --layer-error (per-layer deposit of
-this run against the FP64 oracle on the same events), --serve (continuous
-batching with Poisson arrivals: p50/p99 event latency and throughput, against
-plain FP64 batch stepping of the same events).
+this run against the FP64 oracle on the same events), --serve (the serving
+section alone).
 """
 from __future__ import annotations
 
@@ -44,24 +53,50 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per processed track for each kernel: the SoA fields a
-# participating track reads and writes (FP64 / mixed widths), plus 16 B of
-# tally read-modify-write for charged steps.  The along-step kernels run the
-# pre-step first: it reads fields the step reads anyway and writes n_lambda,
-# Sigma, s_phys, flags and action (26 / 18 B), which are counted here.  E.g.
-# the field along-step reads type, flags, search count (3), slab (2), row,
-# step (8), key (8), T, n_lambda, Sigma (24 / 12), s_phys, s_done, h_try (24),
-# r (24) and u (24 / 12): 117 / 93 B; it writes r, u, T, n_lambda, s_done,
-# h_try, search, flags, slab, action and step: 89 / 69 B; with the deposit
-# and the pre-step's writes 248 / 196 B.
-BYTES_PER_TRACK = {
-    "f64": {"along_neutral": 174, "along_charged": 190, "along_field": 248,
-            "compton": 122, "photoelectric": 122, "pair": 122, "moller": 122, "bhabha": 122,
-            "bremsstrahlung": 122, "annihilation": 122, "init": 206},
-    "mixed": {"along_neutral": 142, "along_charged": 158, "along_field": 196,
-              "compton": 102, "photoelectric": 102, "pair": 102, "moller": 102, "bhabha": 102,
-              "bremsstrahlung": 102, "annihilation": 102, "init": 174},
+# Algorithmic bytes per unit of work, fixed before any measurement from the
+# per-slot field widths of the state (FP64 / mixed): the fields a track that
+# takes an action reads and writes, independent of how a kernel moves them.
+#   pre-step 53 / 41, neutral along-step 110 / 86, charged along-step
+#   134 / 106, field along-step 174 / 134 per completed step and 112 / 100 per
+#   paused trip, deposit 16 (tally read-modify-write), interaction 116 / 84,
+#   secondary 71 / 59 (initializer record written by the interaction) and
+#   172 / 140 when it is initialized (record read, state written), post-step
+#   19 / 15 per completed along-step.
+# The along-step kernels run the pre-step of their tracks (a resumed field
+# step has none) and fold the post-step in; the charged ones deposit.
+UNIT_BYTES = {
+    "f64": {"pre": 53, "neutral": 110, "charged": 134, "field": 174, "pause": 112, "deposit": 16,
+            "interaction": 116, "secondary": 71, "init": 172, "post": 19},
+    "mixed": {"pre": 41, "neutral": 86, "charged": 106, "field": 134, "pause": 100, "deposit": 16,
+              "interaction": 84, "secondary": 59, "init": 140, "post": 15},
 }
+INTERACTIONS = ("compton", "photoelectric", "pair", "moller", "bhabha", "bremsstrahlung", "annihilation")
+
+
+def kernel_bytes(kernel, work, precision):
+    """Algorithmic bytes of `kernel` for the work counters `work` (tracks
+    processed per role, paused field trips)."""
+    u = UNIT_BYTES[precision]
+    if kernel == "along_field":
+        trips, paused = work.get("along_field", 0), work.get("field_paused", 0)
+        done = trips - paused
+        # every trip that is not a resumption runs the pre-step; in the
+        # steady state resumptions equal the pauses of the launch before
+        return done * (u["field"] + u["pre"] + u["deposit"] + u["post"]) + paused * u["pause"]
+    if kernel == "along_neutral":
+        return work.get("along_neutral", 0) * (u["neutral"] + u["pre"] + u["post"])
+    if kernel == "along_charged":
+        return work.get("along_charged", 0) * (u["charged"] + u["pre"] + u["deposit"] + u["post"])
+    if kernel == "interactions":
+        return sum(work.get(k, 0) for k in INTERACTIONS) * u["interaction"]
+    if kernel == "init":
+        return work.get("init", 0) * u["init"]
+    if kernel == "drain":
+        # a drain trip counts as a field step with its pre-step (its
+        # interactions and secondaries are not counted)
+        return work.get("drain", 0) * (u["field"] + u["pre"] + u["deposit"] + u["post"])
+    raise KeyError(kernel)
+
 
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -138,6 +173,10 @@ def parse():
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate / closed-batch event rate")
     ap.add_argument("--extra-loads", type=float, nargs="*", default=[0.5, 0.9],
                     help="further loads served (same arrival seed) after the main one")
+    ap.add_argument("--serve-sample-every", type=int, default=20,
+                    help="per-layer error of the mixed-precision serving run on every n-th event (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the main workload only: no unsorted rate, precision pair or serving section")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size three times (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -293,15 +332,16 @@ def measured_copy_gbs(mib=1024, repeats=10):
     return 2.0 * repeats * (mib << 20) / sec / 1e9
 
 
-def path_roofline(work, steps, rate, precision):
+def path_roofline(work, steps, rate, precision, n_primaries):
     """Whole-path HBM roofline: algorithmic bytes per track-step (every step
-    kernel's processed tracks times its per-track field traffic, summed over
-    the batch, divided by the steps) times track-steps/s, against the HBM
-    peak.  A drain trip counts as a field along-step with its pre-step (its
-    interactions are not counted)."""
-    bpt = BYTES_PER_TRACK[precision]
-    total = sum(work.get(k, 0) * b for k, b in bpt.items())
-    total += work.get("drain", 0) * bpt["along_field"]
+    kernel's units of work times its bytes per unit, summed over the batch,
+    divided by the steps) times track-steps/s, against the HBM peak.
+    Secondaries add their initializer record (the interaction writes it);
+    their initialization is counted by the fill."""
+    total = sum(kernel_bytes(k, work, precision) for k in ("along_field", "along_neutral", "along_charged",
+                                                           "interactions", "init", "drain"))
+    secondaries = max(work.get("init", 0) + work.get("reused_slots", 0) - n_primaries, 0)
+    total += secondaries * UNIT_BYTES[precision]["secondary"]
     b_step = total / max(steps, 1)
     achieved = rate * b_step / 1e9
     return {"bound": "hbm", "bytes_per_step": b_step, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -322,7 +362,37 @@ def layer_error(w, edep):
             "total_rel_err": float(abs(lg.sum() - lr.sum()) / lr.sum())}
 
 
-def serve_mode(args):
+def layer_error_events(w, edep, events):
+    """Per-layer mean deposit of `edep` (rows = `events`) against the FP64
+    oracle on the same events (layers holding >= 1 % of the total)."""
+    import oracle
+    import workloads
+    events = np.asarray(events, dtype=np.int64)
+    sel = np.isin(w.primaries["event"].astype(np.int64), events)
+    prims = w.primaries[sel].copy()
+    remap = {int(e): i for i, e in enumerate(events)}
+    # the oracle's rows are 0..n-1; a primary keeps its event id for the
+    # random-number key and goes to the row of its position in `events`
+    sub = workloads.Workload(w.name, w.stack, w.ecut, w.seed, len(events), prims, w.n_slots)
+    pb = oracle.problem_for(sub)
+    tr, _ = oracle.tracks_from_primaries(prims)
+    rows = np.array([remap[int(e)] for e in prims["event"]], dtype=np.uint32)
+    e_ref, _, _ = pb.run_events(tr, rows, len(events), len(os.sched_getaffinity(0)))
+    lg = edep.reshape(len(edep), -1, 2).sum(2).mean(0)
+    lr = e_ref.reshape(len(e_ref), -1, 2).sum(2).mean(0)
+    big = lr >= 0.01 * lr.sum()
+    err = np.abs(lg - lr) / np.where(lr > 0, lr, 1.0)
+    return {"max_rel_err_layers_ge_1pct": float(err[big].max()), "layers_checked": int(big.sum()),
+            "total_rel_err": float(abs(lg.sum() - lr.sum()) / lr.sum())}
+
+
+def serving_section(args, loads):
+    """Continuous batching of the serving workload in mixed precision and in
+    FP64: p50/p99 event latency and track-steps/s at arrival rates `loads` x
+    the sustained event rate of the closed FP64 batch of the same events
+    (all pushed at once, device-resident timing), and the mixed-precision
+    serving run's per-layer deposit against the FP64 oracle on a subsample
+    of its events."""
     import torch
 
     import workloads
@@ -331,55 +401,126 @@ def serve_mode(args):
     if args.slots:
         w.n_slots = args.slots
     events = serving.split_events(w.primaries)
-    precision = args.precision or "mixed"
-    # closed-batch event rate on a sample, to set the arrival rate
-    n_cal = min(64, len(events))
-    cal = np.concatenate([p for _, p in events[:n_cal]])
-    cal_ev = np.array([e for e, _ in events[:n_cal]], dtype=np.uint64)
-    s = new_session(w, args, precision, args.policy, args.init_partition)
-    time_batch(s, cal, cal_ev)
-    s.release(cal_ev)
-    _, dt_cal = time_batch(s, cal, cal_ev)
-    s.release(cal_ev)
-    batch_rate = n_cal / dt_cal
+    ev_ids = np.array([e for e, _ in events], dtype=np.uint64)
+    # closed FP64 batch of every event (warmed up on the first 64 events)
+    s64 = new_session(w, args, "f64", args.policy, args.init_partition)
+    warm = np.concatenate([p for _, p in events[:64]])
+    time_batch(s64, warm, None)
+    s64.release(ev_ids[:64])
+    c_before = s64.counters()["steps"]
+    c64, dt64 = time_batch(s64, w.primaries, None)
+    s64.release(ev_ids)
+    steps64 = c64["steps"] - c_before
+    event_rate = len(events) / dt64
 
-    def one(sess, load):
-        arrivals = workloads.poisson_arrival_times(w.seed, load * batch_rate, len(events))
+    sample = ev_ids[:: max(1, args.serve_sample_every)]
+
+    def one(sess, load, keep):
+        arrivals = workloads.poisson_arrival_times(w.seed, load * event_rate, len(events))
         torch.cuda.synchronize()
         res = serving.serve(sess, events, arrivals, track_budget=w.n_slots, iterations_per_poll=max(args.graph, 1),
-                            keep_results=False)
-        return {"load": load, "arrival_rate_hz": load * batch_rate,
-                "value": res.steps / res.wall_s, "unit": "track-steps/s",
-                "latency_ms": {"p50": 1e3 * res.percentile(50), "p99": 1e3 * res.percentile(99),
-                               "max": 1e3 * max(res.latency_s.values())},
-                "serve_wall_s": res.wall_s, "max_events_in_flight": res.max_in_flight,
-                "iterations": res.iterations, "ms_per_iteration": 1e3 * res.wall_s / max(res.iterations, 1)}
+                            keep_results=keep)
+        r = {"load": load, "arrival_rate_hz": load * event_rate,
+             "value": res.steps / res.wall_s, "unit": "track-steps/s",
+             "latency_ms": {"p50": 1e3 * res.percentile(50), "p99": 1e3 * res.percentile(99),
+                            "max": 1e3 * max(res.latency_s.values())},
+             "serve_wall_s": res.wall_s, "max_events_in_flight": res.max_in_flight,
+             "iterations": res.iterations, "ms_per_iteration": 1e3 * res.wall_s / max(res.iterations, 1)}
+        return r, res
 
-    main_run = one(s, args.load)
-    runs = {precision: [main_run]}
-    for load in args.extra_loads:
-        runs[precision].append(one(s, load))
-    s.close()
-    # the same arrivals served in plain FP64
-    s64 = new_session(w, args, "f64", args.policy, args.init_partition)
-    runs["f64"] = [one(s64, load) for load in [args.load] + list(args.extra_loads)]
-    # plain FP64 batch stepping of the same events
-    steps0 = s64.counters()["steps"]
-    c64, dt64 = time_batch(s64, w.primaries, [e for e, _ in events])
+    runs = {"mixed": [], "f64": []}
+    kept = None
+    smx = new_session(w, args, "mixed", args.policy, args.init_partition)
+    for k, load in enumerate(loads):
+        r, res = one(smx, load, keep=(k == 0))
+        if k == 0:
+            kept = res
+        runs["mixed"].append(r)
+    smx.close()
+    for load in loads:
+        runs["f64"].append(one(s64, load, keep=False)[0])
     s64.close()
-    steps64 = c64["steps"] - steps0
+    out = {"workload": w.name, "events": len(events), "primaries": int(len(w.primaries)), "n_slots": w.n_slots,
+           "closed_fp64_batch": {"value": steps64 / dt64, "unit": "track-steps/s", "seconds": dt64,
+                                 "track_steps": steps64, "event_rate_hz": event_rate},
+           "arrival_rate": "load x closed_fp64_batch.event_rate_hz (Poisson)", "runs": runs}
+    if args.serve_sample_every > 0:
+        edep = np.stack([kept.edep[int(e)] for e in sample])
+        le = layer_error_events(w, edep, sample)
+        le["sample"] = (f"every {args.serve_sample_every}th event of the mixed-precision serving run at load "
+                        f"{loads[0]} ({len(sample)} events)")
+        out["layer_error_mixed_serving_vs_fp64_oracle"] = le
+    return out
+
+
+def serve_mode(args):
+    loads = [args.load] + list(args.extra_loads)
+    sv = serving_section(args, loads)
+    main_run = sv["runs"]["mixed"][0]
     out = {
         "metric": "event latency p50/p99 and track-steps/s, continuous batching",
         "value": main_run["value"], "unit": "track-steps/s", "n_gpus": 1,
-        "higher_is_better": True, "dtype": "f32+f64" if precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": w.name, "events": len(events), "primaries": int(len(w.primaries)),
-                   "n_slots": w.n_slots, "closed_batch_event_rate_hz": batch_rate, "load": args.load,
-                   "sort_policy": args.policy, "graph_iterations": args.graph},
+        "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": sv["workload"], "events": sv["events"], "primaries": sv["primaries"],
+                   "n_slots": sv["n_slots"], "load": args.load, "sort_policy": args.policy,
+                   "graph_iterations": args.graph},
         "latency_ms": main_run["latency_ms"],
-        "runs": runs,
-        "fp64_batch": {"value": steps64 / dt64, "unit": "track-steps/s", "seconds": dt64},
+        "serving": sv,
     }
     print(json.dumps(out), flush=True)
+
+
+def io_inclusive_rate(w, args, precision):
+    """The main configuration timed from the push of the primaries (host
+    buffer -> device) to the readback of every event's tallies (device ->
+    host): the PCIe-inclusive rate, beside the device-resident `value`."""
+    import torch
+    s = new_session(w, args, precision, args.policy, args.init_partition)
+    events = np.unique(w.primaries["event"])
+    time_batch(s, w.primaries, events)
+    s.release(events)
+    tot, steps = 0.0, 0
+    for _ in range(args.steps):
+        c0 = s.counters()["steps"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.push(w.primaries)
+        c = s.run(max_iterations=10_000_000)
+        s.tallies_by_event(events)
+        tot += time.perf_counter() - t0
+        steps += c["steps"] - c0
+        s.release(events)
+    s.close()
+    return {"value": steps / tot, "unit": "track-steps/s", "ms_per_step": 1e3 * tot / args.steps,
+            "timed": "push of the primaries + stepping until empty + readback of every event's tallies"}
+
+
+def extras(args, w, precision, value, out):
+    """The rest of the metric in the same run: unsorted stepping with every
+    other setting equal, the PCIe-inclusive rate, mixed precision against
+    FP64 on the mixed-species cone workload (with its per-layer error
+    against the FP64 oracle), and the serving loop in both precisions."""
+    import workloads
+    t0 = time.perf_counter()
+    rv = run_variant(w, args, precision, "none", args.init_partition, None)
+    unsorted = rv["steps"] / rv["seconds"]
+    out["unsorted"] = {"sort_policy": "none", "value": unsorted, "unit": "track-steps/s",
+                       "sorted_over_unsorted": value / unsorted,
+                       "same_as_main": "every setting except the sort policy",
+                       "track_steps_per_step": rv["steps"] // args.steps}
+    out["io_inclusive"] = io_inclusive_rate(w, args, precision)
+    wc = workloads.mixed_cone_showers()
+    pair = {"workload": wc.name, "events": wc.n_events, "n_slots": wc.n_slots}
+    for prec in ("f64", "mixed"):
+        rc = run_variant(wc, args, prec, args.policy, args.init_partition, None)
+        pair[prec] = {"value": rc["steps"] / rc["seconds"], "unit": "track-steps/s",
+                      "track_steps_per_step": rc["steps"] // args.steps}
+        if prec == "mixed":
+            pair["layer_error_mixed_vs_fp64_oracle"] = layer_error(wc, rc["edep"])
+    pair["mixed_over_f64"] = pair["mixed"]["value"] / pair["f64"]["value"]
+    out["precision_pair"] = pair
+    out["serving"] = serving_section(args, [0.5, 0.7, 0.9])
+    out["extras_wall_s"] = time.perf_counter() - t0
 
 
 def main():
@@ -442,9 +583,9 @@ def main():
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
         tracks = r["work_prof"][prof_kernel]
-        bpt = BYTES_PER_TRACK[precision][prof_kernel]
         avg_s = ms / 1e3 / launches
-        per_launch = tracks * bpt / launches
+        per_launch = kernel_bytes(prof_kernel, r["work_prof"], precision) / launches
+        bpt = per_launch * launches / max(tracks, 1)
         achieved = per_launch / avg_s / 1e9
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
@@ -461,7 +602,7 @@ def main():
                            "timing": "HIP start/stop events stamped by the kernel's own dispatch packet "
                                      "(hipExtLaunchKernel) on every launch of the kernel, in one extra pass over "
                                      "the same batch (graph replay off for that pass)"}
-    out["path_roofline"] = path_roofline(r["work"], r["steps"], value, precision)
+    out["path_roofline"] = path_roofline(r["work"], r["steps"], value, precision, args.steps * len(w.primaries))
     if not args.no_roofline and args.calibrate_copy_mib == 0:
         # (counter runs leave it out: their only copies are the calibration's)
         copy_gbs = measured_copy_gbs()
@@ -492,6 +633,8 @@ def main():
         out["variants"] = var
     if args.layer_error:
         out["layer_error_vs_fp64_oracle"] = layer_error(w, r["edep"])
+    if not args.no_extras and not args.autotune and args.workload == "electron_showers_1gev_field":
+        extras(args, w, precision, value, out)
     if args.cpu_events > 0:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_events, w.n_events))
     print(json.dumps(out), flush=True)

@@ -267,6 +267,13 @@ ems_status ems_run(ems_ctx* ctx, uint64_t max_iterations, ems_counters* out);
  * tracks of each step iteration). */
 ems_status ems_read_counters(ems_ctx* ctx, ems_counters* out);
 
+/* The counters of the snapshot that the last synchronizing call (ems_step
+ * with counters, ems_run, ems_read_counters, ems_poll_completed) read, with
+ * no device work and no synchronization: a serving loop that has just polled
+ * reads its occupancy here instead of synchronizing a second time.
+ * Paper: "Integration with Perfetto" (as ems_read_counters). */
+ems_status ems_last_counters(ems_ctx* ctx, ems_counters* out);
+
 /* Events whose tracks have all finished since the last poll (serving): an
  * event completes when its last pushed primary and last secondary have
  * retired.  Writes up to `cap` event ids to `events` (completion order) and

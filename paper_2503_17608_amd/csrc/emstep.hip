@@ -1167,6 +1167,13 @@ ems_status ems_read_counters(ems_ctx* c, ems_counters* out)
     return EMS_OK;
 }
 
+ems_status ems_last_counters(ems_ctx* c, ems_counters* out)
+{
+    if (!c || !out) return fail(EMS_ERR_INVALID_ARG, "null");
+    to_counters(c->last, out);
+    return EMS_OK;
+}
+
 ems_status ems_poll_completed(ems_ctx* c, uint64_t* events, uint32_t cap, uint32_t* n)
 {
     if (!c || !n || (!events && cap)) return fail(EMS_ERR_INVALID_ARG, "null");

@@ -102,6 +102,7 @@ _sigs = {
     "ems_run": (C.c_int, [_P, C.c_uint64, C.POINTER(Counters)]),
     "ems_read_counters": (C.c_int, [_P, C.POINTER(Counters)]),
     "ems_poll_completed": (C.c_int, [_P, _P, C.c_uint32, C.POINTER(C.c_uint32)]),
+    "ems_last_counters": (C.c_int, [_P, C.POINTER(Counters)]),
     "ems_read_edep": (C.c_int, [_P, C.c_uint64, _P, C.c_uint32, _P]),
     "ems_read_all_tallies": (C.c_int, [_P, _P, _P, _P]),
     "ems_release_event": (C.c_int, [_P, C.c_uint64]),
@@ -242,6 +243,12 @@ class Session:
     def counters(self):
         c = Counters()
         _check(_lib.ems_read_counters(self._h, C.byref(c)), "ems_read_counters")
+        return c.as_dict()
+
+    def last_counters(self):
+        """Counters of the snapshot the last synchronizing call read (no device work)."""
+        c = Counters()
+        _check(_lib.ems_last_counters(self._h, C.byref(c)), "ems_last_counters")
         return c.as_dict()
 
     # -- results ----------------------------------------------------------------------

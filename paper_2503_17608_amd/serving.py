@@ -95,7 +95,7 @@ def serve(session, events, arrivals, track_budget, iterations_per_poll=8, keep_r
                 res.ledger[ev] = led
             session.release(ev)
             free_rows += 1
-        c = session.counters()
+        c = session.last_counters()          # the poll's snapshot: no second synchronization
         if c["overflow"]:
             # dropped secondaries: results of events in flight are incomplete
             raise RuntimeError("initializer buffer overflow while serving: increase n_initializers")

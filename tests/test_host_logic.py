@@ -61,6 +61,9 @@ class FakeSession:
         return {"alive": len(self.pending), "queued": 0, "pending_primaries": 0, "steps": self.steps,
                 "iterations": self.iterations, "overflow": self.overflow}
 
+    def last_counters(self):
+        return self.counters()
+
     def read_edep(self, ev):
         return np.full(3, float(ev)), {"event": ev}
 
