@@ -268,20 +268,17 @@ __device__ __forceinline__ const Initializer* taken(const Dev<R>& d, uint32_t i)
 template <class R>
 __device__ __forceinline__ void init_slot(const Dev<R>& d, uint32_t slot, const Initializer& rec)
 {
+    // the path length, search state, step limit and cross section of a
+    // step are read only when it resumes from a pause: a new track has none
     d.type[slot] = rec.type;
     d.action[slot] = A_IDLE;
     d.flags[slot] = 0;
-    d.nsearch[slot] = 0;
     d.slab[slot] = rec.slab;
     d.row[slot] = rec.row;
     d.step[slot] = 0;
     d.key[slot] = rec.key;
     d.T[slot] = (R)rec.T;
     d.nl[slot] = R(-1);
-    d.xs[slot] = R(0);
-    d.sphys[slot] = 0.0;
-    d.sdone[slot] = 0.0;
-    d.htry[slot] = 0.0;
     d.x[slot] = rec.r[0];
     d.y[slot] = rec.r[1];
     d.z[slot] = rec.r[2];
@@ -492,41 +489,36 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
     return 1u;
 }
 
-// Pre-step of one live, non-paused track (fields loaded by the caller):
-// interaction length, total cross section, physics step limit and the
-// along-step action, which it returns.  The along-step kernels call it for
-// their tracks before the step (there is no separate pre-step launch), as
-// does the drain.
+// Pre-step of one live, non-paused track, in registers (the caller loaded
+// its fields once and stores what persists once): draws the interaction
+// length when it is unset, and gives the total cross section, the physics
+// step limit and the step's flags (F_DREW, F_LOSS; a new step starts with no
+// other flag).  The along-step kernels and the drain run it for their tracks
+// before the step; there is no separate pre-step launch.
 template <class R>
-__device__ __forceinline__ uint8_t pre_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint8_t typ, R T, R nl,
-                                             uint16_t slab, uint32_t row, uint32_t step, uint64_t key)
+__device__ __forceinline__ void pre_step(const Dev<R>& d, const Tables<R>& tb, int mat, int typ, R T, R& nl,
+                                         uint64_t event, uint64_t key, uint32_t step, R& sig, double& s_phys,
+                                         uint8_t& nf)
 {
-    int mat = d.smat[slab];
-    uint8_t nf = 0;
+    nf = 0;
     if (nl < R(0)) {
-        StepRng<R> rng(d.seed, d.row_event[row], key, step, 0);
+        StepRng<R> rng(d.seed, event, key, step, 0);
         nl = -m_log(rng.next());
-        d.nl[s] = nl;
         nf |= F_DREW;
     }
     Loc<R> l = locate(tb, T);
-    R sig = total_xs(tb, mat, typ, T, l, R(d.ecut));
+    sig = total_xs(tb, mat, typ, T, l, R(d.ecut));
     R s_int = sig > R(0) ? nl / sig : R(INFINITY);
-    R s_phys = s_int;
+    R sp = s_int;
     if (typ != kGamma) {
         R Rg = interp(range_tab(tb, mat, typ), l);
         R s_loss = Rg <= R(kRFinal) ? Rg : m_max(R(kRFinal), R(kRhoRange) * Rg);
         if (s_loss < s_int) {
-            s_phys = s_loss;
+            sp = s_loss;
             nf |= F_LOSS;
         }
     }
-    uint8_t na = typ == kGamma ? A_NEUTRAL : (d.has_field ? A_FIELD : A_CHARGED);
-    d.xs[s] = sig;
-    d.sphys[s] = (double)s_phys;
-    d.flags[s] = nf;
-    d.action[s] = na;
-    return na;
+    s_phys = (double)sp;
 }
 
 // ---- pre-step: interaction length, physics step limit, along-step action -----------
@@ -616,8 +608,8 @@ __device__ __forceinline__ bool stop_defers(const Dev<R>& d, int typ, R& T, Step
 // next action; a positron that stops stays alive with A_ANNIH (annihilation
 // at rest, done by the interaction launch), so no along-step creates tracks.
 template <class R, bool CHARGED>
-__device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int typ, R& T, R sig, double step_len,
-                                             int face, uint8_t fl, int mat, uint16_t& slab, StepTally& tl,
+__device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& tb, int typ, R& T, R sig, double step_len,
+                                             int face, uint8_t& fl, int mat, uint16_t& slab, StepTally& tl,
                                              bool& alive, uint8_t& next_action, R& nl, uint32_t& step, uint64_t key,
                                              uint64_t event, uint32_t row)
 {
@@ -646,7 +638,6 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
                 alive = false;
                 next_action = A_NONE;
                 step = k + 1;
-                d.step[s] = step;
             }
             return;
         }
@@ -666,11 +657,9 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
             next_action = A_IDLE;
         }
         step = k + 1;
-        d.step[s] = step;
     } else if (fl & F_LOSS) {
         next_action = A_IDLE;
         step = k + 1;
-        d.step[s] = step;
     } else {
         StepRng<R> rng(d.seed, event, key, k, (fl & F_DREW) ? 1 : 0);
         R U1 = rng.next();
@@ -691,7 +680,6 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         } else {
             next_action = A_IDLE;
             step = k + 1;
-            d.step[s] = step;
         }
     }
     if (alive && step > kMaxSteps && next_action == A_IDLE) {
@@ -705,7 +693,7 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
             next_action = A_NONE;
         } else if (stop_defers(d, typ, T, tl)) {
             next_action = A_ANNIH;
-            d.flags[s] = (uint8_t)((fl & (uint8_t)~F_PAUSED) | F_COUNTED);
+            fl = (uint8_t)((fl & (uint8_t)~F_PAUSED) | F_COUNTED);
         } else {
             alive = false;
             next_action = A_NONE;
@@ -713,29 +701,31 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
     }
 }
 
-// Along-step of one straight-line track (photon, or charged without field):
-// the new state goes back to the slot and the step's deposit to its tally
-// row; `row` is the track's row, `next` the next action, `retired` the steps
-// of a track that finished (0 while it lives).
+// Along-step of one straight-line track (photon, or charged without field),
+// its pre-step first: the track's fields are loaded once, the step runs in
+// registers and what persists goes back to the slot once; the step's deposit
+// goes to its tally row.  `row` is the track's row, `next` the next action,
+// `retired` the steps of a track that finished (0 while it lives).
 template <class R, bool CHARGED>
 __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint32_t& row,
                                                      uint8_t& next, uint32_t& retired)
 {
-    int typ = d.type[s];
+    const int typ = d.type[s];
     row = d.row[s];
     uint16_t slab = d.slab[s];
     const uint16_t slab0 = slab;
     R T = d.T[s];
     R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
     double r[3] = {d.x[s], d.y[s], d.z[s]};
-    double s_phys = d.sphys[s];
-    uint8_t fl = d.flags[s];
-    R sig = d.xs[s];
     R nl = d.nl[s];
     uint32_t step = d.step[s];
     const uint64_t key = d.key[s];
     const uint64_t event = d.row_event[row];
-    int mat = d.smat[slab];
+    const int mat = d.smat[slab];
+    R sig;
+    double s_phys;
+    uint8_t fl;
+    pre_step(d, tb, mat, typ, T, nl, event, key, step, sig, s_phys, fl);
     double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
     int face;
     double s_geo = straight_distance(r, ud, d.zp[slab], d.zp[slab + 1], d.W, &face);
@@ -751,18 +741,19 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     uint8_t na = A_IDLE;
     const uint32_t k0 = step;
     const double T_pre = (double)T;
-    finish_along<R, CHARGED>(d, tb, s, typ, T, sig, st, face, fl, mat, slab, tl, alive, na, nl, step, key, event,
-                             row);
+    finish_along<R, CHARGED>(d, tb, typ, T, sig, st, face, fl, mat, slab, tl, alive, na, nl, step, key, event, row);
     record_tally(d, row, slab0, tl);
-    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-    if (CHARGED && d.msc && alive && na != A_ANNIH) {
-        msc_deflect(d.seed, event, key, k0, T_pre, st, d.x0[mat], ud);
-        d.ux[s] = (R)ud[0]; d.uy[s] = (R)ud[1]; d.uz[s] = (R)ud[2];
-    }
     if (alive) {
+        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+        if (CHARGED && d.msc && na != A_ANNIH) {
+            msc_deflect(d.seed, event, key, k0, T_pre, st, d.x0[mat], ud);
+            d.ux[s] = (R)ud[0]; d.uy[s] = (R)ud[1]; d.uz[s] = (R)ud[2];
+        }
         d.T[s] = T;
         d.nl[s] = nl;
-        d.slab[s] = slab;
+        if (slab != slab0) d.slab[s] = slab;
+        if (step != k0) d.step[s] = step;
+        d.flags[s] = fl;
         d.action[s] = na;
         next = na;
     } else {
@@ -785,7 +776,6 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     uint8_t next = A_NONE;
     uint32_t retired = 0;
     if (act) {
-        pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
         ++pre_acc;
         along_straight_track<R, CHARGED>(d, tb, s, row, next, retired);
     }
@@ -854,35 +844,47 @@ __device__ __forceinline__ void normalize_d(double v[3])
     v[0] /= n; v[1] /= n; v[2] /= n;
 }
 
-// Along-step of one charged track in the uniform field, with at most
-// `max_sub` RK4 evaluations (0: no cap) before the step pauses.  Outputs as
-// for the straight-line step, plus the RK4 evaluations made (`att`) and
-// whether the step paused (`paused_n`).
+// Along-step of one charged track in the uniform field, its pre-step first
+// unless the step resumes from a pause, with at most `max_sub` RK4
+// evaluations (0: no cap) before the step pauses.  The track's fields are
+// loaded once; the path length, search state, step limit and cross section
+// of a step live in registers and go to the slot only when the step pauses.
+// Outputs as for the straight-line step, plus the RK4 evaluations made
+// (`att`), whether the step paused (`paused_n`) and whether the pre-step ran
+// (`pre_n`).
 template <class R>
 __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int max_sub,
                                                   uint32_t& row, uint8_t& next, uint32_t& retired, uint32_t& att,
-                                                  uint32_t& paused_n)
+                                                  uint32_t& paused_n, uint32_t& pre_n)
 {
-    int typ = d.type[s];
+    const int typ = d.type[s];
     row = d.row[s];
     uint16_t slab = d.slab[s];
     const uint16_t slab0 = slab;
-    int mat = d.smat[slab];
+    const int mat = d.smat[slab];
     R T = d.T[s];
     double u[3] = {(double)d.ux[s], (double)d.uy[s], (double)d.uz[s]};
     double r[3] = {d.x[s], d.y[s], d.z[s]};
-    double s_phys = d.sphys[s];
-    double s_done = d.sdone[s];
-    double h_try = d.htry[s];
-    int n_search = d.nsearch[s];
     uint8_t fl = d.flags[s];
-    // fields used only at the end of the step, loaded with the rest so that
-    // no memory round trip is left for after the integration
-    const R sig = d.xs[s];
     R nl = d.nl[s];
     uint32_t step = d.step[s];
     const uint64_t key = d.key[s];
     const uint64_t event = d.row_event[row];
+    const bool resumed = (fl & F_PAUSED) != 0;
+    double s_phys, s_done = 0.0, h_try = 0.0;
+    int n_search = 0;
+    R sig;
+    if (resumed) {
+        s_phys = d.sphys[s];
+        s_done = d.sdone[s];
+        h_try = d.htry[s];
+        n_search = d.nsearch[s];
+        sig = d.xs[s];
+        pre_n = 0;
+    } else {
+        pre_step(d, tb, mat, typ, T, nl, event, key, step, sig, s_phys, fl);
+        pre_n = 1;
+    }
     double Td = (double)T;
     double q = typ == kPositron ? 1.0 : -1.0;
     double p = sqrt(Td * (Td + 2.0 * kMe));
@@ -957,40 +959,45 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
         h_try = f > 0.0 ? f * h : 0.5 * h;
         n_search += 1;
     }
-    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-    d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
     paused_n = paused ? 1u : 0u;
     if (paused) {
+        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+        d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
         d.sdone[s] = s_done;
         d.htry[s] = h_try;
         d.nsearch[s] = (uint8_t)n_search;
         d.flags[s] = fl | F_PAUSED;
-    } else {
-        d.sdone[s] = 0.0;
-        d.htry[s] = 0.0;
-        d.nsearch[s] = 0;
-        d.flags[s] = fl & (uint8_t)~F_PAUSED;
-        StepTally tl = {0.0, 0, 0, 0};
-        bool alive = true;
-        uint8_t na = A_IDLE;
-        const uint32_t k0 = step;
-        finish_along<R, true>(d, tb, s, typ, T, sig, s_done, face, fl, mat, slab, tl, alive, na, nl, step, key, event,
-                              row);
-        record_tally(d, row, slab0, tl);
-        if (d.msc && alive && na != A_ANNIH) {
-            msc_deflect(d.seed, event, key, k0, Td, s_done, d.x0[mat], u);
-            d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
-        }
-        if (alive) {
-            d.T[s] = T;
+        if (!resumed) {
+            // the step limit, cross section and interaction length of the
+            // step persist until it resumes
+            d.sphys[s] = s_phys;
+            d.xs[s] = sig;
             d.nl[s] = nl;
-            d.slab[s] = slab;
-            d.action[s] = na;
-            next = na;
-        } else {
-            retired = step;
-            retire(d, s, row, retired);
+            d.action[s] = A_FIELD;
         }
+        return;
+    }
+    fl = fl & (uint8_t)~F_PAUSED;
+    StepTally tl = {0.0, 0, 0, 0};
+    bool alive = true;
+    uint8_t na = A_IDLE;
+    const uint32_t k0 = step;
+    finish_along<R, true>(d, tb, typ, T, sig, s_done, face, fl, mat, slab, tl, alive, na, nl, step, key, event, row);
+    record_tally(d, row, slab0, tl);
+    if (alive) {
+        if (d.msc && na != A_ANNIH) msc_deflect(d.seed, event, key, k0, Td, s_done, d.x0[mat], u);
+        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+        d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
+        d.T[s] = T;
+        d.nl[s] = nl;
+        if (slab != slab0) d.slab[s] = slab;
+        if (step != k0) d.step[s] = step;
+        d.flags[s] = fl;
+        d.action[s] = na;
+        next = na;
+    } else {
+        retired = step;
+        retire(d, s, row, retired);
     }
 }
 
@@ -1010,12 +1017,9 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
     uint32_t row = 0;
     uint8_t next = A_NONE;
-    uint32_t retired = 0, att = 0, paused_n = 0;
-    if (act && !(d.flags[s] & F_PAUSED)) {      // a paused step resumes with its step limit
-        pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
-        ++pre_acc;
-    }
-    if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n);
+    uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
+    if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n, pre_n);
+    pre_acc += pre_n;
     leave_event(d, retired != 0, row);
     ret_acc += retired;
     sub_acc += att;
@@ -1326,12 +1330,9 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
         const bool live = owns && d.type[s] != kDead;
         if (!__syncthreads_or(live)) break;
         if (live) {
-            uint8_t a;
-            if (d.flags[s] & F_PAUSED) {
-                a = A_FIELD;
-            } else {
-                a = pre_track(d, tb, s, d.type[s], d.T[s], d.nl[s], d.slab[s], d.row[s], d.step[s], d.key[s]);
-            }
+            // the along-step functions run the pre-step (a paused step is a
+            // field step and resumes without one)
+            const uint8_t a = along_action(d, s);
             uint32_t row = 0, retired = 0;
             uint8_t next = A_NONE;
             if (a == A_NEUTRAL) {
@@ -1340,8 +1341,8 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
                 along_straight_track<R, true>(d, tb, s, row, next, retired);
             } else {
                 // a paused step resumes in the next round (pausing does not change the result)
-                uint32_t att = 0, paused_n = 0;
-                along_field_track<R>(d, tb, s, kDrainSubsteps, row, next, retired, att, paused_n);
+                uint32_t att = 0, paused_n = 0, pre_n = 0;
+                along_field_track<R>(d, tb, s, kDrainSubsteps, row, next, retired, att, paused_n, pre_n);
             }
             if (next >= A_PROC0 && next < A_NUM) {
                 SecBuf<R> sb;
