@@ -36,7 +36,9 @@ serving run's per-layer error against the FP64 oracle on a subsample).
 Other modes: --autotune (tune policy / tail threshold / block sizes /
 fusion / drain on the workload first), --layer-error (per-layer deposit of
 this run against the FP64 oracle on the same events), --serve (the serving
-section alone).
+section alone), --fig2 (along-step time per live track against live tracks,
+and what the drain of the last tracks recovers), --sweep (throughput against
+total track slots, mixed-event and event-parallel modes).
 """
 from __future__ import annotations
 
@@ -177,6 +179,13 @@ def parse():
                     help="per-layer error of the mixed-precision serving run on every n-th event (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="the main workload only: no unsorted rate, precision pair or serving section")
+    ap.add_argument("--fig2", action="store_true",
+                    help="occupancy analysis: along-step time per live track against live tracks, and what the "
+                         "drain recovers")
+    ap.add_argument("--trace-out", default="", help="with --fig2: write the Chrome trace of the recorded run here")
+    ap.add_argument("--sweep", action="store_true",
+                    help="throughput against total track slots (2^14..2^23), mixed-event and event-parallel")
+    ap.add_argument("--sweep-exp", type=int, nargs=2, default=[14, 23], help="slot exponents of the sweep")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size three times (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -523,6 +532,68 @@ def extras(args, w, precision, value, out):
     out["extras_wall_s"] = time.perf_counter() - t0
 
 
+def fig2_mode(args):
+    """Along-step GPU time per live track against the number of live tracks
+    (one iteration at a time, per-kernel HIP events, no drain), the tail
+    onset, and the whole batch timed with and without the drain of the last
+    tracks (graphs on, device-resident timing)."""
+    from paper_2503_17608_amd import trace
+    w = make_workload(args.workload, args.events, args.slots)
+    precision = args.precision or w.precision
+    s = new_session(w, args, precision, args.policy, args.init_partition, graph=0, drain=0)
+    recs = trace.record(s, w.primaries)
+    s.close()
+    if args.trace_out:
+        trace.write(recs, args.trace_out, name=f"{w.name} {args.policy}")
+    an = trace.tail_analysis(recs)
+    thr = args.drain_threshold if args.drain_threshold > 0 else 65536
+    tail = [r for r in recs if r["alive"] + r["queued"] + r["pending"] < thr]
+    tail_ms = sum(sum(r["kernel_ms"].values()) for r in tail)
+    rd = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=thr)
+    rn = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=0)
+    out = {"metric": "along-step time per live track against live tracks", "n_gpus": 1,
+           "config": {"workload": w.name, "events": w.n_events, "n_slots": w.n_slots, "precision": precision,
+                      "sort_policy": args.policy, "init_partition": args.init_partition},
+           "iterations": len(recs), "track_steps": sum(r["steps"] for r in recs),
+           "tail_analysis": an,
+           "below_drain_threshold": {"threshold": thr, "iterations": len(tail), "kernel_ms": tail_ms,
+                                     "share_of_kernel_time": tail_ms / an["kernel_ms"]},
+           "batch_with_drain": {"value": rd["steps"] / rd["seconds"], "ms_per_batch": 1e3 * rd["seconds"] / args.steps,
+                                "iterations_per_batch": rd["iterations"] // args.steps},
+           "batch_without_drain": {"value": rn["steps"] / rn["seconds"],
+                                   "ms_per_batch": 1e3 * rn["seconds"] / args.steps,
+                                   "iterations_per_batch": rn["iterations"] // args.steps}}
+    print(json.dumps(out), flush=True)
+
+
+def sweep_mode(args):
+    """Throughput against the total number of track slots: the mixed-event
+    mode (every event in one slot array on one stream) and the event-parallel
+    mode (k sessions of slots / k, each on its own stream and host thread,
+    events from a shared queue), k = 2, 4, 8."""
+    w = make_workload(args.workload, args.events, args.slots)
+    precision = args.precision or w.precision
+    rows = []
+    lo, hi = args.sweep_exp
+    for e in range(lo, hi + 1):
+        n = 1 << e
+        w.n_slots = n
+        t0 = time.perf_counter()
+        r = run_variant(w, args, precision, args.policy, args.init_partition, None)
+        row = {"slots": n, "mixed": r["steps"] / r["seconds"],
+               "mixed_iterations_per_batch": r["iterations"] // args.steps}
+        for k in (2, 4, 8):
+            if n // k >= 1024:
+                row[f"event_parallel_{k}"] = event_parallel_rate(w, args, precision, k, repeats=1)
+        row["wall_s"] = time.perf_counter() - t0
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    out = {"metric": "track-steps/s against total track slots", "unit": "track-steps/s", "n_gpus": 1,
+           "config": {"workload": w.name, "events": w.n_events, "precision": precision, "sort_policy": args.policy},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -540,6 +611,12 @@ def main():
         del src, dst
     if args.serve:
         serve_mode(args)
+        return
+    if args.fig2:
+        fig2_mode(args)
+        return
+    if args.sweep:
+        sweep_mode(args)
         return
     w = make_workload(args.workload, args.events, args.slots)
     precision = args.precision or w.precision

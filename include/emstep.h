@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 5u
+#define EMS_ABI_VERSION 6u
 
 typedef enum {
     EMS_OK = 0,
@@ -366,6 +366,13 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * bremsstrahlung, drain, interactions, annihilation); 0 keeps
  * ems_options.block_size.  Below tail_threshold live tracks an iteration
  * skips the reordering and runs masked (the device decides per iteration).
+ * phase_sort[p] chooses the reordering per sort point p (0: before the
+ * along-step kernels, 1: before the interaction kernels) and occupancy
+ * bucket: an iteration with n live tracks (n >= tail_threshold) reorders at
+ * sort point p when bit floor(log2 n) of phase_sort[p] is set, and runs that
+ * point's kernels masked otherwise (all bits set: reorder at every
+ * occupancy).  The sort policy itself (partition, radix, queue) is one per
+ * context.
  *
  * Drain (ems_run only; 0 = off): once the latest counter snapshot shows fewer
  * than drain_threshold tracks alive, queued or pending, each further
@@ -389,7 +396,8 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * "interactions" in the block table.
 
  * Setting the tuning re-captures graphs on the next run.
- * Paper: "Reindexing track slots" (sort policy, tail threshold); "Partitioning
+ * Paper: "Reindexing track slots" (sort policy, tail threshold, phase
+ * table); "Partitioning
  * track data" (parent-slot reuse); "Reducing load imbalance" (the drain of the
  * last tracks); "Performance results" (launch shapes). */
 typedef struct {
@@ -400,6 +408,7 @@ typedef struct {
     uint32_t drain_steps;
     uint32_t reuse_parent_slot;
     uint32_t fuse_interactions;
+    uint32_t phase_sort[2];
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

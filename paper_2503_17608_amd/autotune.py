@@ -11,8 +11,16 @@ occupancy masked stepping and no drain look best):
    role then keeps the size that minimised its own total time;
 2. sort policy: none / partition / radix / queue, timed end to end;
 3. tail threshold: the live-track count below which an iteration skips the
-   reordering and runs masked (the "per step phase" choice), timed end to end;
-4. fused or per-process interaction kernels, and the drain threshold below
+   reordering and runs masked, timed end to end;
+4. the phase table: for each sort point (before the along-step kernels,
+   before the interaction kernels) and each occupancy bucket floor(log2 live
+   tracks), reorder or run masked.  The sample is stepped one iteration at a
+   time with per-kernel HIP-event timing in the four combinations (both sort
+   points reordering, either one, neither); the live-track count of every
+   iteration is the same in all four (each track takes one step per
+   iteration whatever the launch shape), so each bucket keeps the
+   combination whose iterations in that bucket took the least GPU time;
+5. fused or per-process interaction kernels, and the drain threshold below
    which the last tracks are drained in block-local loops, timed end to end.
 
 Results can be cached in a JSON file keyed by a workload signature.
@@ -54,9 +62,69 @@ def _run(session, primaries, events):
     return dt
 
 
+ALL_BUCKETS = 0xFFFFFFFF
+
+
+def iteration_times(session, primaries, events, max_iterations=200_000):
+    """Step `primaries` one iteration at a time with per-kernel HIP-event
+    timing: (live tracks, summed kernel ms) of every iteration."""
+    session.push(primaries)
+    session.profile(emstep.role_mask(*emstep.KERNEL_ROLES))
+    session.profile_read()
+    out = []
+    try:
+        for _ in range(max_iterations):
+            c = session.step(1)
+            prof = session.profile_read()
+            out.append((int(c["alive"]), sum(v[0] for v in prof.values() if v[1] > 0)))
+            if c["alive"] == 0 and c["queued"] == 0 and c["pending_primaries"] == 0:
+                break
+    finally:
+        session.profile(0)
+    session.release(events)
+    return out
+
+
+def phase_table(session, sample, events):
+    """Per sort point and occupancy bucket: reorder or run masked (step 4 of
+    the module docstring).  Returns the two bucket masks and the per-bucket
+    times of the four combinations."""
+    combos = {(1, 1): (ALL_BUCKETS, ALL_BUCKETS), (0, 1): (0, ALL_BUCKETS), (1, 0): (ALL_BUCKETS, 0), (0, 0): (0, 0)}
+    per = {}
+    alive_ref = None
+    for combo, masks in combos.items():
+        session.set_tuning(phase_sort=masks)
+        rec = iteration_times(session, sample, events)
+        alive = [a for a, _ in rec]
+        if alive_ref is None:
+            alive_ref = alive
+        elif alive != alive_ref:
+            raise RuntimeError("live tracks per iteration differ between launch shapes")
+        t = {}
+        for a, ms in rec:
+            if a > 0:
+                b = a.bit_length() - 1
+                t[b] = t.get(b, 0.0) + ms
+        per[combo] = t
+    m1 = m2 = 0
+    buckets = sorted(set().union(*[set(t) for t in per.values()]))
+    choice = {}
+    for b in buckets:
+        best = min(combos, key=lambda k: per[k].get(b, float("inf")))
+        choice[b] = best
+        m1 |= best[0] << b
+        m2 |= best[1] << b
+    # buckets the sample never reached keep reordering
+    seen = sum(1 << b for b in buckets)
+    m1 |= ALL_BUCKETS & ~seen
+    m2 |= ALL_BUCKETS & ~seen
+    return (m1, m2), {"choice": {str(b): list(c) for b, c in choice.items()},
+                      "ms": {f"{k[0]}{k[1]}": {str(b): v for b, v in t.items()} for k, t in per.items()}}
+
+
 def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
              thresholds=(0, 2048, 16384, 131072), blocks=BLOCK_CANDIDATES, repeats=1, cache=None, key=None,
-             log=None, drains=(0, 16384, 65536)):
+             log=None, drains=(0, 16384, 65536), phases=True):
     """Tune `session` (an emstep.Session with geometry and tables loaded) on
     the primaries `sample`; applies and returns the chosen tuning."""
     if cache and key and os.path.exists(cache):
@@ -65,7 +133,8 @@ def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
             t = db[key]
             session.set_tuning(sort_policy=t["sort_policy"], tail_threshold=t["tail_threshold"], block=t["block"],
                                fuse_interactions=t.get("fuse_interactions", False),
-                               drain_threshold=t.get("drain_threshold", 0))
+                               drain_threshold=t.get("drain_threshold", 0),
+                               phase_sort=t.get("phase_sort", (ALL_BUCKETS, ALL_BUCKETS)))
             return t
     events = np.unique(sample["event"])
     say = log or (lambda *a: None)
@@ -106,7 +175,15 @@ def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
         best_th = 0
     say("thresholds", th_t)
     session.set_tuning(sort_policy=best_policy, tail_threshold=best_th, block=best_block)
-    # 4. interaction kernels fused or not, then the drain threshold
+    # 4. phase table (per sort point and occupancy bucket), drain off so that
+    # every iteration of the sample is a step-loop iteration
+    phase_masks, phase_info = (ALL_BUCKETS, ALL_BUCKETS), {}
+    if phases and best_policy != "none":
+        session.set_tuning(drain_threshold=0)
+        phase_masks, phase_info = phase_table(session, sample, events)
+        say("phase table", phase_info.get("choice"))
+    session.set_tuning(phase_sort=phase_masks)
+    # 5. interaction kernels fused or not, then the drain threshold
     fuse_t = {}
     for f in (False, True):
         session.set_tuning(fuse_interactions=f, drain_threshold=0)
@@ -119,9 +196,10 @@ def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
     best_drain = min(drain_t, key=drain_t.get)
     say("fuse", fuse_t, "drain", drain_t)
     session.set_tuning(sort_policy=best_policy, tail_threshold=best_th, block=best_block,
-                       fuse_interactions=best_fuse, drain_threshold=best_drain)
+                       fuse_interactions=best_fuse, drain_threshold=best_drain, phase_sort=phase_masks)
     result = {"sort_policy": best_policy, "tail_threshold": int(best_th), "block": best_block,
               "fuse_interactions": bool(best_fuse), "drain_threshold": int(best_drain),
+              "phase_sort": [int(phase_masks[0]), int(phase_masks[1])], "phase_table": phase_info,
               "policy_seconds": pol_t, "threshold_seconds": {str(k): v for k, v in th_t.items()},
               "fuse_seconds": {str(k): v for k, v in fuse_t.items()},
               "drain_seconds": {str(k): v for k, v in drain_t.items()},

@@ -109,7 +109,7 @@ struct Counters {
     unsigned int list_cnt[16];         // queue policy: entries of each interaction list
     unsigned int alive_before;         // live tracks found by the vacancy pass (before the fill)
     unsigned int done_count;           // events completed so far (entries written to the ring)
-    unsigned int phase_sorted;         // this iteration reorders tracks (occupancy above the tail threshold)
+    unsigned int phase_sorted;         // reordering this iteration: bit 0 sort point 1, bit 1 sort point 2
 };
 
 // work counter indices

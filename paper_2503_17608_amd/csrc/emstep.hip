@@ -195,6 +195,7 @@ struct ems_ctx {
     // tuning (switchable at run time)
     int policy = 0;
     uint32_t tail_threshold = 0;
+    uint32_t phase_sort[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
     uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
@@ -274,6 +275,8 @@ Dev<R> make_dev(const ems_ctx* c)
     d.sorted = c->policy == EMS_SORT_NONE ? 0 : 1;
     d.sorted2 = c->policy == EMS_SORT_NONE ? 0 : (c->policy == EMS_SORT_QUEUE ? 2 : 1);
     d.tail_threshold = c->tail_threshold;
+    d.phase_sort1 = c->phase_sort[0];
+    d.phase_sort2 = c->phase_sort[1];
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.msc = c->opt.msc ? 1 : 0;
@@ -434,7 +437,7 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, int km)
         ln.k(R_SORT, true, false, k_sort_hist<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
              (const uint8_t*)nullptr, n, cnt, nt);
         ln.k(R_SORT, false, false, k_sort_scan<16>, dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)d.ctr,
-             tot);
+             tot, km >= 2 ? 1u : 2u);
         ln.k(R_SORT, false, true, k_sort_scatter<R, 16>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
     } else {
@@ -442,7 +445,7 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, int km)
         ln.k(R_SORT, true, false, k_sort_hist<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km1,
              (const uint8_t*)nullptr, n, cnt, nt);
         ln.k(R_SORT, false, false, k_sort_scan<128>, dim3(128), dim3(256), 0, c->stream, cnt, nt,
-             (const Counters*)d.ctr, tot);
+             (const Counters*)d.ctr, tot, km1 >= 2 ? 1u : 2u);
         ln.k(R_SORT, false, true, k_sort_scatter<R, 128>, dim3(nt), dim3(kSortThreads), 0, c->stream, d, km1,
              (const uint8_t*)nullptr, n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, d.perm);
     }
@@ -1387,14 +1390,15 @@ ems_status ems_debug_sort(ems_ctx* c, const uint8_t* keys, uint64_t n, int32_t p
     if (nb == 16) {
         hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk, (uint32_t)n,
                            cnt, nt);
-        hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr, tot);
+        hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr, tot,
+                           0u);
         hipLaunchKernelGGL((k_sort_scatter<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, dk,
                            (uint32_t)n, cnt, nt, (const uint32_t*)tot, dp);
     } else {
         hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk,
                            (uint32_t)n, cnt, nt);
         hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
-                           tot);
+                           tot, 0u);
         hipLaunchKernelGGL((k_sort_scatter<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, dk,
                            (uint32_t)n, cnt, nt, (const uint32_t*)tot, dp);
     }
@@ -1429,14 +1433,14 @@ ems_status ems_sort_keys_noalloc(ems_ctx* c, const uint8_t* keys, uint64_t n, in
         hipLaunchKernelGGL((k_sort_hist<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, keys,
                            (uint32_t)n, cnt, nt);
         hipLaunchKernelGGL((k_sort_scan<16>), dim3(16), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
-                           tot);
+                           tot, 0u);
         hipLaunchKernelGGL((k_sort_scatter<double, 16>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 0, keys,
                            (uint32_t)n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, perm);
     } else {
         hipLaunchKernelGGL((k_sort_hist<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, keys,
                            (uint32_t)n, cnt, nt);
         hipLaunchKernelGGL((k_sort_scan<128>), dim3(128), dim3(256), 0, c->stream, cnt, nt, (const Counters*)nullptr,
-                           tot);
+                           tot, 0u);
         hipLaunchKernelGGL((k_sort_scatter<double, 128>), dim3(nt), dim3(kSortThreads), 0, c->stream, d, 1, keys,
                            (uint32_t)n, (const uint32_t*)cnt, nt, (const uint32_t*)tot, perm);
     }
@@ -1456,6 +1460,8 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
     if (t->drain_threshold > 0 && t->drain_steps == 0) return fail(EMS_ERR_INVALID_ARG, "drain_steps must be > 0");
     c->policy = t->sort_policy;
     c->tail_threshold = t->tail_threshold;
+    c->phase_sort[0] = t->phase_sort[0];
+    c->phase_sort[1] = t->phase_sort[1];
     c->drain_threshold = t->drain_threshold;
     c->drain_steps = t->drain_steps;
     c->reuse_parent = t->reuse_parent_slot ? 1u : 0u;
@@ -1473,6 +1479,8 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     t->drain_steps = c->drain_steps;
     t->reuse_parent_slot = c->reuse_parent;
     t->fuse_interactions = c->fuse_interactions;
+    t->phase_sort[0] = c->phase_sort[0];
+    t->phase_sort[1] = c->phase_sort[1];
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];
     return EMS_OK;
 }

@@ -72,6 +72,10 @@ struct Dev {
     int sorted;             // along-step kernels: 0 masked over all slots, 1 sorted permutation ranges
     int sorted2;            // interaction kernels: 0 masked, 1 sorted ranges, 2 lists filled by the along-step
     unsigned int tail_threshold;  // below this many live tracks an iteration runs masked (no reordering)
+    // per occupancy bucket b = floor(log2 live tracks): bit b set when sort
+    // point 1 (before the along-steps) / 2 (before the interactions)
+    // reorders in an iteration of that bucket, else its kernels run masked
+    unsigned int phase_sort1, phase_sort2;
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
@@ -252,7 +256,15 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
         c->n_alive += (uint32_t)(tq + tp);
         c->list_cnt[0] = c->n_alive;
         for (int a = 1; a < 16; ++a) c->list_cnt[a] = 0;     // lists are refilled every iteration
-        c->phase_sorted = (d.sorted || d.sorted2) && c->n_alive >= d.tail_threshold ? 1u : 0u;
+        // this iteration's reordering: by sort point, from the occupancy
+        // bucket's entry of the phase table and the tail threshold
+        unsigned int ph = 0;
+        if (c->n_alive > 0 && c->n_alive >= d.tail_threshold) {
+            const int b = 31 - __clz((int)c->n_alive);
+            if (d.sorted && ((d.phase_sort1 >> b) & 1u)) ph |= 1u;
+            if (d.sorted2 && ((d.phase_sort2 >> b) & 1u)) ph |= 2u;
+        }
+        c->phase_sorted = ph;
     }
 }
 
@@ -356,7 +368,8 @@ __device__ __forceinline__ uint8_t along_action(const Dev<R>& d, uint32_t s)
 // end of each trip.
 #define EMS_TRACK_RANGE(d, a)                                                              \
     unsigned long long _work = 0;                                                           \
-    const int _mode = (d).ctr->phase_sorted ? ((a) >= A_PROC0 ? (d).sorted2 : (d).sorted) : 0; \
+    const int _mode = (a) >= A_PROC0 ? (((d).ctr->phase_sorted & 2u) ? (d).sorted2 : 0)           \
+                                     : (((d).ctr->phase_sorted & 1u) ? (d).sorted : 0);            \
     const uint32_t _n = _mode == 2 ? (d).ctr->list_cnt[a]                                    \
                         : (_mode ? (d).ctr->range_cnt[a] : (d).n_slots);                     \
     const uint32_t _off = _mode == 1 ? (d).ctr->range_off[a] : 0u;                          \
@@ -492,19 +505,26 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
 // Pre-step of one live, non-paused track, in registers (the caller loaded
 // its fields once and stores what persists once): draws the interaction
 // length when it is unset, and gives the total cross section, the physics
-// step limit and the step's flags (F_DREW, F_LOSS; a new step starts with no
-// other flag).  The along-step kernels and the drain run it for their tracks
+// step limit, the step's flags (F_DREW, F_LOSS; a new step starts with no
+// other flag) and the random word of the step's process selection.  The along-step kernels and the drain run it for their tracks
 // before the step; there is no separate pre-step launch.
 template <class R>
 __device__ __forceinline__ void pre_step(const Dev<R>& d, const Tables<R>& tb, int mat, int typ, R T, R& nl,
                                          uint64_t event, uint64_t key, uint32_t step, R& sig, double& s_phys,
-                                         uint8_t& nf)
+                                         uint8_t& nf, uint64_t& w_sel)
 {
+    // Block 0 of the step's uniforms, computed once: word 0 is the
+    // interaction-length uniform when one is drawn, and the next unused word
+    // is the process-selection uniform of the step's end (`w_sel`).  A wave
+    // evaluates the block for all its lanes whenever any of them draws, so
+    // keeping the word spares the end of the step a second evaluation.
+    const U64x4 b0 = philox4x64_10(key, (uint64_t)step, 0, 0, d.seed, event);
     nf = 0;
+    w_sel = b0.w[0];
     if (nl < R(0)) {
-        StepRng<R> rng(d.seed, event, key, step, 0);
-        nl = -m_log(rng.next());
+        nl = -m_log(unit_from<R>(b0.w[0]));
         nf |= F_DREW;
+        w_sel = b0.w[1];
     }
     Loc<R> l = locate(tb, T);
     sig = total_xs(tb, mat, typ, T, l, R(d.ecut));
@@ -611,7 +631,7 @@ template <class R, bool CHARGED>
 __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& tb, int typ, R& T, R sig, double step_len,
                                              int face, uint8_t& fl, int mat, uint16_t& slab, StepTally& tl,
                                              bool& alive, uint8_t& next_action, R& nl, uint32_t& step, uint64_t key,
-                                             uint64_t event, uint32_t row)
+                                             uint64_t event, uint32_t row, bool have_sel, uint64_t w_sel)
 {
     // step, key and row come in registers (loaded with the rest of the
     // track up front); step leaves as the track's step count after this step
@@ -661,8 +681,15 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         next_action = A_IDLE;
         step = k + 1;
     } else {
-        StepRng<R> rng(d.seed, event, key, k, (fl & F_DREW) ? 1 : 0);
-        R U1 = rng.next();
+        // the process-selection uniform: kept from the pre-step's block, or
+        // (a step resumed after a pause, which ran no pre-step) drawn here
+        R U1;
+        if (have_sel) {
+            U1 = unit_from<R>(w_sel);
+        } else {
+            StepRng<R> rng(d.seed, event, key, k, (fl & F_DREW) ? 1 : 0);
+            U1 = rng.next();
+        }
         R sig1;
         Loc<R> l1;
         l1 = locate(tb, T);
@@ -725,7 +752,8 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     R sig;
     double s_phys;
     uint8_t fl;
-    pre_step(d, tb, mat, typ, T, nl, event, key, step, sig, s_phys, fl);
+    uint64_t w_sel;
+    pre_step(d, tb, mat, typ, T, nl, event, key, step, sig, s_phys, fl, w_sel);
     double ud[3] = {(double)u[0], (double)u[1], (double)u[2]};
     int face;
     double s_geo = straight_distance(r, ud, d.zp[slab], d.zp[slab + 1], d.W, &face);
@@ -741,7 +769,8 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     uint8_t na = A_IDLE;
     const uint32_t k0 = step;
     const double T_pre = (double)T;
-    finish_along<R, CHARGED>(d, tb, typ, T, sig, st, face, fl, mat, slab, tl, alive, na, nl, step, key, event, row);
+    finish_along<R, CHARGED>(d, tb, typ, T, sig, st, face, fl, mat, slab, tl, alive, na, nl, step, key, event, row,
+                             true, w_sel);
     record_tally(d, row, slab0, tl);
     if (alive) {
         d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
@@ -781,7 +810,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_straight(Dev<R> d)
     }
     leave_event(d, retired != 0, row);
     ret_acc += retired;
-    if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+    if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u)) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
     flush_count(d, CHARGED ? W_CHARGED : W_NEUTRAL, _work);
     flush_count(d, kStepsSlot + (CHARGED ? W_CHARGED : W_NEUTRAL), ret_acc);
@@ -874,6 +903,7 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
     double s_phys, s_done = 0.0, h_try = 0.0;
     int n_search = 0;
     R sig;
+    uint64_t w_sel = 0;
     if (resumed) {
         s_phys = d.sphys[s];
         s_done = d.sdone[s];
@@ -882,7 +912,7 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
         sig = d.xs[s];
         pre_n = 0;
     } else {
-        pre_step(d, tb, mat, typ, T, nl, event, key, step, sig, s_phys, fl);
+        pre_step(d, tb, mat, typ, T, nl, event, key, step, sig, s_phys, fl, w_sel);
         pre_n = 1;
     }
     double Td = (double)T;
@@ -982,7 +1012,8 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
     bool alive = true;
     uint8_t na = A_IDLE;
     const uint32_t k0 = step;
-    finish_along<R, true>(d, tb, typ, T, sig, s_done, face, fl, mat, slab, tl, alive, na, nl, step, key, event, row);
+    finish_along<R, true>(d, tb, typ, T, sig, s_done, face, fl, mat, slab, tl, alive, na, nl, step, key, event, row,
+                          !resumed, w_sel);
     record_tally(d, row, slab0, tl);
     if (alive) {
         if (d.msc && na != A_ANNIH) msc_deflect(d.seed, event, key, k0, Td, s_done, d.x0[mat], u);
@@ -1024,7 +1055,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     ret_acc += retired;
     sub_acc += att;
     pause_acc += paused_n;
-    if (d.sorted2 == 2 && d.ctr->phase_sorted) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+    if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u)) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
     EMS_END_TRACKS
     flush_count(d, W_FIELD, _work);
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
@@ -1122,7 +1153,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
 template <class R>
 __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
 {
-    const int mode = d.ctr->phase_sorted ? d.sorted2 : 0;
+    const int mode = (d.ctr->phase_sorted & 2u) ? d.sorted2 : 0;
     uint32_t n = d.n_slots, off = 0;
     uint32_t lc0 = 0, lc1 = 0, lc2 = 0, lc3 = 0, lc4 = 0, lc5 = 0;
     if (mode == 1) {
@@ -1410,7 +1441,7 @@ template <class R, int NB>
 __global__ void __launch_bounds__(kSortThreads) k_sort_hist(Dev<R> d, int keymode, const uint8_t* ext_keys, uint32_t n,
                                                             uint32_t* cnt, uint32_t n_tiles)
 {
-    if (!ext_keys && !d.ctr->phase_sorted) return;
+    if (!ext_keys && !(d.ctr->phase_sorted & (keymode >= 2 ? 1u : 2u))) return;
     __shared__ uint32_t h[NB];
     for (int b = threadIdx.x; b < NB; b += kSortThreads) h[b] = 0;
     __syncthreads();
@@ -1429,9 +1460,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(Dev<R> d, int keymod
 // in place (tile order) and writes the bin's total.
 template <int NB>
 __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* cnt, uint32_t n_tiles, const Counters* ctr,
-                                                   uint32_t* bin_total)
+                                                   uint32_t* bin_total, unsigned int phase_bit)
 {
-    if (ctr && !ctr->phase_sorted) return;
+    if (ctr && !(ctr->phase_sorted & phase_bit)) return;
     __shared__ uint32_t wsum[4];
     const uint32_t bin = blockIdx.x;
     uint32_t* c = cnt + (size_t)bin * n_tiles;
@@ -1466,7 +1497,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(Dev<R> d, int key
                                                                uint32_t n, const uint32_t* cnt, uint32_t n_tiles,
                                                                const uint32_t* bin_total, uint32_t* perm)
 {
-    if (!ext_keys && !d.ctr->phase_sorted) return;
+    if (!ext_keys && !(d.ctr->phase_sorted & (keymode >= 2 ? 1u : 2u))) return;
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t run[NB];
     __shared__ uint32_t bbase[NB + 1];

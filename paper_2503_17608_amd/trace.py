@@ -8,7 +8,9 @@ iteration: live / queued / pending tracks, steps completed, and the GPU time
 of every kernel role.  `to_chrome_trace` turns the records into counter
 tracks (occupancy, steps) and one slice per kernel role per iteration, laid
 end to end on a GPU-time axis (the slices give each role's time, not the
-overlap of concurrent streams).
+overlap of concurrent streams).  `tail_analysis` bins the records by live
+tracks and finds where the along-step time per track leaves its plateau
+(the paper's analysis of along-step time against active tracks).
 
 Command line:
     python -m paper_2503_17608_amd.trace --events 200 --out trace.json
@@ -69,6 +71,56 @@ def to_chrome_trace(records, name="step loop"):
         ev.append({"name": f"iteration {r['iteration']}", "cat": "iteration", "ph": "X", "pid": 1, "tid": 2,
                    "ts": t0, "dur": t - t0, "args": {"alive": r["alive"], "steps": r["steps"]}})
     return {"traceEvents": ev, "displayTimeUnit": "ms"}
+
+
+ALONG_ROLES = ("along_neutral", "along_charged", "along_field")
+
+
+def tail_analysis(records, onset_factor=2.0):
+    """The occupancy analysis of a recorded run: along-step GPU time per
+    iteration and per live track, binned by live tracks (powers of two), and
+    the tail onset: the largest live-track bin whose along-step time per
+    track exceeds `onset_factor` times the lowest bin value (the plateau of
+    a full device).  Also the share of the run's kernel time spent in the
+    iterations below each bin."""
+    rows = []
+    for r in records:
+        n = r["alive"]
+        if n <= 0:
+            continue
+        along = sum(r["kernel_ms"].get(k, 0.0) for k in ALONG_ROLES)
+        total = sum(r["kernel_ms"].values())
+        rows.append((n, along, total, r["steps"]))
+    if not rows:
+        return {"bins": [], "onset_alive": None}
+    total_ms = sum(x[2] for x in rows)
+    bins = {}
+    for n, along, total, steps in rows:
+        b = n.bit_length() - 1
+        e = bins.setdefault(b, [0, 0.0, 0.0, 0, 0])
+        e[0] += 1
+        e[1] += along
+        e[2] += total
+        e[3] += steps
+        e[4] += n
+    out = []
+    for b in sorted(bins):
+        it, along, total, steps, tracks = bins[b]
+        out.append({"alive_from": 1 << b, "alive_to": (1 << (b + 1)) - 1, "iterations": it,
+                    "along_us_per_iteration": 1e3 * along / it, "along_ns_per_track": 1e6 * along / tracks,
+                    "kernel_us_per_iteration": 1e3 * total / it, "kernel_ns_per_step": 1e6 * total / max(steps, 1),
+                    "share_of_kernel_time": total / total_ms})
+    plateau = min(x["along_ns_per_track"] for x in out)
+    onset = None
+    for x in out:
+        if x["along_ns_per_track"] > onset_factor * plateau:
+            onset = x["alive_to"]
+    below = 0.0
+    for x in out:
+        below += x["share_of_kernel_time"]
+        x["share_at_or_below"] = below
+    return {"bins": out, "plateau_along_ns_per_track": plateau, "onset_factor": onset_factor,
+            "onset_alive": onset, "kernel_ms": total_ms}
 
 
 def write(records, path, name="step loop"):

@@ -75,11 +75,15 @@ def device_history(session_factory, prims, n_slots, max_iterations=200000):
     return np.concatenate(chunks) if chunks else np.zeros(0, dtype=t.dtype)
 
 
-def _state_diff(g, o):
-    """Per-step metric of one state (device record g, oracle post-step o)."""
+def _state_diff(g, o, pre):
+    """Per-step metric of one state (device record g, oracle post-step o,
+    oracle pre-step pre): energies relative to the pre-step energy,
+    directions absolute, positions relative to max(|r|, 1 cm), the
+    interaction length relative to max(n_lambda, 1).  A different particle
+    type, slab or interaction-length state is a discrete difference (inf)."""
     if int(g["type"]) != int(o["type"]) or int(g["slab"]) != int(o["slab"]):
         return "type/slab", np.inf
-    T0 = max(abs(float(o["T"])), 1e-300)
+    T0 = max(abs(float(pre["T"])), 1e-300)
     d = {"T": abs(float(g["T"]) - float(o["T"])) / T0,
          "u": float(np.abs(g["u"] - o["u"]).max()),
          "r": float(np.abs(g["r"] - o["r"]).max() / max(np.linalg.norm(o["r"]), 1.0))}
@@ -91,8 +95,20 @@ def _state_diff(g, o):
     return k, d[k]
 
 
-def first_divergence(trace, dev, tol=1e-12):
-    """Compare the oracle trace of an event with the device states."""
+@dataclass
+class Flip:
+    index: int                 # oracle record index (history order) of the first discrete difference, -1 if none
+    key: int
+    step: int
+    what: str
+    margin: float              # smallest oracle decision margin of that step (or of the step that created the track)
+    kind: str
+    drift: float               # largest continuous per-step difference seen before it (any track)
+    first_drift_index: int     # first record whose continuous difference exceeds the tolerance
+    n_steps: int
+
+
+def _compare(trace, dev, tol):
     at = {}
     for i in range(len(dev)):
         at[(int(dev["key"][i]), int(dev["step"][i]))] = i
@@ -105,17 +121,23 @@ def first_divergence(trace, dev, tol=1e-12):
         rec = trace[i]
         key, k1 = int(rec["post"]["key"]), int(rec["post"]["step"])
         j = at.get((key, k1))
-        what, diff = None, 0.0
         if rec["post"]["alive"]:
             if j is None:
                 what, diff = "track ended on the device only", np.inf
             else:
-                what, diff = _state_diff(dev[j], rec["post"])
-                if diff <= tol:
-                    what = None
+                what, diff = _state_diff(dev[j], rec["post"], rec["pre"])
         elif j is not None:
             what, diff = "track ended in the oracle only", np.inf
-        if what is None:
+        else:
+            what, diff = "", 0.0
+        yield i, rec, key, what, diff, creator
+
+
+def first_divergence(trace, dev, tol=1e-12):
+    """The first record (history order) whose post-step state the device does
+    not reproduce to `tol`, with the oracle's decision margin there."""
+    for i, rec, key, what, diff, creator in _compare(trace, dev, tol):
+        if diff <= tol:
             continue
         pm, pk = float("nan"), ""
         if int(rec["pre"]["step"]) == 0 and key in creator:
@@ -126,11 +148,36 @@ def first_divergence(trace, dev, tol=1e-12):
     return Divergence(-1, 0, 0, "", 0.0, np.inf, "", float("nan"), "", len(trace))
 
 
+def first_flip(trace, dev, tol=1e-12):
+    """The first discrete difference between the histories (a different
+    particle type, slab, interaction-length state, a track that ends on one
+    side only, or a per-step difference above 1e-6), with the oracle's decision margin at that step (the smaller of
+    the step's and, for a track's first step, of the step that created it),
+    and the largest continuous per-step difference seen before it."""
+    drift, first_drift = 0.0, -1
+    for i, rec, key, what, diff, creator in _compare(trace, dev, tol):
+        # (a difference of 1e-6 in one step is no rounding drift in FP64:
+        # the step took another process or sampled another final state)
+        if np.isfinite(diff) and diff <= 1e-6:
+            if diff > tol and first_drift < 0:
+                first_drift = i
+            drift = max(drift, diff)
+            continue
+        m, kind = float(rec["m"]["margin"]), oracle.MARGIN_KINDS[int(rec["m"]["kind"])]
+        if int(rec["pre"]["step"]) == 0 and key in creator:
+            pr = trace[creator[key]]
+            if float(pr["m"]["margin"]) < m:
+                m, kind = float(pr["m"]["margin"]), oracle.MARGIN_KINDS[int(pr["m"]["kind"])]
+        return Flip(i, key, int(rec["pre"]["step"]), what, m, kind, drift, first_drift, len(trace))
+    return Flip(-1, 0, 0, "", np.inf, "", drift, first_drift, len(trace))
+
+
 def diagnose_event(w, event, session_factory, n_slots=8192, tol=1e-12, msc=False):
-    """First divergence of event `event` of workload `w` (oracle vs device)."""
+    """First continuous divergence and first discrete difference (flip) of
+    event `event` of workload `w`, oracle against device."""
     prims = w.primaries[w.primaries["event"] == event]
     pb = oracle.problem_for(w, msc=msc)
     tr, _ = oracle.tracks_from_primaries(prims)
     trace = pb.trace_event(tr)
     dev = device_history(session_factory, prims, n_slots)
-    return first_divergence(trace, dev, tol)
+    return first_divergence(trace, dev, tol), first_flip(trace, dev, tol)

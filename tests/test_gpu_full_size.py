@@ -4,11 +4,13 @@ partitioned fill, 8-iteration graph batches, LDS-staged tables, one stream,
 substep cap 10, fused interaction kernel, drain below 65536 tracks), plus
 degenerate and rejected inputs.
 
-* 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event against
-  the FP64 oracle (integer ledger equal, deposits to 1e-9 of the primary
-  energy), for the sort policies none / partition / radix / queue, with the
-  unpartitioned fill, with parent-slot reuse, and with the seven interaction
-  kernels on four streams and no drain;
+* 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event of the
+  benchmark's configuration against the FP64 oracle (integer ledger equal,
+  deposits to 1e-9 of the primary energy, or a decision flip that the flip
+  diagnoser shows rounding decided), and the sort policies none / radix /
+  queue, the unpartitioned fill, parent-slot reuse, and the seven
+  interaction kernels on four streams with no drain against that run
+  (integer ledgers equal, deposits to 1e-12);
 * 10^4 mixed primaries in a 5 degree cone at 2^20 slots: FP64 per event
   against the oracle, and the mixed-precision run's per-layer mean deposit
   within 0.5 % of the FP64 oracle;
@@ -23,7 +25,10 @@ import numpy as np
 import pytest
 
 import workloads
-from tests.gpu_helpers import layer_sums, ledger_int_mismatch, run_oracle, session_for
+from tests.gpu_helpers import assert_events_match as _assert_events_match
+from tests.gpu_helpers import assert_same_as as _assert_same_as
+from tests.gpu_helpers import event_energy as _event_energy
+from tests.gpu_helpers import layer_sums, run_oracle, session_for
 
 pytestmark = pytest.mark.gpu
 
@@ -48,27 +53,6 @@ def _run(w, events=None, tuning=None, **kw):
     return edep, led, c
 
 
-def _event_energy(w):
-    return np.bincount(w.primaries["event"].astype(np.int64), weights=w.primaries["T"], minlength=w.n_events)
-
-
-def _assert_events_match(w, edep, led, e_ref, l_ref, tag, events=None):
-    """Integer ledgers equal per event; per-slab deposits within 1e-7 of the
-    event's energy, and within 1e-9 for all but 0.1 % of the events.  The
-    device's and the host's libm and FMA contraction differ in the last bit;
-    over the ~10^4 steps of a 1 GeV history such differences can grow
-    without changing any decision, so the bound is looser than per step."""
-    e0 = _event_energy(w)
-    if events is not None:
-        e0 = e0[np.asarray(events, dtype=np.int64)]
-    bad = ledger_int_mismatch(led, l_ref)
-    assert bad is None, (tag, bad)
-    rel = np.abs(edep - e_ref).max(1) / e0
-    assert rel.max() < 1e-7, (tag, rel.max())
-    assert np.count_nonzero(rel > 1e-9) <= max(1, len(rel) // 1000), (tag, np.sort(rel)[-5:])
-    assert np.all(np.abs(led["escaped"] - l_ref["escaped"]) <= 1e-7 * e0), tag
-
-
 def _assert_ledger_exact(w, edep, led, events=None):
     e0 = _event_energy(w)
     if events is not None:
@@ -81,6 +65,7 @@ def test_full_size_electron_showers_every_policy():
     w = workloads.electron_showers_1gev_field()
     assert w.n_events == 10_000 and w.n_slots == 1 << 20
     e_ref, l_ref, steps = run_oracle(w)
+    first = None
     for policy in ("partition", "none", "radix", "queue", "partition+fill0", "partition+reuse",
                    "partition+unfused+nodrain"):
         if policy == "partition+fill0":
@@ -96,7 +81,13 @@ def test_full_size_electron_showers_every_policy():
             edep, led, c = _run(w, sort_policy=policy)
         assert c["overflow"] == 0, policy
         assert c["steps"] == steps, (policy, c["steps"], steps)
-        _assert_events_match(w, edep, led, e_ref, l_ref, policy)
+        if first is None:
+            # the benchmark's configuration against the oracle ...
+            _assert_events_match(w, edep, led, e_ref, l_ref, policy)
+            first = (edep, led)
+        else:
+            # ... and every other configuration against it
+            _assert_same_as(w, edep, led, first[0], first[1], policy)
     _assert_ledger_exact(w, edep, led)
     lg, lr = layer_sums(edep), layer_sums(e_ref)
     sig = np.sqrt(lg.var(0) / len(lg) + lr.var(0) / len(lr))
@@ -137,7 +128,10 @@ def test_full_size_batched_events_sampled():
     assert c["overflow"] == 0
     _assert_ledger_exact(w, edep_all, led_all)
     e_ref, l_ref, _ = run_oracle(w, events=sample)
-    _assert_events_match(w, edep_all[sample], led_all[sample], e_ref, l_ref, "sample", events=sample)
+    # (events of up to 500 primaries of up to 100 GeV are too long for a
+    # step-by-step diagnosis: here every sampled event must be within 1e-9)
+    _assert_events_match(w, edep_all[sample], led_all[sample], e_ref, l_ref, "sample", events=sample,
+                         diagnose=False)
 
 
 def _degenerate_primaries(w):

@@ -16,7 +16,8 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_helpers import layer_sums, ledger_int_mismatch, random_states, session_for, to_lib_tracks
+from tests.gpu_helpers import (assert_events_match, layer_sums, ledger_int_mismatch, random_states, session_for,
+                               to_lib_tracks)
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +76,8 @@ def test_sort_permutation_bit_exact(n, policy, nb):
 
 
 # ----------------------------------------------------------------------------- one step
-def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc=False, steps=(0, 200)):
+def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc=False, steps=(0, 200),
+                  return_margins=False):
     rng = np.random.default_rng(seed)
     f32 = precision == "mixed"
     states = random_states(w, n, rng, types=types, e_max=e_max, f32=f32, steps=steps)
@@ -91,7 +93,7 @@ def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc
 
     pb = oracle.problem_for(w, msc=msc)
     ref_t = states.copy()
-    res = pb.step(ref_t)
+    res, margins = pb.step_margins(ref_t)
 
     bad = []
     worst = 0.0
@@ -111,20 +113,20 @@ def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc
             if g["slab"] != o["slab"] or g["step"] != o["step"] or g["type"] != o["type"]:
                 bad.append((i, "int", (g["slab"], g["step"]), (o["slab"], o["step"])))
                 continue
-            errs.append(abs(g["T"] - o["T"]) / T0)
-            errs.append(np.abs(g["u"] - o["u"]).max())
-            errs.append(np.abs(g["r"] - o["r"]).max() / max(np.linalg.norm(o["r"]), 1.0))
+            errs.append(("T", abs(g["T"] - o["T"]) / T0))
+            errs.append(("u", np.abs(g["u"] - o["u"]).max()))
+            errs.append(("r", np.abs(g["r"] - o["r"]).max() / max(np.linalg.norm(o["r"]), 1.0)))
             if (o["nl"] < 0) != (g["nl"] < 0):
                 bad.append((i, "nl-unset", g["nl"], o["nl"]))
                 continue
             if o["nl"] >= 0:
-                errs.append(abs(g["nl"] - o["nl"]) / max(abs(o["nl"]), 1.0))
+                errs.append(("n_lambda", abs(g["nl"] - o["nl"]) / max(abs(o["nl"]), 1.0)))
         # tallies of this track's row
         e_gpu = edep[r]
         e_ref = np.zeros_like(e_gpu)
         e_ref[res[i]["dep_slab"]] = res[i]["edep"]
-        errs.append(np.abs(e_gpu - e_ref).max() / T0)
-        errs.append(abs(led[r]["escaped"] - res[i]["escaped"]) / T0)
+        errs.append(("deposit", np.abs(e_gpu - e_ref).max() / T0))
+        errs.append(("escaped", abs(led[r]["escaped"] - res[i]["escaped"]) / T0))
         if led[r]["n_pair"] != res[i]["n_pair"] or led[r]["n_annih"] != res[i]["n_annih"]:
             bad.append((i, "pair/annih"))
             continue
@@ -141,13 +143,15 @@ def _step_compare(w, n, precision, seed, tol, types=(0, 1, 2), e_max=1000.0, msc
             if a["key"] != b["key"] or a["type"] != b["type"] or a["slab"] != b["slab"]:
                 bad.append((i, "sec-int"))
                 break
-            errs.append(abs(a["T"] - b["T"]) / T0)
-            errs.append(np.abs(a["u"] - b["u"]).max())
-            errs.append(np.abs(a["r"] - b["r"]).max() / max(np.linalg.norm(b["r"]), 1.0))
-        e = max(errs) if errs else 0.0
+            errs.append(("secondary T", abs(a["T"] - b["T"]) / T0))
+            errs.append(("secondary u", np.abs(a["u"] - b["u"]).max()))
+            errs.append(("secondary r", np.abs(a["r"] - b["r"]).max() / max(np.linalg.norm(b["r"]), 1.0)))
+        what, e = max(errs, key=lambda x: x[1]) if errs else ("", 0.0)
         worst = max(worst, e)
         if e > tol:
-            bad.append((i, "tol", e, res[i]["outcome"], res[i]["process"]))
+            bad.append((i, "tol", e, what, res[i]["outcome"], res[i]["process"]))
+    if return_margins:
+        return bad, worst, margins, states
     return bad, worst
 
 
@@ -174,10 +178,54 @@ def test_single_step_parity_fp64(wl):
 def test_single_step_parity_mixed(wl):
     w = workloads.small_electron_showers(1) if wl == "nofield" else workloads.electron_showers_1gev_field(1)
     n = 30000
-    bad, worst = _step_compare(w, n, "mixed", seed=17, tol=1e-5)
-    print("worst", worst, "mismatches", len(bad), bad[:5])
-    # FP32 decisions may flip where the oracle's margin is below FP32 resolution
-    assert len(bad) <= max(3, int(2e-3 * n)), bad[:10]
+    bad, worst, margins, states = _step_compare(w, n, "mixed", seed=17, tol=1e-5, return_margins=True)
+    _assert_fp32_flips(w, bad, worst, margins, states, n)
+
+
+def _draw_resolution(w, st):
+    """Relative difference of the interaction length drawn by a step in FP32
+    and in FP64 from the same Philox word: the FP32 uniform keeps the word's
+    top 23 bits, so -ln U differs by up to 2^-24 / U, which is large for
+    small U.  Zero when the step draws no interaction length."""
+    if st["nl"] >= 0:
+        return 0.0
+    wd = int(oracle.philox4x64([int(st["key"]), int(st["step"]), 0, 0], [w.seed, int(st["event"])])[0])
+    u64 = ((wd >> 12) + 0.5) * 2.0 ** -52
+    u32 = float(np.float32(((wd >> 41) + 0.5) * 2.0 ** -23))
+    n64, n32 = -np.log(u64), -np.log(u32)
+    return abs(n32 - n64) / max(n64, 1.0)
+
+
+def _assert_fp32_flips(w, bad, worst, margins, states, n):
+    """Mixed precision against the FP64 oracle: a step outside 1e-5 (of any
+    kind: a state, tally or secondary outside tolerance, a different
+    process, end of step or secondary) is allowed only where
+    * the oracle took one of the step's discrete decisions within 1e-5 of its
+      threshold, which FP32 arithmetic can take the other way (a flip), at
+      most 1e-4 of the steps (at least 3), or
+    * the step drew its interaction length from a uniform small enough that
+      the FP32 uniform's 23 bits change -ln U by more than 1e-6 (the FP32
+      reading of the random numbers: same word, fewer bits), which moves the
+      step's end by more than the tolerance without any decision near its
+      threshold; such draws are about 1e-3 of the draws, and the test allows
+      2e-3 of the steps."""
+    flips, resolution, unexplained = [], [], []
+    for b in bad:
+        i = b[0]
+        mg, kind = float(margins[i]["margin"]), oracle.MARGIN_KINDS[int(margins[i]["kind"])]
+        dr = _draw_resolution(w, states[i])
+        rec = (i, b[1:4], mg, kind, dr)
+        if mg < 1e-5:
+            flips.append(rec)
+        elif dr > 1e-6:
+            resolution.append(rec)
+        else:
+            unexplained.append(rec)
+    print("worst", worst, "mismatches", len(bad), "flips", len(flips), "draw resolution", len(resolution),
+          "unexplained", len(unexplained), (unexplained or flips or resolution)[:6])
+    assert not unexplained, unexplained[:10]
+    assert len(flips) <= max(3, int(1e-4 * n)), flips[:10]
+    assert len(resolution) <= max(3, int(2e-3 * n)), resolution[:10]
 
 
 # ----------------------------------------------------------------------------- showers
@@ -308,12 +356,13 @@ def test_single_step_parity_with_multiple_scattering(precision, wl):
     w = workloads.small_electron_showers(1) if wl == "nofield" else workloads.electron_showers_1gev_field(1)
     n = 20000
     tol = 1e-12 if precision == "f64" else 1e-5
-    bad, worst = _step_compare(w, n, precision, seed=23, tol=tol, types=(1, 2), msc=True)
-    print("worst", worst, "mismatches", len(bad), bad[:5])
+    bad, worst, margins, states = _step_compare(w, n, precision, seed=23, tol=tol, types=(1, 2), msc=True,
+                                                return_margins=True)
     if precision == "f64":
+        print("worst", worst, "mismatches", len(bad), bad[:5])
         assert not bad, bad[:10]
     else:
-        assert len(bad) <= max(3, int(2e-3 * n)), bad[:10]
+        _assert_fp32_flips(w, bad, worst, margins, states, n)
 
 
 def test_showers_with_multiple_scattering_match_oracle():
@@ -332,6 +381,4 @@ def test_showers_with_multiple_scattering_match_oracle():
         edep, led = s.tallies_by_event(np.arange(w.n_events))
         s.close()
         assert c["steps"] == steps, (policy, drain, c["steps"], steps)
-        assert _ledger_equal_int(led, l_ref) is None, (policy, drain)
-        rel = np.abs(edep - e_ref).max(1) / w.primaries["T"]
-        assert rel.max() < 1e-7 and np.count_nonzero(rel > 1e-9) <= 1, (policy, drain, np.sort(rel)[-3:])
+        assert_events_match(w, edep, led, e_ref, l_ref, (policy, drain), msc=True)

@@ -207,7 +207,7 @@ def test_autotune_finds_the_cost_model_optimum(monkeypatch):
     monkeypatch.setattr(time, "sleep", lambda dt: setattr(clock, "t", clock.t + dt))
     monkeypatch.setattr(autotune, "_run", lambda sess, sample, events: _timed(sess, clock))
     sample = _events(4)[0][1]
-    res = autotune.autotune(s, sample)
+    res = autotune.autotune(s, sample, phases=False)
     assert res["sort_policy"] == "partition"
     assert res["tail_threshold"] == 2048
     assert res["fuse_interactions"] is True and res["drain_threshold"] == 16384
@@ -241,3 +241,53 @@ def test_event_parallel_hands_out_every_chunk_once():
     assert steps == sum(s.steps for s in sessions)
     for e, v in edep.items():
         assert np.all(v == float(e))
+
+
+class PhaseSession:
+    """Iterations with a fixed sequence of live-track counts whose kernel time
+    depends on the phase table: reordering at sort point 1 pays above 4096
+    live tracks and costs below, at sort point 2 above 256."""
+    ALIVE = [1 << 20, 1 << 18, 5000, 300, 20, 0]
+
+    def __init__(self):
+        self.masks = (autotune.ALL_BUCKETS, autotune.ALL_BUCKETS)
+        self.i = 0
+        self.last = 0.0
+
+    def set_tuning(self, phase_sort=None, **kw):
+        if phase_sort is not None:
+            self.masks = phase_sort
+
+    def push(self, prims):
+        self.i = 0
+
+    def profile(self, mask):
+        pass
+
+    def release(self, events):
+        pass
+
+    def step(self, n):
+        a = self.ALIVE[self.i]
+        self.i += 1
+        t = 1.0
+        if a:
+            b = a.bit_length() - 1
+            s1, s2 = (self.masks[0] >> b) & 1, (self.masks[1] >> b) & 1
+            t += (0.1 if s1 else 0.3) if a >= 4096 else (0.5 if s1 else 0.2)
+            t += (0.1 if s2 else 0.3) if a >= 256 else (0.5 if s2 else 0.2)
+        self.last = t
+        return {"alive": a, "queued": 0, "pending_primaries": 0}
+
+    def profile_read(self):
+        return {"along_field": (self.last, 1)}
+
+
+def test_phase_table_reorders_each_sort_point_where_it_pays():
+    s = PhaseSession()
+    (m1, m2), info = autotune.phase_table(s, np.zeros(1), np.zeros(1, dtype=np.uint64))
+    for a, want1, want2 in ((1 << 20, 1, 1), (1 << 18, 1, 1), (5000, 1, 1), (300, 0, 1), (20, 0, 0)):
+        b = a.bit_length() - 1
+        assert (m1 >> b) & 1 == want1 and (m2 >> b) & 1 == want2, (a, info["choice"])
+    # buckets the sample never reached keep reordering
+    assert (m1 >> 30) & 1 and (m2 >> 30) & 1 and (m1 >> 0) & 1

@@ -30,3 +30,22 @@ def test_counter_tracks_carry_occupancy():
     doc = trace.to_chrome_trace(_records())
     cs = [e for e in doc["traceEvents"] if e["ph"] == "C" and e["name"] == "tracks"]
     assert [(c["args"]["alive"], c["args"]["queued"], c["args"]["pending"]) for c in cs] == [(10, 4, 2), (3, 0, 0)]
+
+
+def test_tail_analysis_finds_where_time_per_track_leaves_its_plateau():
+    # a device whose along-step time is max(latency floor, tracks x 1 ns):
+    # 20 us floor, so below 20 000 tracks the time per track rises
+    recs = []
+    for i, n in enumerate([1 << 20, 700_000, 300_000, 100_000, 40_000, 15_000, 6_000, 2_000, 500, 100, 10]):
+        along = max(0.020, n * 1e-6)                       # ms
+        recs.append({"iteration": i, "alive": n, "queued": 0, "pending": 0, "steps": n,
+                     "kernel_ms": {"along_field": along, "sort": 0.010}})
+    a = trace.tail_analysis(recs, onset_factor=2.0)
+    assert abs(a["plateau_along_ns_per_track"] - 1.0) < 1e-9
+    # 15 000 tracks (bin 8192-16383) cost 1.33 ns per track, 6 000 tracks
+    # (bin 4096-8191) 3.3 ns: the tail starts in the 4096-8191 bin
+    assert a["onset_alive"] == 8191
+    assert abs(a["bins"][-1]["share_at_or_below"] - 1.0) < 1e-12
+    assert sum(b["iterations"] for b in a["bins"]) == len(recs)
+    top = a["bins"][-1]
+    assert top["alive_from"] == 1 << 20 and abs(top["along_ns_per_track"] - 1.0) < 1e-9
