@@ -294,14 +294,25 @@ def cpu_baseline(w, n_events):
                             "sample": f"first {n1} events ({steps1} track-steps, {dt1:.2f} s)"}}
 
 
-def event_parallel_rate(w, args, precision, k, repeats=2):
+def drain_for(args, n_slots):
+    """The drain threshold for a session of n_slots slots: the configured one
+    at 2^20 slots and above, scaled with the slots below (a fixed threshold
+    would drain a small session from its start)."""
+    if args.drain_threshold <= 0:
+        return 0
+    return max(256, min(args.drain_threshold, args.drain_threshold * n_slots // (1 << 20)))
+
+
+def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
     """Event-parallel mode: k sessions of n_slots/k slots, each on its own
     stream and host thread, events handed out in chunks; track-steps/s."""
     import torch
 
     from paper_2503_17608_amd import emstep, multistream
     st = w.stack
-    chunk = max(1, w.n_events // (4 * k))
+    # the paper's event-parallel runs hand 16 large events to the streams;
+    # here the workload's events are grouped into 16 chunks of equal count
+    chunk = max(1, (w.n_events + 15) // 16)
     sessions = []
     for _ in range(k):
         s = emstep.Session(max(w.n_slots // k, 1024), precision=precision, max_events=chunk, max_slabs=st.n_slabs,
@@ -309,17 +320,26 @@ def event_parallel_rate(w, args, precision, k, repeats=2):
                            max_substeps=args.max_substeps, graph_iterations=args.graph, lds_tables=args.lds_tables,
                            streams=1, stream=torch.cuda.Stream(), n_primaries=max(len(w.primaries), 1 << 16))
         s.load(st.z_planes, st.slab_material, st.half_width, st.B, st.materials, w.ecut)
-        if args.drain_threshold > 0:
-            s.set_tuning(drain_threshold=max(args.drain_threshold // k, 256), drain_steps=args.drain_steps)
+        # the same tuning as the mixed-event run, the drain threshold scaled
+        # to the session's slots
+        s.set_tuning(drain_threshold=drain_for(args, w.n_slots // k), drain_steps=args.drain_steps,
+                     fuse_interactions=bool(args.fuse_interactions))
         sessions.append(s)
     multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)     # warm-up
     best = None
+    it0 = [s.counters()["iterations"] for s in sessions]
     for _ in range(repeats):
         torch.cuda.synchronize()
         _, _, steps, wall = multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)
         best = steps / wall if best is None else max(best, steps / wall)
+    its = [s.counters()["iterations"] - a for s, a in zip(sessions, it0)]
     for s in sessions:
         s.close()
+    if details:
+        n_chunks = (w.n_events + chunk - 1) // chunk
+        return best, {"sessions": k, "chunk_events": chunk, "chunks": n_chunks,
+                      "iterations_per_session": [x // repeats for x in its],
+                      "iterations_per_chunk": sum(its) / repeats / n_chunks}
     return best
 
 
@@ -579,12 +599,13 @@ def sweep_mode(args):
         n = 1 << e
         w.n_slots = n
         t0 = time.perf_counter()
-        r = run_variant(w, args, precision, args.policy, args.init_partition, None)
+        r = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=drain_for(args, n))
         row = {"slots": n, "mixed": r["steps"] / r["seconds"],
                "mixed_iterations_per_batch": r["iterations"] // args.steps}
         for k in (2, 4, 8):
             if n // k >= 1024:
-                row[f"event_parallel_{k}"] = event_parallel_rate(w, args, precision, k, repeats=1)
+                row[f"event_parallel_{k}"], row[f"event_parallel_{k}_detail"] = event_parallel_rate(
+                    w, args, precision, k, repeats=1, details=True)
         row["wall_s"] = time.perf_counter() - t0
         print(json.dumps(row), flush=True)
         rows.append(row)

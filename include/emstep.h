@@ -90,7 +90,7 @@ typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_particle;
 typedef struct {
     uint32_t abi_version;      /* must be EMS_ABI_VERSION */
     int32_t precision;         /* ems_precision: FP64, or FP32 energies/directions/tables with FP64 positions */
-    uint64_t n_slots;          /* track slots (threads of the state arrays) */
+    uint64_t n_slots;          /* track slots (threads of the state arrays), in [1, 2^30) */
     uint64_t n_initializers;   /* capacity of the secondary initializer buffer */
     uint64_t n_primaries;      /* capacity of the pending-primary buffer */
     uint32_t max_events;       /* tally rows (events resident at once) */

@@ -195,6 +195,10 @@ struct ems_ctx {
     // tuning (switchable at run time)
     int policy = 0;
     uint32_t tail_threshold = 0;
+    // resident-grid cache of the field along-step, per precision (FP64, FP32)
+    int field_grid_bs[2] = {0, 0};
+    size_t field_grid_lds[2] = {0, 0};
+    uint32_t field_grid_resident[2] = {0, 0};
     uint32_t phase_sort[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
@@ -451,6 +455,31 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, int km)
     }
 }
 
+// Grid of the field along-step with a sort policy: the blocks the device holds
+// at once (each thread then walks its tracks at the grid stride with the
+// next track's loads in flight), at most the slot-covering grid.  Measured:
+// one resident round 2.97e9 track-steps/s, two 2.90e9, the slot-covering
+// grid (one track per thread) 2.84e9.
+template <class R>
+uint32_t field_grid(ems_ctx* c, uint32_t g, int bs, size_t lds)
+{
+    const int k = sizeof(R) == 8 ? 0 : 1;
+    if (c->field_grid_bs[k] != bs || c->field_grid_lds[k] != lds) {
+        int nb = 0, cus = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_along_field<R>), bs,
+                                                         lds) != hipSuccess ||
+            nb < 1)
+            nb = 1;
+        c->field_grid_resident[k] = (uint32_t)(nb * cus);
+        c->field_grid_bs[k] = bs;
+        c->field_grid_lds[k] = lds;
+    }
+    return c->field_grid_resident[k] < g ? c->field_grid_resident[k] : g;
+}
+
 template <class R>
 void launch_iteration(ems_ctx* c, bool no_init, bool prof)
 {
@@ -483,7 +512,10 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     ln.one(R_ALONG_NEUTRAL, k_along_straight<R, false>, dim3(G(R_ALONG_NEUTRAL)), dim3(B(R_ALONG_NEUTRAL)), lds,
            s_neutral, d);
     if (d.has_field)
-        ln.one(R_ALONG_FIELD, k_along_field<R>, dim3(G(R_ALONG_FIELD)), dim3(B(R_ALONG_FIELD)), lds, st, d);
+        ln.one(R_ALONG_FIELD, k_along_field<R>,
+               dim3(c->policy == EMS_SORT_NONE ? G(R_ALONG_FIELD)
+                                               : field_grid<R>(c, G(R_ALONG_FIELD), B(R_ALONG_FIELD), lds)),
+               dim3(B(R_ALONG_FIELD)), lds, st, d);
     else
         ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
                st, d);

@@ -881,23 +881,52 @@ __device__ __forceinline__ void normalize_d(double v[3])
 // Outputs as for the straight-line step, plus the RK4 evaluations made
 // (`att`), whether the step paused (`paused_n`) and whether the pre-step ran
 // (`pre_n`).
+// The fields a field step reads first, loaded together (the field kernel
+// loads the next track's while it steps the current one).
 template <class R>
-__device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int max_sub,
-                                                  uint32_t& row, uint8_t& next, uint32_t& retired, uint32_t& att,
-                                                  uint32_t& paused_n, uint32_t& pre_n)
+struct FieldIn {
+    uint8_t typ, fl;
+    uint16_t slab;
+    uint32_t row, step;
+    uint64_t key;
+    R T, nl;
+    R u[3];
+    double r[3];
+};
+
+template <class R>
+__device__ __forceinline__ void load_field_in(const Dev<R>& d, uint32_t s, FieldIn<R>& f)
 {
-    const int typ = d.type[s];
-    row = d.row[s];
-    uint16_t slab = d.slab[s];
+    f.typ = d.type[s];
+    f.fl = d.flags[s];
+    f.slab = d.slab[s];
+    f.row = d.row[s];
+    f.step = d.step[s];
+    f.key = d.key[s];
+    f.T = d.T[s];
+    f.nl = d.nl[s];
+    f.u[0] = d.ux[s]; f.u[1] = d.uy[s]; f.u[2] = d.uz[s];
+    f.r[0] = d.x[s]; f.r[1] = d.y[s]; f.r[2] = d.z[s];
+}
+
+template <class R>
+__device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s,
+                                                  const FieldIn<R>& in, int max_sub, uint32_t& row, uint8_t& next,
+                                                  uint32_t& retired, uint32_t& att, uint32_t& paused_n,
+                                                  uint32_t& pre_n)
+{
+    const int typ = in.typ;
+    row = in.row;
+    uint16_t slab = in.slab;
     const uint16_t slab0 = slab;
     const int mat = d.smat[slab];
-    R T = d.T[s];
-    double u[3] = {(double)d.ux[s], (double)d.uy[s], (double)d.uz[s]};
-    double r[3] = {d.x[s], d.y[s], d.z[s]};
-    uint8_t fl = d.flags[s];
-    R nl = d.nl[s];
-    uint32_t step = d.step[s];
-    const uint64_t key = d.key[s];
+    R T = in.T;
+    double u[3] = {(double)in.u[0], (double)in.u[1], (double)in.u[2]};
+    double r[3] = {in.r[0], in.r[1], in.r[2]};
+    uint8_t fl = in.fl;
+    R nl = in.nl;
+    uint32_t step = in.step;
+    const uint64_t key = in.key;
     const uint64_t event = d.row_event[row];
     const bool resumed = (fl & F_PAUSED) != 0;
     double s_phys, s_done = 0.0, h_try = 0.0;
@@ -1032,6 +1061,16 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
     }
 }
 
+template <class R>
+__device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, int max_sub,
+                                                  uint32_t& row, uint8_t& next, uint32_t& retired, uint32_t& att,
+                                                  uint32_t& paused_n, uint32_t& pre_n)
+{
+    FieldIn<R> in;
+    load_field_in(d, s, in);
+    along_field_track<R>(d, tb, s, in, max_sub, row, next, retired, att, paused_n, pre_n);
+}
+
 // Uniform-field propagation with RK4 substeps of at most sqrt(8 d_chord /
 // curvature), boundary search by chord fraction, and a cap of max_substeps
 // RK4 evaluations per iteration: at the cap the step pauses with its
@@ -1045,18 +1084,55 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
     EMS_TRACK_RANGE(d, A_FIELD)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
     unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0, pre_acc = 0;
-    EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
-    uint32_t row = 0;
-    uint8_t next = A_NONE;
-    uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
-    if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n, pre_n);
-    pre_acc += pre_n;
-    leave_event(d, retired != 0, row);
-    ret_acc += retired;
-    sub_acc += att;
-    pause_acc += paused_n;
-    if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u)) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
-    EMS_END_TRACKS
+    if (_mode == 1) {
+        // sorted: the field tracks are one index range.  Each thread walks
+        // its tracks at the grid stride and loads the next one's fields (and
+        // the slot after it) before stepping the current one, so those loads
+        // are in flight during the step.
+        const uint32_t stride = gridDim.x * blockDim.x;
+        uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+        uint32_t s = i < _n ? d.perm[_off + i] : 0u;
+        FieldIn<R> cur;
+        if (i < _n) load_field_in(d, s, cur);
+        uint32_t s_next = i + stride < _n ? d.perm[_off + i + stride] : 0u;
+        for (uint32_t base = blockIdx.x * blockDim.x; base < _n; base += stride) {
+            const bool act = i < _n;
+            const uint32_t i1 = i + stride, i2 = i + 2 * stride;
+            FieldIn<R> nxt;
+            if (i1 < _n) load_field_in(d, s_next, nxt);
+            const uint32_t s_after = i2 < _n ? d.perm[_off + i2] : 0u;
+            uint32_t row = 0;
+            uint8_t next = A_NONE;
+            uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
+            if (act) along_field_track<R>(d, tb, s, cur, d.max_substeps, row, next, retired, att, paused_n, pre_n);
+            _work += act ? 1u : 0u;
+            pre_acc += pre_n;
+            leave_event(d, retired != 0, row);
+            ret_acc += retired;
+            sub_acc += att;
+            pause_acc += paused_n;
+            if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u))
+                append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+            i = i1;
+            s = s_next;
+            cur = nxt;
+            s_next = s_after;
+        }
+    } else {
+        EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
+        uint32_t row = 0;
+        uint8_t next = A_NONE;
+        uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
+        if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n, pre_n);
+        pre_acc += pre_n;
+        leave_event(d, retired != 0, row);
+        ret_acc += retired;
+        sub_acc += att;
+        pause_acc += paused_n;
+        if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u))
+            append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+        EMS_END_TRACKS
+    }
     flush_count(d, W_FIELD, _work);
     flush_count(d, kStepsSlot + W_FIELD, ret_acc);
     flush_count(d, W_SUBSTEPS, sub_acc);
