@@ -203,10 +203,12 @@ def make_workload(name, events, slots):
     return w
 
 
-def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None):
+def new_session(w, args, precision, policy, init_partition, graph=None, drain=None, reuse=None, fuse=None,
+                n_initializers=None):
     from paper_2503_17608_amd import emstep
     st = w.stack
     s = emstep.Session(w.n_slots, precision=precision, max_events=max(w.n_events, 1), max_slabs=st.n_slabs,
+                       n_initializers=n_initializers,
                        max_materials=len(st.materials), seed=w.seed, sort_policy=policy,
                        init_partition=init_partition, max_substeps=args.max_substeps, block_size=args.block_size,
                        graph_iterations=args.graph if graph is None else graph, lds_tables=args.lds_tables,
@@ -230,8 +232,10 @@ def time_batch(s, primaries, events):
     return c, time.perf_counter() - t0
 
 
-def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None):
-    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse)
+def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=None, drain=None, reuse=None, fuse=None,
+                n_initializers=None):
+    s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse,
+                    n_initializers=n_initializers)
     events = np.unique(w.primaries["event"])
     tuned = None
     if tune is not None:
@@ -316,6 +320,7 @@ def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
     sessions = []
     for _ in range(k):
         s = emstep.Session(max(w.n_slots // k, 1024), precision=precision, max_events=chunk, max_slabs=st.n_slabs,
+                           n_initializers=max(16 * (w.n_slots // k), 1 << 23),
                            max_materials=len(st.materials), seed=w.seed, sort_policy=args.policy,
                            max_substeps=args.max_substeps, graph_iterations=args.graph, lds_tables=args.lds_tables,
                            streams=1, stream=torch.cuda.Stream(), n_primaries=max(len(w.primaries), 1 << 16))
@@ -599,7 +604,10 @@ def sweep_mode(args):
         n = 1 << e
         w.n_slots = n
         t0 = time.perf_counter()
-        r = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=drain_for(args, n))
+        # few slots hold back many secondaries: the initializer buffer is
+        # sized for the whole workload's peak, not for the slots
+        r = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=drain_for(args, n),
+                        n_initializers=max(16 * n, 1 << 24))
         row = {"slots": n, "mixed": r["steps"] / r["seconds"],
                "mixed_iterations_per_batch": r["iterations"] // args.steps}
         for k in (2, 4, 8):
@@ -677,7 +685,8 @@ def main():
     }
     if r["tuned"] is not None:
         out["config"]["autotuned"] = {k: r["tuned"][k] for k in ("sort_policy", "tail_threshold", "block",
-                                                                 "fuse_interactions", "drain_threshold")}
+                                                                 "fuse_interactions", "drain_threshold", "phase_sort")}
+        out["config"]["autotuned"]["phase_choice"] = r["tuned"].get("phase_table", {}).get("choice")
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
         tracks = r["work_prof"][prof_kernel]
