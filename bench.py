@@ -332,19 +332,23 @@ def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
         sessions.append(s)
     multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)     # warm-up
     best = None
-    it0 = [s.counters()["iterations"] for s in sessions]
+    log = []
     for _ in range(repeats):
         torch.cuda.synchronize()
-        _, _, steps, wall = multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)
+        log = []
+        _, _, steps, wall = multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False,
+                                                           chunk_log=log)
         best = steps / wall if best is None else max(best, steps / wall)
-    its = [s.counters()["iterations"] - a for s, a in zip(sessions, it0)]
     for s in sessions:
         s.close()
     if details:
-        n_chunks = (w.n_events + chunk - 1) // chunk
-        return best, {"sessions": k, "chunk_events": chunk, "chunks": n_chunks,
-                      "iterations_per_session": [x // repeats for x in its],
-                      "iterations_per_chunk": sum(its) / repeats / n_chunks}
+        n = max(len(log), 1)
+        return best, {"sessions": k, "chunk_events": chunk, "chunks": len(log),
+                      "iterations_per_chunk": sum(x["iterations"] for x in log) / n,
+                      "run_ms_per_chunk": 1e3 * sum(x["run_s"] for x in log) / n,
+                      "push_release_ms_per_chunk": 1e3 * sum(x["push_s"] + x["release_s"] for x in log) / n,
+                      "chunks_per_session": [sum(1 for x in log if x["session"] == j) for j in range(k)],
+                      "wall_s": max((x["end"] for x in log), default=0.0)}
     return best
 
 

@@ -375,7 +375,10 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * context.
  *
  * Drain (ems_run only; 0 = off): once the latest counter snapshot shows fewer
- * than drain_threshold tracks alive, queued or pending, each further
+ * than drain_threshold tracks alive, queued or pending, and no more than the
+ * snapshot before it (the tail of the run, not the ramp of a run that starts
+ * with few tracks: the first snapshot never starts it; 0xFFFFFFFF drains from
+ * the first iteration on), each further
  * iteration fills the vacant slots and then runs one kernel in which every
  * block steps its own tracks in rounds, for up to drain_steps rounds (> 0):
  * half of a block's threads own occupied slots and half vacant ones,

@@ -67,45 +67,59 @@ ALL_BUCKETS = 0xFFFFFFFF
 
 def iteration_times(session, primaries, events, max_iterations=200_000):
     """Step `primaries` one iteration at a time with per-kernel HIP-event
-    timing: (live tracks, summed kernel ms) of every iteration."""
+    timing: (live tracks, summed kernel ms) of every iteration, and the
+    track-steps the run took."""
     session.push(primaries)
     session.profile(emstep.role_mask(*emstep.KERNEL_ROLES))
     session.profile_read()
     out = []
+    steps0 = int(session.counters().get("steps", 0)) if hasattr(session, "counters") else None
+    steps = None
     try:
         for _ in range(max_iterations):
             c = session.step(1)
             prof = session.profile_read()
             out.append((int(c["alive"]), sum(v[0] for v in prof.values() if v[1] > 0)))
+            if steps0 is None:
+                steps0 = int(c.get("steps", 0))
+            steps = int(c.get("steps", 0))
             if c["alive"] == 0 and c["queued"] == 0 and c["pending_primaries"] == 0:
                 break
     finally:
         session.profile(0)
     session.release(events)
-    return out
+    return out, (steps or 0) - (steps0 or 0)
 
 
 def phase_table(session, sample, events):
     """Per sort point and occupancy bucket: reorder or run masked (step 4 of
-    the module docstring).  Returns the two bucket masks and the per-bucket
-    times of the four combinations."""
+    the module docstring).  Returns the two bucket masks and, per bucket, the
+    kernel time per live track of the four combinations.
+
+    Once the initializer queue holds more tracks than there are vacancies,
+    which of them take the free slots follows the order in which the
+    interactions appended them, and that order follows the slot order the
+    sort points produce: the live-track count of an iteration can differ
+    between the combinations while every track's history, and so the run's
+    total of track-steps, is the same.  Buckets are therefore compared by
+    kernel time per live track."""
     combos = {(1, 1): (ALL_BUCKETS, ALL_BUCKETS), (0, 1): (0, ALL_BUCKETS), (1, 0): (ALL_BUCKETS, 0), (0, 0): (0, 0)}
     per = {}
-    alive_ref = None
+    steps_ref = None
     for combo, masks in combos.items():
         session.set_tuning(phase_sort=masks)
-        rec = iteration_times(session, sample, events)
-        alive = [a for a, _ in rec]
-        if alive_ref is None:
-            alive_ref = alive
-        elif alive != alive_ref:
-            raise RuntimeError("live tracks per iteration differ between launch shapes")
-        t = {}
-        for a, ms in rec:
+        rec, steps = iteration_times(session, sample, events)
+        if steps_ref is None:
+            steps_ref = steps
+        elif steps != steps_ref:
+            raise RuntimeError(f"track-steps differ between launch shapes ({steps} against {steps_ref})")
+        ms, tracks = {}, {}
+        for a, t in rec:
             if a > 0:
                 b = a.bit_length() - 1
-                t[b] = t.get(b, 0.0) + ms
-        per[combo] = t
+                ms[b] = ms.get(b, 0.0) + t
+                tracks[b] = tracks.get(b, 0) + a
+        per[combo] = {b: ms[b] / tracks[b] for b in ms}
     m1 = m2 = 0
     buckets = sorted(set().union(*[set(t) for t in per.values()]))
     choice = {}
@@ -119,7 +133,7 @@ def phase_table(session, sample, events):
     m1 |= ALL_BUCKETS & ~seen
     m2 |= ALL_BUCKETS & ~seen
     return (m1, m2), {"choice": {str(b): list(c) for b, c in choice.items()},
-                      "ms": {f"{k[0]}{k[1]}": {str(b): v for b, v in t.items()} for k, t in per.items()}}
+                      "ms_per_track": {f"{k[0]}{k[1]}": {str(b): v for b, v in t.items()} for k, t in per.items()}}
 
 
 def autotune(session, sample, policies=("none", "partition", "radix", "queue"),

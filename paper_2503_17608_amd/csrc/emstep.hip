@@ -1144,15 +1144,26 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
     bool have_done = false;
     bool finished = false;
     int in_flight = 0;
+    // tracks alive, queued or pending in the latest snapshot and in the one
+    // before it
+    uint64_t left = UINT64_MAX, left_before = UINT64_MAX;
+    bool draining = false;
     while (!finished) {
         if (launched < max_iterations) {
-            // below the drain threshold (as of the latest snapshot) the rest
-            // of the work is drained, one drain iteration at a time
-            uint64_t left = have_done ? (uint64_t)done.n_alive + done.queue_size + (done.prim_end - done.prim_next)
-                                      : UINT64_MAX;
-            if (c->drain_threshold > 0 && left < c->drain_threshold) {
-                uint64_t want = align_up(std::max<uint64_t>(2 * left, 256), 256);
-                launch_drain_any(c, (uint32_t)std::min<uint64_t>(want, c->L.drain_threads));
+            // the rest of the work is drained, one drain iteration at a time,
+            // once the latest snapshot shows fewer tracks than the threshold
+            // and no more than the snapshot before it (the tail of the run,
+            // not the ramp of one that starts with few tracks), until a
+            // snapshot shows the threshold reached again; the largest
+            // threshold drains every iteration from the first
+            const bool below = c->drain_threshold > 0 && left < c->drain_threshold;
+            draining = c->drain_threshold == UINT32_MAX || (below && (draining || left <= left_before));
+            if (draining) {
+                // two threads per track left (half of a block's threads own
+                // vacant slots); before the first snapshot, all of them
+                const uint64_t cap = c->L.drain_threads;
+                const uint64_t want = left >= cap ? cap : align_up(std::max<uint64_t>(2 * left, 256), 256);
+                launch_drain_any(c, (uint32_t)std::min<uint64_t>(want, cap));
                 launch_completions(c);
                 HIP_TRY(hipGetLastError());
                 launched += 1;
@@ -1171,6 +1182,9 @@ ems_status ems_run(ems_ctx* c, uint64_t max_iterations, ems_counters* out)
             int slot = (int)((seq - in_flight) % c->snap_slots);
             HIP_TRY(hipEventSynchronize(c->snap_ev[slot]));
             done = c->snap[slot];
+            // the first snapshot has none before it: no drain decision yet
+            left_before = have_done ? left : 0;
+            left = (uint64_t)done.n_alive + done.queue_size + (done.prim_end - done.prim_next);
             have_done = true;
             --in_flight;
             if (done.overflow) {

@@ -22,11 +22,14 @@ import numpy as np
 from .serving import split_events
 
 
-def run_event_parallel(sessions, primaries, chunk_events=64, keep_results=True):
+def run_event_parallel(sessions, primaries, chunk_events=64, keep_results=True, chunk_log=None):
     """Transport `primaries` with one host thread per session.
 
     Returns (edep: {event: per-slab array}, ledger: {event: record}, steps, wall seconds).
-    Each session needs max_events >= chunk_events."""
+    Each session needs max_events >= chunk_events.  With a list as
+    `chunk_log`, one record per chunk is appended to it: the session, the
+    chunk's start and end (seconds from the start of the call), the seconds
+    spent in push, run and release, and its iterations and track-steps."""
     events = split_events(primaries)
     chunks = [events[i:i + chunk_events] for i in range(0, len(events), chunk_events)]
     lock = threading.Lock()
@@ -37,7 +40,8 @@ def run_event_parallel(sessions, primaries, chunk_events=64, keep_results=True):
 
     def worker(k):
         s = sessions[k]
-        c0 = s.counters()["steps"]
+        prev = s.counters()
+        c0 = prev["steps"]
         try:
             while True:
                 with lock:
@@ -46,14 +50,24 @@ def run_event_parallel(sessions, primaries, chunk_events=64, keep_results=True):
                     chunk = chunks[next_chunk[0]]
                     next_chunk[0] += 1
                 ev = np.array([e for e, _ in chunk], dtype=np.uint64)
+                ta = time.perf_counter()
                 s.push(np.concatenate([p for _, p in chunk]))
-                s.run()
+                tb = time.perf_counter()
+                c = s.run()
+                tc = time.perf_counter()
                 if keep_results:
                     e, led = s.tallies_by_event(ev)
                     for i, x in enumerate(ev):
                         edep[int(x)] = e[i]
                         ledger[int(x)] = led[i]
                 s.release(ev)
+                td = time.perf_counter()
+                if chunk_log is not None:
+                    with lock:
+                        chunk_log.append({"session": k, "start": ta - t0, "end": td - t0, "push_s": tb - ta,
+                                          "run_s": tc - tb, "release_s": td - tc, "iterations": int(c["iterations"] - prev["iterations"]),
+                                          "steps": int(c["steps"] - prev["steps"])})
+                prev = c
         except Exception as exc:          # surfaced to the caller below
             errors.append(exc)
         steps[k] = s.counters()["steps"] - c0

@@ -342,16 +342,16 @@ def test_drain_mode_matches_step_loop_and_oracle(precision):
     results: every track is stepped by the same per-track code with the same
     keyed random numbers, whatever the threshold, the per-launch round budget
     (small budgets stop blocks mid-shower and hand their stacks back) or the
-    slot count.  Draining from the start (threshold 2^30) puts whole 1 GeV
-    showers into one block, so its stack overflows into the initializer
-    buffer."""
+    slot count.  Draining from the first iteration (threshold 0xFFFFFFFF)
+    puts whole 1 GeV showers into one block, so its stack overflows into the
+    initializer buffer; the other thresholds start the drain in the tail."""
     w = workloads.electron_showers_1gev_field(30, n_slots=1 << 15)
     ref_e, ref_l, ref_c = _run_lib(w, precision=precision, sort_policy="partition", graph_iterations=4)
     if precision == "f64":
         e_or, l_or, steps = _run_oracle(w)
         assert ref_c["steps"] == steps
         assert _ledger_equal_int(ref_l, l_or) is None
-    for thr, budget, slots in [(1 << 30, 4096, 1 << 15), (4000, 3, 1 << 15), (20000, 64, 5000), (1000, 100000, 1 << 16)]:
+    for thr, budget, slots in [(0xFFFFFFFF, 4096, 1 << 15), (4000, 3, 1 << 15), (20000, 64, 5000), (1000, 100000, 1 << 16)]:
         s = session_for(w, n_slots=slots, precision=precision, sort_policy="partition", graph_iterations=4)
         s.set_tuning(drain_threshold=thr, drain_steps=budget)
         s.push(w.primaries)

@@ -291,3 +291,35 @@ def test_phase_table_reorders_each_sort_point_where_it_pays():
         assert (m1 >> b) & 1 == want1 and (m2 >> b) & 1 == want2, (a, info["choice"])
     # buckets the sample never reached keep reordering
     assert (m1 >> 30) & 1 and (m2 >> 30) & 1 and (m1 >> 0) & 1
+
+
+class ShiftedPhaseSession(PhaseSession):
+    """Live-track counts that depend on the phase table (which queued tracks
+    take the free slots follows the slot order) while the run's total of
+    track-steps does not."""
+
+    def step(self, n):
+        c = super().step(n)
+        a = c["alive"]
+        if a and not (self.masks[0] & 1):
+            c["alive"] = a + (1 if self.i % 2 else -1)
+        c["steps"] = self.steps_total
+        return c
+
+    steps_total = 1000
+
+
+def test_phase_table_accepts_live_counts_that_follow_the_slot_order():
+    s = ShiftedPhaseSession()
+    (m1, m2), info = autotune.phase_table(s, np.zeros(1), np.zeros(1, dtype=np.uint64))
+    assert set(info["ms_per_track"]) == {"11", "01", "10", "00"}
+
+
+def test_phase_table_rejects_runs_whose_track_steps_differ():
+    class Drifting(ShiftedPhaseSession):
+        def step(self, n):
+            c = super().step(n)
+            c["steps"] = self.steps_total + (self.masks[1] & 1) * self.i
+            return c
+    with pytest.raises(RuntimeError, match="track-steps differ"):
+        autotune.phase_table(Drifting(), np.zeros(1), np.zeros(1, dtype=np.uint64))
