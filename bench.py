@@ -140,7 +140,7 @@ def committed_traffic(kernel, key):
 
 
 WORKLOADS = ("electron_showers_1gev_field", "small_electron_showers", "mixed_cone_showers",
-             "batched_mixed_events", "serving_events")
+             "batched_mixed_events", "serving_events", "lhc_like_events")
 
 
 def parse():
@@ -186,6 +186,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against total track slots (2^14..2^23), mixed-event and event-parallel")
     ap.add_argument("--sweep-exp", type=int, nargs=2, default=[14, 23], help="slot exponents of the sweep")
+    ap.add_argument("--sweep-k", type=int, nargs="*", default=[2, 4, 8], help="event-parallel session counts")
+    ap.add_argument("--initializers", type=int, default=0,
+                    help="initializer records per session in the sweep (0 = max(16 x slots, 2^24))")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size three times (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -236,39 +239,41 @@ def run_variant(w, args, precision, policy, init_partition, prof_kernel, tune=No
                 n_initializers=None):
     s = new_session(w, args, precision, policy, init_partition, drain=drain, reuse=reuse, fuse=fuse,
                     n_initializers=n_initializers)
-    events = np.unique(w.primaries["event"])
-    tuned = None
-    if tune is not None:
-        tuned = tune(s)
-    for _ in range(args.warmup):
-        time_batch(s, w.primaries, events)
-        s.release(events)
-    c0 = s.counters()
-    total_t = 0.0
-    iters = 0
-    for k in range(args.steps):
-        c_before = s.counters()
-        c, dt = time_batch(s, w.primaries, events)
-        total_t += dt
-        iters += c["iterations"] - c_before["iterations"]
-        if k + 1 < args.steps or prof_kernel:
+    try:
+        events = np.unique(w.primaries["event"])
+        tuned = None
+        if tune is not None:
+            tuned = tune(s)
+        for _ in range(args.warmup):
+            time_batch(s, w.primaries, events)
             s.release(events)
-    c1 = s.counters()
-    prof = {}
-    work_prof = {}
-    if prof_kernel:
-        # one more pass over the same batch with HIP events around the kernel
-        from paper_2503_17608_amd import emstep
-        s.profile(emstep.role_mask(prof_kernel))
-        s.profile_read()
-        cp0 = s.counters()
-        time_batch(s, w.primaries, events)
-        cp1 = s.counters()
-        prof = s.profile_read()
-        s.profile(0)
-        work_prof = {k: cp1["work"][k] - cp0["work"][k] for k in cp1["work"]}
-    edep, led = s.tallies_by_event(events)
-    s.close()
+        c0 = s.counters()
+        total_t = 0.0
+        iters = 0
+        for k in range(args.steps):
+            c_before = s.counters()
+            c, dt = time_batch(s, w.primaries, events)
+            total_t += dt
+            iters += c["iterations"] - c_before["iterations"]
+            if k + 1 < args.steps or prof_kernel:
+                s.release(events)
+        c1 = s.counters()
+        prof = {}
+        work_prof = {}
+        if prof_kernel:
+            # one more pass over the same batch with HIP events around the kernel
+            from paper_2503_17608_amd import emstep
+            s.profile(emstep.role_mask(prof_kernel))
+            s.profile_read()
+            cp0 = s.counters()
+            time_batch(s, w.primaries, events)
+            cp1 = s.counters()
+            prof = s.profile_read()
+            s.profile(0)
+            work_prof = {k: cp1["work"][k] - cp0["work"][k] for k in cp1["work"]}
+        edep, led = s.tallies_by_event(events)
+    finally:
+        s.close()
     steps = c1["steps"] - c0["steps"]
     work = {k: c1["work"][k] - c0["work"][k] for k in c1["work"]}
     return {"steps": steps, "seconds": total_t, "iterations": iters, "work": work, "prof": prof,
@@ -320,7 +325,7 @@ def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
     sessions = []
     for _ in range(k):
         s = emstep.Session(max(w.n_slots // k, 1024), precision=precision, max_events=chunk, max_slabs=st.n_slabs,
-                           n_initializers=max(16 * (w.n_slots // k), 1 << 23),
+                           n_initializers=getattr(args, "initializers", 0) or max(16 * (w.n_slots // k), 1 << 23),
                            max_materials=len(st.materials), seed=w.seed, sort_policy=args.policy,
                            max_substeps=args.max_substeps, graph_iterations=args.graph, lds_tables=args.lds_tables,
                            streams=1, stream=torch.cuda.Stream(), n_primaries=max(len(w.primaries), 1 << 16))
@@ -330,17 +335,19 @@ def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
         s.set_tuning(drain_threshold=drain_for(args, w.n_slots // k), drain_steps=args.drain_steps,
                      fuse_interactions=bool(args.fuse_interactions))
         sessions.append(s)
-    multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)     # warm-up
     best = None
     log = []
-    for _ in range(repeats):
-        torch.cuda.synchronize()
-        log = []
-        _, _, steps, wall = multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False,
-                                                           chunk_log=log)
-        best = steps / wall if best is None else max(best, steps / wall)
-    for s in sessions:
-        s.close()
+    try:
+        multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False)     # warm-up
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            log = []
+            _, _, steps, wall = multistream.run_event_parallel(sessions, w.primaries, chunk, keep_results=False,
+                                                               chunk_log=log)
+            best = steps / wall if best is None else max(best, steps / wall)
+    finally:
+        for s in sessions:
+            s.close()
     if details:
         n = max(len(log), 1)
         return best, {"sessions": k, "chunk_events": chunk, "chunks": len(log),
@@ -610,14 +617,21 @@ def sweep_mode(args):
         t0 = time.perf_counter()
         # few slots hold back many secondaries: the initializer buffer is
         # sized for the whole workload's peak, not for the slots
-        r = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=drain_for(args, n),
-                        n_initializers=max(16 * n, 1 << 24))
-        row = {"slots": n, "mixed": r["steps"] / r["seconds"],
-               "mixed_iterations_per_batch": r["iterations"] // args.steps}
-        for k in (2, 4, 8):
+        from paper_2503_17608_amd.emstep import EmsError
+        row = {"slots": n}
+        try:
+            r = run_variant(w, args, precision, args.policy, args.init_partition, None, drain=drain_for(args, n),
+                            n_initializers=args.initializers or max(16 * n, 1 << 24))
+            row.update({"mixed": r["steps"] / r["seconds"], "mixed_iterations_per_batch": r["iterations"] // args.steps})
+        except EmsError as e:          # e.g. more secondaries waiting than the initializer buffer holds
+            row["mixed_error"] = str(e)
+        for k in args.sweep_k:
             if n // k >= 1024:
-                row[f"event_parallel_{k}"], row[f"event_parallel_{k}_detail"] = event_parallel_rate(
-                    w, args, precision, k, repeats=1, details=True)
+                try:
+                    row[f"event_parallel_{k}"], row[f"event_parallel_{k}_detail"] = event_parallel_rate(
+                        w, args, precision, k, repeats=1, details=True)
+                except EmsError as e:
+                    row[f"event_parallel_{k}_error"] = str(e)
         row["wall_s"] = time.perf_counter() - t0
         print(json.dumps(row), flush=True)
         rows.append(row)

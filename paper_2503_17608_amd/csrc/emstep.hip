@@ -51,6 +51,7 @@ ems_status fail(ems_status s, const std::string& msg)
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 constexpr uint64_t kStagingCap = 1 << 16;   // primaries / row registrations per host-to-device copy
+constexpr uint32_t kMaxCounterCopies = 64;   // copies of the per-event counters (a power of two)
 
 // a new event row: {event id, row, registration generation}
 struct RowReg {
@@ -63,7 +64,8 @@ struct Layout {
     uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
-    uint64_t drain_stack, regs, x0, rowsum;
+    uint64_t drain_stack, regs, x0, rowsum, ledger_out;
+    uint32_t n_rep, ledger_rs, live_rs;   // copies of the per-event counters, rows per copy
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads; 8 stack records each)
     uint64_t total;
@@ -121,8 +123,15 @@ Layout make_layout(const ems_options& o)
     L.smat = take(4 * (uint64_t)o.max_slabs);
     L.row_event = take(8 * (uint64_t)o.max_events);
     L.edep = take(8 * (uint64_t)o.max_events * o.max_slabs);
-    L.ledger = take(sizeof(Ledger) * (uint64_t)o.max_events);
-    L.live = take(4 * (uint64_t)o.max_events);
+    // per-event counters in up to 64 copies (each copy's rows padded to whole
+    // 4 KiB pages), fewer when the copies would exceed 64 MiB
+    L.ledger_rs = (uint32_t)align_up((uint64_t)o.max_events, 64);     // 64 x 72 B = 4.5 KiB
+    L.live_rs = (uint32_t)align_up((uint64_t)o.max_events, 1024);     // 1024 x 4 B = 4 KiB
+    L.n_rep = kMaxCounterCopies;
+    while (L.n_rep > 1 && (uint64_t)L.n_rep * (sizeof(Ledger) * L.ledger_rs + 4ull * L.live_rs) > (64ull << 20))
+        L.n_rep >>= 1;
+    L.ledger = take(sizeof(Ledger) * (uint64_t)L.ledger_rs * L.n_rep);
+    L.live = take(4ull * L.live_rs * L.n_rep);
     L.done_ring = take(8 * (uint64_t)o.max_events);
     L.row_gen = take(4 * (uint64_t)o.max_events);
     L.row_state = take(4 * (uint64_t)o.max_events);
@@ -133,6 +142,7 @@ Layout make_layout(const ems_options& o)
     L.drain_threads = (uint32_t)std::min<uint64_t>(kDrainThreadsMax, align_up(n, 256));
     L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
     L.regs = take(sizeof(RowReg) * kStagingCap);
+    L.ledger_out = take(sizeof(Ledger) * (uint64_t)o.max_events);
     L.x0 = take(8ull * o.max_materials);
     L.total = off;
     return L;
@@ -269,6 +279,9 @@ Dev<R> make_dev(const ems_ctx* c)
     d.ledger = (Ledger*)(b + L.ledger);
     d.edep_stride = (int)c->opt.max_slabs;
     d.live = (unsigned int*)(b + L.live);
+    d.rep_mask = L.n_rep - 1;
+    d.ledger_rs = L.ledger_rs;
+    d.live_rs = L.live_rs;
     d.done_ring = (unsigned long long*)(b + L.done_ring);
     d.row_gen = (const unsigned int*)(b + L.row_gen);
     d.row_state = (unsigned int*)(b + L.row_state);
@@ -310,27 +323,52 @@ __global__ void k_reset_queue(Counters* c)
 }
 
 // A batch of registrations {event, row, generation}: one block per row.
+// Every copy of the row's ledger and live count is cleared.
 __global__ void k_set_rows(const RowReg* regs, uint64_t* row_event, double* edep, Ledger* led, uint32_t n_slabs,
-                           unsigned int* live, unsigned int* row_gen, unsigned int* row_state)
+                           unsigned int* live, unsigned int* row_gen, unsigned int* row_state, uint32_t n_rep,
+                           uint32_t ledger_rs, uint32_t live_rs)
 {
     const RowReg g = regs[blockIdx.x];
     for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)g.row * n_slabs + i] = 0.0;
+    for (uint32_t r = threadIdx.x; r < n_rep; r += blockDim.x) {
+        led[(size_t)r * ledger_rs + g.row] = Ledger{};
+        live[(size_t)r * live_rs + g.row] = 0u;
+    }
     if (threadIdx.x == 0) {
         row_event[g.row] = g.ev;
-        led[g.row] = Ledger{};
-        live[g.row] = 0u;
         row_gen[g.row] = g.gen;
         row_state[g.row] = g.ev != UINT64_MAX ? 1u : 0u;
     }
 }
 
-// pushed primaries count toward their event until they retire
+// pushed primaries count toward their event until they retire (thread i
+// adds to copy i mod n_rep of the live count)
 __global__ void k_count_primaries(const Initializer* prims, uint64_t cap, uint64_t start, uint64_t n,
-                                  unsigned int* live)
+                                  unsigned int* live, uint32_t rep_mask, uint32_t live_rs)
 {
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    atomicAdd(&live[prims[(start + i) % cap].row], 1u);
+    atomicAdd(&live[(size_t)(i & rep_mask) * live_rs + prims[(start + i) % cap].row], 1u);
+}
+
+// Sum the copies of the ledgers of rows [row0, row0 + n) into out[0, n).
+__global__ void k_ledger_sum(const Ledger* led, uint32_t n_rep, uint32_t ledger_rs, uint32_t row0, uint32_t n,
+                             Ledger* out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Ledger s{};
+    for (uint32_t r = 0; r < n_rep; ++r) {
+        const Ledger& l = led[(size_t)r * ledger_rs + row0 + i];
+        s.escaped += l.escaped;
+        s.n_pair += l.n_pair;
+        s.n_annih += l.n_annih;
+        s.steps += l.steps;
+        for (int t = 0; t < 3; ++t) s.n_sec[t] += l.n_sec[t];
+        s.n_guard += l.n_guard;
+        s.n_reject_cap += l.n_reject_cap;
+    }
+    out[i] = s;
 }
 
 // Sum each row of the per-block partial counters: block w sums row w.
@@ -710,7 +748,7 @@ __global__ void k_inject(Dev<R> d, const ems_track* t, uint64_t n)
         return;
     }
     const ems_track& r = t[i];
-    atomicAdd(&d.live[r.row], 1u);
+    atomicAdd(live_of(d, r.row), 1u);
     d.type[i] = (uint8_t)r.type;
     d.action[i] = A_IDLE;
     d.flags[i] = 0;
@@ -799,7 +837,7 @@ ems_status flush_rows(ems_ctx* c)
                            (uint64_t*)(c->ws + c->L.row_event), (double*)(c->ws + c->L.edep),
                            (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs,
                            (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen),
-                           (unsigned int*)(c->ws + c->L.row_state));
+                           (unsigned int*)(c->ws + c->L.row_state), c->L.n_rep, c->L.ledger_rs, c->L.live_rs);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->staging_ev, c->stream));
         c->staging_busy = true;
@@ -1096,7 +1134,8 @@ ems_status ems_push_primaries(ems_ctx* c, const ems_primary* p, uint64_t n)
         HIP_TRY(hipEventRecord(c->staging_ev, c->stream));
         c->staging_busy = true;
         hipLaunchKernelGGL(k_count_primaries, dim3((chunk + 255) / 256), dim3(256), 0, c->stream, (const Initializer*)dst,
-                           cap, c->prim_end, chunk, (unsigned int*)(c->ws + c->L.live));
+                           cap, c->prim_end, chunk, (unsigned int*)(c->ws + c->L.live), c->L.n_rep - 1,
+                           c->L.live_rs);
         HIP_TRY(hipGetLastError());
         c->prim_end += chunk;
         done += chunk;
@@ -1268,9 +1307,12 @@ ems_status ems_read_edep(ems_ctx* c, uint64_t event, double* per_slab, uint32_t 
         HIP_TRY(hipMemcpyAsync(per_slab, c->ws + c->L.edep + 8ull * row * c->opt.max_slabs, 8ull * c->n_slabs,
                                hipMemcpyDeviceToHost, c->stream));
     }
-    if (ledger)
-        HIP_TRY(hipMemcpyAsync(ledger, c->ws + c->L.ledger + sizeof(Ledger) * row, sizeof(Ledger),
-                               hipMemcpyDeviceToHost, c->stream));
+    if (ledger) {
+        hipLaunchKernelGGL(k_ledger_sum, dim3(1), dim3(64), 0, c->stream, (const Ledger*)(c->ws + c->L.ledger),
+                           c->L.n_rep, c->L.ledger_rs, row, 1u, (Ledger*)(c->ws + c->L.ledger_out));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(ledger, c->ws + c->L.ledger_out, sizeof(Ledger), hipMemcpyDeviceToHost, c->stream));
+    }
     HIP_TRY(hipStreamSynchronize(c->stream));
     return EMS_OK;
 }
@@ -1288,8 +1330,14 @@ ems_status ems_read_all_tallies(ems_ctx* c, double* edep, ems_ledger* ledgers, u
         for (uint64_t r = 0; r < rows; ++r)
             std::memcpy(edep + r * c->n_slabs, tmp.data() + r * c->opt.max_slabs, 8ull * c->n_slabs);
     }
-    if (ledgers)
-        HIP_TRY(hipMemcpyAsync(ledgers, c->ws + c->L.ledger, sizeof(Ledger) * rows, hipMemcpyDeviceToHost, c->stream));
+    if (ledgers) {
+        hipLaunchKernelGGL(k_ledger_sum, dim3((uint32_t)((rows + 255) / 256)), dim3(256), 0, c->stream,
+                           (const Ledger*)(c->ws + c->L.ledger), c->L.n_rep, c->L.ledger_rs, 0u, (uint32_t)rows,
+                           (Ledger*)(c->ws + c->L.ledger_out));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(ledgers, c->ws + c->L.ledger_out, sizeof(Ledger) * rows, hipMemcpyDeviceToHost,
+                               c->stream));
+    }
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (row_event) std::memcpy(row_event, c->row_event.data(), 8ull * rows);
     return EMS_OK;

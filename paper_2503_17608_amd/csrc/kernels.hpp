@@ -59,11 +59,14 @@ struct Dev {
     uint64_t seed;
     const uint64_t* row_event;
     double* edep;           // [rows][edep_stride]
-    Ledger* ledger;
+    Ledger* ledger;         // [n_rep][ledger_rs] (copies of the per-event ledger, summed by readers)
     unsigned long long* part;   // per-block partial counters [kNumW][part_stride] (no global atomics)
     unsigned int part_stride;
     unsigned int* row_state;    // 1 while an event occupies the row and has not been reported complete
-    unsigned int* live;     // per row: primaries pending + tracks alive or queued
+    unsigned int* live;     // [n_rep][live_rs]; per row, summed over the copies: primaries pending +
+                            // tracks alive or queued
+    unsigned int rep_mask;  // n_rep - 1 (n_rep a power of two)
+    unsigned int ledger_rs, live_rs;   // rows per copy (padded to 4 KiB pages)
     unsigned long long* done_ring;  // completed events as (generation << 32 | row), capacity rows
     const unsigned int* row_gen;    // registration generation of each row
     unsigned int n_rows;
@@ -145,12 +148,35 @@ __device__ __forceinline__ void flush_count_shared(const Dev<R>& d, int role, un
     if (threadIdx.x == 0 && t) atomicAdd(&d.part[(size_t)role * d.part_stride + blockIdx.x], t);
 }
 
+// Per-event counters (the ledger and the live count) are kept in n_rep
+// copies, each in pages of its own: a thread adds to the copy of its global
+// index.  An event with many tracks in flight would otherwise funnel every
+// retirement, secondary and step count of a launch into a few addresses,
+// whose device-scope atomics are performed one after another; spread over
+// the copies they proceed in parallel.  Readers sum the copies.
+__device__ __forceinline__ uint32_t rep_index(uint32_t mask)
+{
+    return (blockIdx.x * blockDim.x + threadIdx.x) & mask;
+}
+
+template <class R>
+__device__ __forceinline__ Ledger& ledger_of(const Dev<R>& d, uint32_t row)
+{
+    return d.ledger[(size_t)rep_index(d.rep_mask) * d.ledger_rs + row];
+}
+
+template <class R>
+__device__ __forceinline__ unsigned int* live_of(const Dev<R>& d, uint32_t row)
+{
+    return d.live + (size_t)rep_index(d.rep_mask) * d.live_rs + row;
+}
+
 // A retired track leaves its event (no-return atomic); completion is detected
 // after the iteration by the row scan.
 template <class R>
 __device__ __forceinline__ void leave_event(const Dev<R>& d, bool retired, uint32_t row)
 {
-    if (retired) atomicSub(&d.live[row], 1u);
+    if (retired) atomicSub(live_of(d, row), 1u);
 }
 
 // Queue policy: append slot s to the list of action `key` (lanes with act set).
@@ -404,7 +430,7 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
     __shared__ unsigned long long bbase;
     const int n = sb.n;
     if (__syncthreads_count(n) == 0) {           // block-uniform
-        if (retiring) atomicSub(&d.live[row], 1u);
+        if (retiring) atomicSub(live_of(d, row), 1u);
         return;
     }
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -447,11 +473,11 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
         n_ele += v.type == kElectron;
         n_pos += v.type == kPositron;
     });
-    if (n_gam) atomicAdd(&d.ledger[row].n_sec[kGamma], (unsigned long long)n_gam);
-    if (n_ele) atomicAdd(&d.ledger[row].n_sec[kElectron], (unsigned long long)n_ele);
-    if (n_pos) atomicAdd(&d.ledger[row].n_sec[kPositron], (unsigned long long)n_pos);
+    if (n_gam) atomicAdd(&ledger_of(d, row).n_sec[kGamma], (unsigned long long)n_gam);
+    if (n_ele) atomicAdd(&ledger_of(d, row).n_sec[kElectron], (unsigned long long)n_ele);
+    if (n_pos) atomicAdd(&ledger_of(d, row).n_sec[kPositron], (unsigned long long)n_pos);
     const int dlive = (int)(n_gam + n_ele + n_pos) - (retiring ? 1 : 0);
-    if (dlive != 0) atomicAdd(&d.live[row], (unsigned int)dlive);    // modulo 2^32: a decrement for -1
+    if (dlive != 0) atomicAdd(live_of(d, row), (unsigned int)dlive);    // modulo 2^32: a decrement for -1
     __syncthreads();                                  // wtot / bbase are reused by the next trip
 }
 
@@ -459,9 +485,9 @@ template <class R>
 __device__ __forceinline__ void record_tally(const Dev<R>& d, uint32_t row, int slab, const StepTally& tl)
 {
     if (tl.edep != 0.0) atomicAdd(&d.edep[(size_t)row * d.edep_stride + slab], tl.edep);
-    if (tl.n_pair) atomicAdd(&d.ledger[row].n_pair, (unsigned long long)tl.n_pair);
-    if (tl.n_annih) atomicAdd(&d.ledger[row].n_annih, (unsigned long long)tl.n_annih);
-    if (tl.capped) atomicAdd(&d.ledger[row].n_reject_cap, 1ull);
+    if (tl.n_pair) atomicAdd(&ledger_of(d, row).n_pair, (unsigned long long)tl.n_pair);
+    if (tl.n_annih) atomicAdd(&ledger_of(d, row).n_annih, (unsigned long long)tl.n_annih);
+    if (tl.capped) atomicAdd(&ledger_of(d, row).n_reject_cap, 1ull);
 }
 
 // a track finishes: free its slot and add its steps to the event ledger (the
@@ -471,7 +497,7 @@ __device__ __forceinline__ void retire(const Dev<R>& d, uint32_t s, uint32_t row
 {
     d.type[s] = kDead;
     d.action[s] = A_NONE;
-    atomicAdd(&d.ledger[row].steps, (unsigned long long)steps);
+    atomicAdd(&ledger_of(d, row).steps, (unsigned long long)steps);
 }
 
 // Parent-slot reuse: a track that ended in this step hands its slot to its
@@ -494,8 +520,8 @@ __device__ __forceinline__ uint32_t reuse_slot(const Dev<R>& d, uint32_t s, SecB
     rec.type = (uint8_t)v.type;
     rec.pad = 0;
     init_slot(d, s, rec);
-    atomicAdd(&d.ledger[row].n_sec[v.type], 1ull);
-    atomicAdd(&d.live[row], 1u);
+    atomicAdd(&ledger_of(d, row).n_sec[v.type], 1ull);
+    atomicAdd(live_of(d, row), 1u);
     sb.s0 = sb.s1;
     sb.s1 = sb.s2;
     sb.n -= 1;
@@ -669,7 +695,7 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
         else if (face == F_ZHI) next = slab + 1;
         else next = -1;
         if (next < 0 || next >= d.n_slabs) {
-            atomicAdd(&d.ledger[row].escaped, (double)T);
+            atomicAdd(&ledger_of(d, row).escaped, (double)T);
             alive = false;
             next_action = A_NONE;
         } else {
@@ -712,7 +738,7 @@ __device__ __forceinline__ void finish_along(const Dev<R>& d, const Tables<R>& t
     if (alive && step > kMaxSteps && next_action == A_IDLE) {
         // step guard: the track stops after this (counted) step; a positron
         // annihilates at rest with the counted step's index
-        atomicAdd(&d.ledger[row].n_guard, 1ull);
+        atomicAdd(&ledger_of(d, row).n_guard, 1ull);
         if (typ == kGamma) {
             tl.edep += (double)T;
             T = R(0);
@@ -1178,7 +1204,7 @@ __device__ __forceinline__ void interact_track(const Dev<R>& d, uint32_t s, SecB
     uint32_t steps = (PROC == P_ANNIH && (fl & F_COUNTED)) ? p.step : p.step + 1;
     d.step[s] = steps;
     if (p.alive && steps > kMaxSteps) {
-        atomicAdd(&d.ledger[row].n_guard, 1ull);
+        atomicAdd(&ledger_of(d, row).n_guard, 1ull);
         p.step = steps;
         if (p.type != kGamma) stop_lepton<R>(pp, p, sb, tl);
         else { tl.edep += (double)p.T; p.alive = false; }
@@ -1330,7 +1356,7 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
 {
     // the event's counters change once per track, as in append_secondaries
     const int dlive = sb.n - (retiring ? 1 : 0);
-    if (dlive != 0) atomicAdd(&d.live[row], (unsigned int)dlive);    // modulo 2^32: a decrement for -1
+    if (dlive != 0) atomicAdd(live_of(d, row), (unsigned int)dlive);    // modulo 2^32: a decrement for -1
     if (sb.n == 0) return;
     const int pos = atomicAdd(top, sb.n);
     unsigned int n_gam = 0, n_ele = 0, n_pos = 0;
@@ -1355,9 +1381,9 @@ __device__ __forceinline__ void drain_push(const Dev<R>& d, const SecBuf<R>& sb,
             else atomicOr(&d.ctr->overflow, 1u);
         }
     });
-    if (n_gam) atomicAdd(&d.ledger[row].n_sec[kGamma], (unsigned long long)n_gam);
-    if (n_ele) atomicAdd(&d.ledger[row].n_sec[kElectron], (unsigned long long)n_ele);
-    if (n_pos) atomicAdd(&d.ledger[row].n_sec[kPositron], (unsigned long long)n_pos);
+    if (n_gam) atomicAdd(&ledger_of(d, row).n_sec[kGamma], (unsigned long long)n_gam);
+    if (n_ele) atomicAdd(&ledger_of(d, row).n_sec[kElectron], (unsigned long long)n_ele);
+    if (n_pos) atomicAdd(&ledger_of(d, row).n_sec[kPositron], (unsigned long long)n_pos);
 }
 
 // Exclusive rank of a true flag among the block's threads, and their total.
@@ -1487,7 +1513,9 @@ __global__ void k_scan_completions(Dev<R> d)
 {
     uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= d.n_rows) return;
-    if (d.row_state[row] == 1u && d.live[row] == 0u) {
+    unsigned int live = 0;          // modulo 2^32: a copy can hold a net decrement
+    for (uint32_t r = 0; r <= d.rep_mask; ++r) live += d.live[(size_t)r * d.live_rs + row];
+    if (d.row_state[row] == 1u && live == 0u) {
         d.row_state[row] = 0u;
         unsigned int k = atomicAdd(&d.ctr->done_count, 1u);
         d.done_ring[k % d.n_rows] = ((unsigned long long)d.row_gen[row] << 32) | row;

@@ -163,6 +163,15 @@ def batched_mixed_events(n_events: int = 64, seed: int = 1, n_slots: int = 1 << 
                     make_primaries(seed, n_events, (1, 500), "mixed", (10.0, 100000.0)), n_slots)
 
 
+def lhc_like_events(n_events: int = 16, seed: int = 1, n_slots: int = 1 << 21, per_event: int = 1300,
+                    energy_mev: float = 10000.0) -> Workload:
+    """16 events of 1300 e- at 10 GeV each (the event size of the paper's benchmark problems: the energy
+    an LHC collision deposits), +z; 50-layer stack, 1 T, 0.1 MeV cut, FP64."""
+    st = sampling_stack(50, 40.0, (1.0, 0.0, 0.0))
+    return Workload(f"pb_lar50_{n_events}ev_{per_event}e{energy_mev / 1000:g}GeV_B1T", st, 0.1, seed, n_events,
+                    make_primaries(seed, n_events, per_event, ELECTRON, energy_mev), n_slots)
+
+
 def poisson_arrival_times(seed: int, rate_hz: float, n: int) -> np.ndarray:
     """Arrival times of n events at Poisson rate: key (seed, 2^64-1), counter (k, 0, 0, 3)."""
     t = 0.0
