@@ -188,7 +188,8 @@ def parse():
     ap.add_argument("--sweep-exp", type=int, nargs=2, default=[14, 23], help="slot exponents of the sweep")
     ap.add_argument("--sweep-k", type=int, nargs="*", default=[2, 4, 8], help="event-parallel session counts")
     ap.add_argument("--initializers", type=int, default=0,
-                    help="initializer records per session in the sweep (0 = max(16 x slots, 2^24))")
+                    help="initializer records of the mixed-event session in the sweep, shared out among the "
+                         "event-parallel sessions (0 = max(16 x slots, 2^24))")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size three times (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -325,7 +326,7 @@ def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
     sessions = []
     for _ in range(k):
         s = emstep.Session(max(w.n_slots // k, 1024), precision=precision, max_events=chunk, max_slabs=st.n_slabs,
-                           n_initializers=getattr(args, "initializers", 0) or max(16 * (w.n_slots // k), 1 << 23),
+                           n_initializers=max(getattr(args, "initializers", 0) // k, 16 * (w.n_slots // k), 1 << 23),
                            max_materials=len(st.materials), seed=w.seed, sort_policy=args.policy,
                            max_substeps=args.max_substeps, graph_iterations=args.graph, lds_tables=args.lds_tables,
                            streams=1, stream=torch.cuda.Stream(), n_primaries=max(len(w.primaries), 1 << 16))

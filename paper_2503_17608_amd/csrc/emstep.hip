@@ -66,6 +66,8 @@ struct Layout {
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
     uint64_t drain_stack, regs, x0, rowsum, ledger_out;
     uint32_t n_rep, ledger_rs, live_rs;   // copies of the per-event counters, rows per copy
+    uint32_t n_rep_e;                      // copies of the deposit tallies
+    uint64_t edep_rs, edep_out;            // doubles per copy; summed tallies for readers
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads; 8 stack records each)
     uint64_t total;
@@ -122,7 +124,16 @@ Layout make_layout(const ems_options& o)
     L.zp = take(8 * ((uint64_t)o.max_slabs + 1));
     L.smat = take(4 * (uint64_t)o.max_slabs);
     L.row_event = take(8 * (uint64_t)o.max_events);
-    L.edep = take(8 * (uint64_t)o.max_events * o.max_slabs);
+    // deposit tallies in copies (page-padded): about one tally address per
+    // track slot, at most 64 copies and 64 MiB.  Many events over many slabs
+    // spread their deposits by themselves (one copy); a few large events put
+    // thousands of tracks on each of their slabs
+    L.edep_rs = align_up((uint64_t)o.max_events * o.max_slabs, 512);   // 512 x 8 B = 4 KiB
+    L.n_rep_e = 1;
+    while (L.n_rep_e < kMaxCounterCopies && 2ull * L.n_rep_e * o.max_events * o.max_slabs <= o.n_slots &&
+           8ull * L.edep_rs * 2 * L.n_rep_e <= (64ull << 20))
+        L.n_rep_e <<= 1;
+    L.edep = take(8ull * L.edep_rs * L.n_rep_e);
     // per-event counters in up to 64 copies (each copy's rows padded to whole
     // 4 KiB pages), fewer when the copies would exceed 64 MiB
     L.ledger_rs = (uint32_t)align_up((uint64_t)o.max_events, 64);     // 64 x 72 B = 4.5 KiB
@@ -143,6 +154,7 @@ Layout make_layout(const ems_options& o)
     L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
     L.regs = take(sizeof(RowReg) * kStagingCap);
     L.ledger_out = take(sizeof(Ledger) * (uint64_t)o.max_events);
+    L.edep_out = take(8ull * o.max_events * o.max_slabs);
     L.x0 = take(8ull * o.max_materials);
     L.total = off;
     return L;
@@ -278,6 +290,8 @@ Dev<R> make_dev(const ems_ctx* c)
     d.edep = (double*)(b + L.edep);
     d.ledger = (Ledger*)(b + L.ledger);
     d.edep_stride = (int)c->opt.max_slabs;
+    d.edep_rep_mask = L.n_rep_e - 1;
+    d.edep_rs = L.edep_rs;
     d.live = (unsigned int*)(b + L.live);
     d.rep_mask = L.n_rep - 1;
     d.ledger_rs = L.ledger_rs;
@@ -326,10 +340,11 @@ __global__ void k_reset_queue(Counters* c)
 // Every copy of the row's ledger and live count is cleared.
 __global__ void k_set_rows(const RowReg* regs, uint64_t* row_event, double* edep, Ledger* led, uint32_t n_slabs,
                            unsigned int* live, unsigned int* row_gen, unsigned int* row_state, uint32_t n_rep,
-                           uint32_t ledger_rs, uint32_t live_rs)
+                           uint32_t ledger_rs, uint32_t live_rs, uint32_t n_rep_e, uint64_t edep_rs)
 {
     const RowReg g = regs[blockIdx.x];
-    for (uint32_t i = threadIdx.x; i < n_slabs; i += blockDim.x) edep[(size_t)g.row * n_slabs + i] = 0.0;
+    for (uint32_t i = threadIdx.x; i < n_slabs * n_rep_e; i += blockDim.x)
+        edep[(size_t)(i / n_slabs) * edep_rs + (size_t)g.row * n_slabs + i % n_slabs] = 0.0;
     for (uint32_t r = threadIdx.x; r < n_rep; r += blockDim.x) {
         led[(size_t)r * ledger_rs + g.row] = Ledger{};
         live[(size_t)r * live_rs + g.row] = 0u;
@@ -349,6 +364,19 @@ __global__ void k_count_primaries(const Initializer* prims, uint64_t cap, uint64
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     atomicAdd(&live[(size_t)(i & rep_mask) * live_rs + prims[(start + i) % cap].row], 1u);
+}
+
+// Sum the copies of the deposit tallies of rows [row0, row0 + n) (stride
+// n_slabs doubles) into out[0, n * n_slabs).
+__global__ void k_edep_sum(const double* edep, uint32_t n_rep, uint64_t edep_rs, uint32_t n_slabs, uint32_t row0,
+                           uint32_t n, double* out)
+{
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)n * n_slabs) return;
+    const uint64_t at = (uint64_t)row0 * n_slabs + i;
+    double v = 0.0;
+    for (uint32_t r = 0; r < n_rep; ++r) v += edep[r * edep_rs + at];
+    out[i] = v;
 }
 
 // Sum the copies of the ledgers of rows [row0, row0 + n) into out[0, n).
@@ -837,7 +865,8 @@ ems_status flush_rows(ems_ctx* c)
                            (uint64_t*)(c->ws + c->L.row_event), (double*)(c->ws + c->L.edep),
                            (Ledger*)(c->ws + c->L.ledger), (uint32_t)c->opt.max_slabs,
                            (unsigned int*)(c->ws + c->L.live), (unsigned int*)(c->ws + c->L.row_gen),
-                           (unsigned int*)(c->ws + c->L.row_state), c->L.n_rep, c->L.ledger_rs, c->L.live_rs);
+                           (unsigned int*)(c->ws + c->L.row_state), c->L.n_rep, c->L.ledger_rs, c->L.live_rs,
+                           c->L.n_rep_e, c->L.edep_rs);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->staging_ev, c->stream));
         c->staging_busy = true;
@@ -1304,8 +1333,11 @@ ems_status ems_read_edep(ems_ctx* c, uint64_t event, double* per_slab, uint32_t 
     uint32_t row = it->second;
     if (per_slab) {
         if (n_slabs < c->n_slabs) return fail(EMS_ERR_INVALID_ARG, "per_slab too small");
-        HIP_TRY(hipMemcpyAsync(per_slab, c->ws + c->L.edep + 8ull * row * c->opt.max_slabs, 8ull * c->n_slabs,
-                               hipMemcpyDeviceToHost, c->stream));
+        const uint32_t ms = (uint32_t)c->opt.max_slabs;
+        hipLaunchKernelGGL(k_edep_sum, dim3((ms + 255) / 256), dim3(256), 0, c->stream, (const double*)(c->ws + c->L.edep),
+                           c->L.n_rep_e, c->L.edep_rs, ms, row, 1u, (double*)(c->ws + c->L.edep_out));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(per_slab, c->ws + c->L.edep_out, 8ull * c->n_slabs, hipMemcpyDeviceToHost, c->stream));
     }
     if (ledger) {
         hipLaunchKernelGGL(k_ledger_sum, dim3(1), dim3(64), 0, c->stream, (const Ledger*)(c->ws + c->L.ledger),
@@ -1324,7 +1356,12 @@ ems_status ems_read_all_tallies(ems_ctx* c, double* edep, ems_ledger* ledgers, u
     if (edep) {
         // rows are stored with stride max_slabs; return them with stride n_slabs
         std::vector<double> tmp(rows * c->opt.max_slabs);
-        HIP_TRY(hipMemcpyAsync(tmp.data(), c->ws + c->L.edep, 8ull * rows * c->opt.max_slabs, hipMemcpyDeviceToHost,
+        const uint32_t ms = (uint32_t)c->opt.max_slabs;
+        hipLaunchKernelGGL(k_edep_sum, dim3((uint32_t)((rows * ms + 255) / 256)), dim3(256), 0, c->stream,
+                           (const double*)(c->ws + c->L.edep), c->L.n_rep_e, c->L.edep_rs, ms, 0u, (uint32_t)rows,
+                           (double*)(c->ws + c->L.edep_out));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(tmp.data(), c->ws + c->L.edep_out, 8ull * rows * c->opt.max_slabs, hipMemcpyDeviceToHost,
                                c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         for (uint64_t r = 0; r < rows; ++r)

@@ -58,7 +58,7 @@ struct Dev {
     double ecut;
     uint64_t seed;
     const uint64_t* row_event;
-    double* edep;           // [rows][edep_stride]
+    double* edep;           // [n_rep_e][edep_rs] copies of [rows][edep_stride], summed by readers
     Ledger* ledger;         // [n_rep][ledger_rs] (copies of the per-event ledger, summed by readers)
     unsigned long long* part;   // per-block partial counters [kNumW][part_stride] (no global atomics)
     unsigned int part_stride;
@@ -71,6 +71,8 @@ struct Dev {
     const unsigned int* row_gen;    // registration generation of each row
     unsigned int n_rows;
     int edep_stride;
+    unsigned int edep_rep_mask;   // copies of the deposit tallies - 1 (a power of two)
+    unsigned long long edep_rs;   // doubles per copy (padded to 4 KiB pages)
     int max_substeps;
     int sorted;             // along-step kernels: 0 masked over all slots, 1 sorted permutation ranges
     int sorted2;            // interaction kernels: 0 masked, 1 sorted ranges, 2 lists filled by the along-step
@@ -148,9 +150,9 @@ __device__ __forceinline__ void flush_count_shared(const Dev<R>& d, int role, un
     if (threadIdx.x == 0 && t) atomicAdd(&d.part[(size_t)role * d.part_stride + blockIdx.x], t);
 }
 
-// Per-event counters (the ledger and the live count) are kept in n_rep
-// copies, each in pages of its own: a thread adds to the copy of its global
-// index.  An event with many tracks in flight would otherwise funnel every
+// Per-event counters (the ledger and the live count) and the deposit tallies
+// are kept in several copies, each in pages of its own: a thread adds to the
+// copy of its global index.  An event with many tracks in flight would otherwise funnel every
 // retirement, secondary and step count of a launch into a few addresses,
 // whose device-scope atomics are performed one after another; spread over
 // the copies they proceed in parallel.  Readers sum the copies.
@@ -484,7 +486,9 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
 template <class R>
 __device__ __forceinline__ void record_tally(const Dev<R>& d, uint32_t row, int slab, const StepTally& tl)
 {
-    if (tl.edep != 0.0) atomicAdd(&d.edep[(size_t)row * d.edep_stride + slab], tl.edep);
+    if (tl.edep != 0.0)
+        atomicAdd(&d.edep[(size_t)rep_index(d.edep_rep_mask) * d.edep_rs + (size_t)row * d.edep_stride + slab],
+                  tl.edep);
     if (tl.n_pair) atomicAdd(&ledger_of(d, row).n_pair, (unsigned long long)tl.n_pair);
     if (tl.n_annih) atomicAdd(&ledger_of(d, row).n_annih, (unsigned long long)tl.n_annih);
     if (tl.capped) atomicAdd(&ledger_of(d, row).n_reject_cap, 1ull);
