@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 6u
+#define EMS_ABI_VERSION 7u
 
 typedef enum {
     EMS_OK = 0,
@@ -90,7 +90,7 @@ typedef enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 } ems_particle;
 typedef struct {
     uint32_t abi_version;      /* must be EMS_ABI_VERSION */
     int32_t precision;         /* ems_precision: FP64, or FP32 energies/directions/tables with FP64 positions */
-    uint64_t n_slots;          /* track slots (threads of the state arrays), in [1, 2^30) */
+    uint64_t n_slots;          /* track slots (threads of the state arrays), in [1, 2^30] */
     uint64_t n_initializers;   /* capacity of the secondary initializer buffer */
     uint64_t n_primaries;      /* capacity of the pending-primary buffer */
     uint32_t max_events;       /* tally rows (events resident at once) */
@@ -118,6 +118,16 @@ typedef struct {
                                   by multiple scattering: Rayleigh-distributed space angle of Highland
                                   width at the pre-step energy, uniform azimuth (Philox domain 5);
                                   0: no scattering (the physics of the benchmark workloads) */
+    int32_t deterministic;     /* 1: secondaries enter the initializer buffer in the order of the
+                                  interacting tracks (their positions in the sort permutation, or
+                                  their slots when unsorted) instead of the order in which blocks
+                                  reach the buffer, so the buffer contents, the slots the fill assigns
+                                  and every integer of the state repeat exactly from run to run; the
+                                  interaction kernels stage up to 3 records per slot (240 B per slot
+                                  more workspace) and two kernels append them after the interactions.
+                                  The queue policy (its lists) and the drain (its block-local stacks)
+                                  append out of order: they are rejected.  0: block-aggregated appends
+                                  (paper: "Stepping algorithm", the deterministic fill of vacancies) */
 } ems_options;
 
 typedef struct { double Z, A, density, I_eV; } ems_material;
@@ -398,6 +408,8 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * boundaries) instead of seven launches on the library's streams; kernel role
  * "interactions" in the block table.
 
+ * With ems_options.deterministic set, the queue policy and a drain threshold
+ * above 0 are rejected (EMS_ERR_INVALID_ARG).
  * Setting the tuning re-captures graphs on the next run.
  * Paper: "Reindexing track slots" (sort policy, tail threshold, phase
  * table); "Partitioning

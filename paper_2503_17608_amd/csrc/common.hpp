@@ -110,6 +110,7 @@ struct Counters {
     unsigned int alive_before;         // live tracks found by the vacancy pass (before the fill)
     unsigned int done_count;           // events completed so far (entries written to the ring)
     unsigned int phase_sorted;         // reordering this iteration: bit 0 sort point 1, bit 1 sort point 2
+    unsigned long long sec_base;       // deterministic appends: buffer size before this iteration's appends
 };
 
 // work counter indices

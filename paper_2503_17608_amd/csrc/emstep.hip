@@ -68,6 +68,7 @@ struct Layout {
     uint32_t n_rep, ledger_rs, live_rs;   // copies of the per-event counters, rows per copy
     uint32_t n_rep_e;                      // copies of the deposit tallies
     uint64_t edep_rs, edep_out;            // doubles per copy; summed tallies for readers
+    uint64_t sec_cnt, sec_blk, sec_rec;    // deterministic appends (staging; 0 when off)
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads; 8 stack records each)
     uint64_t total;
@@ -134,13 +135,17 @@ Layout make_layout(const ems_options& o)
            8ull * L.edep_rs * 2 * L.n_rep_e <= (64ull << 20))
         L.n_rep_e <<= 1;
     L.edep = take(8ull * L.edep_rs * L.n_rep_e);
-    // per-event counters in up to 64 copies (each copy's rows padded to whole
-    // 4 KiB pages), fewer when the copies would exceed 64 MiB
+    // per-event counters in copies (each copy's rows padded to whole 4 KiB
+    // pages): one copy per 64 track slots per event row, at most 64 copies
+    // and 64 MiB.  Many events share the slots' updates by themselves (one
+    // copy for 10^4 events in 2^20 slots); a few large events put 10^5
+    // tracks on each row
     L.ledger_rs = (uint32_t)align_up((uint64_t)o.max_events, 64);     // 64 x 72 B = 4.5 KiB
     L.live_rs = (uint32_t)align_up((uint64_t)o.max_events, 1024);     // 1024 x 4 B = 4 KiB
-    L.n_rep = kMaxCounterCopies;
-    while (L.n_rep > 1 && (uint64_t)L.n_rep * (sizeof(Ledger) * L.ledger_rs + 4ull * L.live_rs) > (64ull << 20))
-        L.n_rep >>= 1;
+    L.n_rep = 1;
+    while (L.n_rep < kMaxCounterCopies && 2ull * L.n_rep * o.max_events * 64 <= o.n_slots &&
+           2ull * L.n_rep * (sizeof(Ledger) * L.ledger_rs + 4ull * L.live_rs) <= (64ull << 20))
+        L.n_rep <<= 1;
     L.ledger = take(sizeof(Ledger) * (uint64_t)L.ledger_rs * L.n_rep);
     L.live = take(4ull * L.live_rs * L.n_rep);
     L.done_ring = take(8 * (uint64_t)o.max_events);
@@ -154,6 +159,11 @@ Layout make_layout(const ems_options& o)
     L.drain_stack = take(sizeof(Initializer) * kDrainDepth * (uint64_t)L.drain_threads);
     L.regs = take(sizeof(RowReg) * kStagingCap);
     L.ledger_out = take(sizeof(Ledger) * (uint64_t)o.max_events);
+    if (o.deterministic) {
+        L.sec_cnt = take(n);
+        L.sec_blk = take(4 * nvb);
+        L.sec_rec = take(sizeof(Initializer) * 3 * n);
+    }
     L.edep_out = take(8ull * o.max_events * o.max_slabs);
     L.x0 = take(8ull * o.max_materials);
     L.total = off;
@@ -311,6 +321,10 @@ Dev<R> make_dev(const ems_ctx* c)
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.msc = c->opt.msc ? 1 : 0;
+    d.det = c->opt.deterministic ? 1 : 0;
+    d.sec_cnt = c->opt.deterministic ? (uint8_t*)(b + L.sec_cnt) : nullptr;
+    d.sec_blk = c->opt.deterministic ? (uint32_t*)(b + L.sec_blk) : nullptr;
+    d.sec_rec = c->opt.deterministic ? (Initializer*)(b + L.sec_rec) : nullptr;
     d.x0 = (const double*)(c->ws + c->L.x0);
     d.n_tab = (int)(c->n_materials * kTabPerMat * kNodes);
     return d;
@@ -546,6 +560,34 @@ uint32_t field_grid(ems_ctx* c, uint32_t g, int bs, size_t lds)
     return c->field_grid_resident[k] < g ? c->field_grid_resident[k] : g;
 }
 
+// The interaction kernels of an iteration: one fused launch, or seven on
+// the library's streams.
+template <class R, bool DET>
+void launch_interactions(ems_ctx* c, const Dev<R>& d, Launcher& ln, int nw)
+{
+    const int bs_def = c->opt.block_size > 0 ? c->opt.block_size : 256;
+    const uint32_t n = d.n_slots;
+    auto B = [&](int role) { return c->block[role] > 0 ? c->block[role] : bs_def; };
+    auto G = [&](int role) { return grid_for(n, B(role)); };
+    hipStream_t st = c->stream;
+    if (c->fuse_interactions) {
+        // all seven actions in one launch over the combined index range
+        ln.one(R_INTERACT_ALL, k_interact_all<R, DET>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
+        return;
+    }
+    // seven independent branches spread over the streams
+    if (nw > 0) fork(c, 1, nw);
+    auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
+    ln.one(R_COMPTON, k_interact<R, P_COMPTON, DET>, dim3(G(R_COMPTON)), dim3(B(R_COMPTON)), 0, on(0), d);
+    ln.one(R_PHOTO, k_interact<R, P_PHOTO, DET>, dim3(G(R_PHOTO)), dim3(B(R_PHOTO)), 0, on(1), d);
+    ln.one(R_PAIR, k_interact<R, P_PAIR, DET>, dim3(G(R_PAIR)), dim3(B(R_PAIR)), 0, on(2), d);
+    ln.one(R_MOLLER, k_interact<R, P_MOLLER, DET>, dim3(G(R_MOLLER)), dim3(B(R_MOLLER)), 0, on(3), d);
+    ln.one(R_BHABHA, k_interact<R, P_BHABHA, DET>, dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d);
+    ln.one(R_BREMS, k_interact<R, P_BREMS, DET>, dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d);
+    ln.one(R_ANNIH, k_interact<R, P_ANNIH, DET>, dim3(G(R_ANNIH)), dim3(B(R_ANNIH)), 0, on(6), d);
+    if (nw > 0) join(c, 1, nw);
+}
+
 template <class R>
 void launch_iteration(ems_ctx* c, bool no_init, bool prof)
 {
@@ -587,22 +629,13 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
                st, d);
     if (nw > 0) join(c, 0, 1);
     if (d.sorted2 == 1) launch_sort<R>(c, d, ln, 0);
-    if (c->fuse_interactions) {
-        // all seven actions in one launch over the combined index range
-        ln.one(R_INTERACT_ALL, k_interact_all<R>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
-        return;
+    if (d.det) launch_interactions<R, true>(c, d, ln, nw);
+    else launch_interactions<R, false>(c, d, ln, nw);
+    if (d.det) {
+        // deterministic appends: the staged secondaries in interaction order
+        ln.k(R_INIT, true, false, k_sec_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+        ln.k(R_INIT, false, true, k_sec_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
     }
-    // interactions: seven independent branches spread over the streams
-    if (nw > 0) fork(c, 1, nw);
-    auto on = [&](int k) { return k % c->n_streams == 0 ? st : c->workers[k % c->n_streams - 1]; };
-    ln.one(R_COMPTON, k_interact<R, P_COMPTON>, dim3(G(R_COMPTON)), dim3(B(R_COMPTON)), 0, on(0), d);
-    ln.one(R_PHOTO, k_interact<R, P_PHOTO>, dim3(G(R_PHOTO)), dim3(B(R_PHOTO)), 0, on(1), d);
-    ln.one(R_PAIR, k_interact<R, P_PAIR>, dim3(G(R_PAIR)), dim3(B(R_PAIR)), 0, on(2), d);
-    ln.one(R_MOLLER, k_interact<R, P_MOLLER>, dim3(G(R_MOLLER)), dim3(B(R_MOLLER)), 0, on(3), d);
-    ln.one(R_BHABHA, k_interact<R, P_BHABHA>, dim3(G(R_BHABHA)), dim3(B(R_BHABHA)), 0, on(4), d);
-    ln.one(R_BREMS, k_interact<R, P_BREMS>, dim3(G(R_BREMS)), dim3(B(R_BREMS)), 0, on(5), d);
-    ln.one(R_ANNIH, k_interact<R, P_ANNIH>, dim3(G(R_ANNIH)), dim3(B(R_ANNIH)), 0, on(6), d);
-    if (nw > 0) join(c, 1, nw);
 }
 
 void launch_iteration_any(ems_ctx* c, bool no_init, bool prof)
@@ -900,6 +933,9 @@ static ems_status validate(const ems_options* o)
     if (o->graph_iterations < 0) return fail(EMS_ERR_INVALID_ARG, "graph_iterations");
     if (o->streams < 0 || o->streams > 4) return fail(EMS_ERR_INVALID_ARG, "streams must be in [0, 4]");
     if (o->msc != 0 && o->msc != 1) return fail(EMS_ERR_INVALID_ARG, "msc must be 0 or 1");
+    if (o->deterministic != 0 && o->deterministic != 1) return fail(EMS_ERR_INVALID_ARG, "deterministic must be 0 or 1");
+    if (o->deterministic && o->sort_policy == EMS_SORT_QUEUE)
+        return fail(EMS_ERR_INVALID_ARG, "deterministic appends do not combine with the queue policy");
     return EMS_OK;
 }
 
@@ -965,6 +1001,9 @@ ems_status ems_create(const ems_options* opt, void* device_workspace, uint64_t b
                        (uint8_t*)(c->ws + L.row_event), (uint8_t)0xFF, 8ull * opt->max_events);
     hipLaunchKernelGGL(k_zero_bytes, dim3(grid_for(tb, 256)), dim3(256), 0, c->stream, (uint8_t*)(c->ws + L.edep),
                        L.incr - L.edep);
+    if (opt->deterministic)
+        hipLaunchKernelGGL(k_zero_bytes, dim3(grid_for(n, 256)), dim3(256), 0, c->stream,
+                           (uint8_t*)(c->ws + L.sec_cnt), n);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(EMS_ERR_DEVICE, "initial clear failed"));
     *out = c;
     return EMS_OK;
@@ -1589,6 +1628,8 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
             return fail(EMS_ERR_INVALID_ARG, "block sizes must be 0 or a multiple of 64 in [64, 512]");
     }
     if (t->drain_threshold > 0 && t->drain_steps == 0) return fail(EMS_ERR_INVALID_ARG, "drain_steps must be > 0");
+    if (c->opt.deterministic && (t->sort_policy == EMS_SORT_QUEUE || t->drain_threshold > 0))
+        return fail(EMS_ERR_INVALID_ARG, "deterministic appends do not combine with the queue policy or the drain");
     c->policy = t->sort_policy;
     c->tail_threshold = t->tail_threshold;
     c->phase_sort[0] = t->phase_sort[0];

@@ -84,6 +84,12 @@ struct Dev {
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
+    // deterministic appends: secondaries staged per position of the
+    // interaction order (up to 3 records each), appended in that order
+    int det;
+    uint8_t* sec_cnt;       // [n_slots] secondaries staged at a position (0 between iterations)
+    Initializer* sec_rec;   // [n_slots][3]
+    uint32_t* sec_blk;      // per block of kVacBlock positions: secondaries staged
     const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
@@ -296,6 +302,65 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
     }
 }
 
+// ---- deterministic appends --------------------------------------------------------
+// The interaction kernels staged each track's secondaries at its position in
+// the interaction order; these two kernels append them to the initializer
+// buffer in position order, so the buffer, and with it the slots the next
+// fill assigns, repeat exactly from run to run (the paper's deterministic
+// vacancy fill).  First the secondaries per block of positions; block 0 also
+// records the buffer size the appends start from.
+template <class R>
+__global__ void __launch_bounds__(kVacBlock) k_sec_count(Dev<R> d)
+{
+    __shared__ uint32_t red[kVacBlock / 64];
+    const uint32_t p = blockIdx.x * kVacBlock + threadIdx.x;
+    uint32_t c = p < d.n_slots ? d.sec_cnt[p] : 0u;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < kVacBlock / 64; ++i) t += red[i];
+        d.sec_blk[blockIdx.x] = t;
+        if (blockIdx.x == 0) d.ctr->sec_base = d.ctr->queue_size;
+    }
+}
+
+// Then each position's records go to sec_base + (secondaries staged at
+// earlier positions); the staging counts are cleared for the next iteration
+// and the last block sets the buffer size.
+template <class R>
+__global__ void __launch_bounds__(kVacBlock) k_sec_scatter(Dev<R> d)
+{
+    __shared__ uint32_t red[kVacBlock / 64];
+    __shared__ uint32_t wsum[kVacBlock / 64];
+    const uint32_t prefix = block_prefix(d.sec_blk, blockIdx.x, red);
+    const uint32_t p = blockIdx.x * kVacBlock + threadIdx.x;
+    const uint32_t c = p < d.n_slots ? d.sec_cnt[p] : 0u;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t off = prefix + (x - c);
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    const unsigned long long base = d.ctr->sec_base;
+    for (uint32_t k = 0; k < c; ++k) {
+        const unsigned long long q = base + off + k;
+        if (q < d.queue_cap) d.queue[q] = d.sec_rec[(size_t)p * 3 + k];
+        else atomicOr(&d.ctr->overflow, 1u);
+    }
+    if (c) d.sec_cnt[p] = 0;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        uint32_t blk = 0;
+        for (int i = 0; i < kVacBlock / 64; ++i) blk += wsum[i];
+        d.ctr->queue_size = base + prefix + blk;
+    }
+}
+
 template <class R>
 __device__ __forceinline__ const Initializer* taken(const Dev<R>& d, uint32_t i)
 {
@@ -425,12 +490,60 @@ __device__ __forceinline__ uint8_t along_action(const Dev<R>& d, uint32_t s)
 // cancel.  All threads of the block must call it (block-uniform control
 // flow).
 template <class R>
+__device__ __forceinline__ Initializer secondary_record(const Sec<R>& v, const double r[3], uint32_t row,
+                                                       uint16_t slab)
+{
+    Initializer rec;
+    rec.T = (double)v.T;
+    rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
+    rec.u[0] = (double)v.ux; rec.u[1] = (double)v.uy; rec.u[2] = (double)v.uz;
+    rec.key = v.key;
+    rec.row = row;
+    rec.slab = slab;
+    rec.type = (uint8_t)v.type;
+    rec.pad = 0;
+    return rec;
+}
+
+// The event's counters for the secondaries of one track (and the track
+// itself when it ends in this step).
+template <class R>
+__device__ __forceinline__ void count_secondaries(const Dev<R>& d, uint32_t row, unsigned int n_gam,
+                                                  unsigned int n_ele, unsigned int n_pos, bool retiring)
+{
+    if (n_gam) atomicAdd(&ledger_of(d, row).n_sec[kGamma], (unsigned long long)n_gam);
+    if (n_ele) atomicAdd(&ledger_of(d, row).n_sec[kElectron], (unsigned long long)n_ele);
+    if (n_pos) atomicAdd(&ledger_of(d, row).n_sec[kPositron], (unsigned long long)n_pos);
+    const int dlive = (int)(n_gam + n_ele + n_pos) - (retiring ? 1 : 0);
+    if (dlive != 0) atomicAdd(live_of(d, row), (unsigned int)dlive);    // modulo 2^32: a decrement for -1
+}
+
+// `at` is the track's position in the interaction order of this iteration
+// (its index in the sort permutation, or its slot when unsorted): with
+// deterministic appends the secondaries are staged there and appended in
+// position order after the interaction kernels (k_sec_count,
+// k_sec_scatter); otherwise they go straight to the buffer, in an order that
+// depends on which blocks run first.  (DET is a template parameter so that
+// the default kernels compile without the staging path.)
+template <class R, bool DET>
 __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf<R>& sb, uint32_t row,
-                                                   uint16_t slab, const double r[3], bool retiring)
+                                                   uint16_t slab, const double r[3], bool retiring, uint32_t at)
 {
     __shared__ unsigned int wtot[16];
     __shared__ unsigned long long bbase;
     const int n = sb.n;
+    if (DET) {
+        unsigned int n_gam = 0, n_ele = 0, n_pos = 0;
+        sb.each([&](const Sec<R>& v, int k) {
+            d.sec_rec[(size_t)at * 3 + k] = secondary_record(v, r, row, slab);
+            n_gam += v.type == kGamma;
+            n_ele += v.type == kElectron;
+            n_pos += v.type == kPositron;
+        });
+        if (n) d.sec_cnt[at] = (uint8_t)n;
+        count_secondaries(d, row, n_gam, n_ele, n_pos, retiring);
+        return;
+    }
     if (__syncthreads_count(n) == 0) {           // block-uniform
         if (retiring) atomicSub(live_of(d, row), 1u);
         return;
@@ -461,25 +574,12 @@ __device__ __forceinline__ void append_secondaries(const Dev<R>& d, const SecBuf
             atomicOr(&d.ctr->overflow, 1u);
             return;
         }
-        Initializer rec;
-        rec.T = (double)v.T;
-        rec.r[0] = r[0]; rec.r[1] = r[1]; rec.r[2] = r[2];
-        rec.u[0] = (double)v.ux; rec.u[1] = (double)v.uy; rec.u[2] = (double)v.uz;
-        rec.key = v.key;
-        rec.row = row;
-        rec.slab = slab;
-        rec.type = (uint8_t)v.type;
-        rec.pad = 0;
-        d.queue[q] = rec;
+        d.queue[q] = secondary_record(v, r, row, slab);
         n_gam += v.type == kGamma;
         n_ele += v.type == kElectron;
         n_pos += v.type == kPositron;
     });
-    if (n_gam) atomicAdd(&ledger_of(d, row).n_sec[kGamma], (unsigned long long)n_gam);
-    if (n_ele) atomicAdd(&ledger_of(d, row).n_sec[kElectron], (unsigned long long)n_ele);
-    if (n_pos) atomicAdd(&ledger_of(d, row).n_sec[kPositron], (unsigned long long)n_pos);
-    const int dlive = (int)(n_gam + n_ele + n_pos) - (retiring ? 1 : 0);
-    if (dlive != 0) atomicAdd(live_of(d, row), (unsigned int)dlive);    // modulo 2^32: a decrement for -1
+    count_secondaries(d, row, n_gam, n_ele, n_pos, retiring);
     __syncthreads();                                  // wtot / bbase are reused by the next trip
 }
 
@@ -1226,7 +1326,7 @@ __device__ __forceinline__ void interact_track(const Dev<R>& d, uint32_t s, SecB
 }
 
 // ---- discrete interactions: one kernel per process ---------------------------------
-template <class R, int PROC>
+template <class R, int PROC, bool DET>
 __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
 {
     EMS_TRACK_RANGE(d, (uint8_t)(A_PROC0 + PROC))
@@ -1240,7 +1340,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
     uint32_t retired = 0;
     if (act) interact_track<R, PROC>(d, s, sb, r, row, slab, retired);
     if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
-    append_secondaries(d, sb, row, slab, r, retired != 0);
+    append_secondaries<R, DET>(d, sb, row, slab, r, retired != 0, _off + _i);
     ret_acc += retired;
     EMS_END_TRACKS
     flush_count(d, W_PROC0 + PROC, _work);
@@ -1256,7 +1356,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact(Dev<R> d)
 // range boundaries.  The per-track code is that of the per-process kernels;
 // the launch count per iteration drops from seven to one.  Unsorted, it masks
 // over all slots like the per-process kernels.
-template <class R>
+template <class R, bool DET>
 __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
 {
     const int mode = (d.ctr->phase_sorted & 2u) ? d.sorted2 : 0;
@@ -1323,7 +1423,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
             }
         }
         if (retired) reuse_acc += reuse_slot(d, s, sb, row, slab, r);
-        append_secondaries(d, sb, row, slab, r, retired != 0);
+        append_secondaries<R, DET>(d, sb, row, slab, r, retired != 0, off + i);
         ret_acc += retired;
     }
     flush_count(d, W_PROC0 + P_COMPTON, w0);

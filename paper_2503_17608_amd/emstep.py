@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 FP64, MIXED = 0, 1
 SORT_NONE, SORT_PARTITION, SORT_RADIX, SORT_QUEUE = 0, 1, 2, 3
 SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX, "queue": SORT_QUEUE}
@@ -41,7 +41,7 @@ class Options(C.Structure):
         ("max_events", C.c_uint32), ("max_slabs", C.c_uint32), ("max_materials", C.c_uint32),
         ("sort_policy", C.c_int32), ("init_partition", C.c_int32), ("max_substeps", C.c_int32),
         ("seed", C.c_uint64), ("block_size", C.c_int32), ("graph_iterations", C.c_int32),
-        ("lds_tables", C.c_int32), ("streams", C.c_int32), ("msc", C.c_int32),
+        ("lds_tables", C.c_int32), ("streams", C.c_int32), ("msc", C.c_int32), ("deterministic", C.c_int32),
     ]
 
 
@@ -150,7 +150,7 @@ class Session:
     def __init__(self, n_slots, precision="f64", n_initializers=None, n_primaries=None, max_events=1024,
                  max_slabs=128, max_materials=4, sort_policy="none", init_partition=False, max_substeps=10,
                  seed=1, block_size=0, graph_iterations=0, lds_tables=1, streams=4, device="cuda:0",
-                 stream=None, msc=False):
+                 stream=None, msc=False, deterministic=False):
         o = Options()
         o.abi_version = ABI_VERSION
         o.precision = MIXED if precision in ("mixed", "f32", MIXED) else FP64
@@ -169,6 +169,7 @@ class Session:
         o.lds_tables = int(lds_tables)
         o.streams = int(streams)
         o.msc = int(bool(msc))
+        o.deterministic = int(bool(deterministic))
         self.options = o
         nbytes = C.c_uint64(0)
         _check(_lib.ems_query_workspace(C.byref(o), C.byref(nbytes)), "ems_query_workspace")
