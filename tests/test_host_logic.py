@@ -235,8 +235,13 @@ def test_event_parallel_hands_out_every_chunk_once():
     sessions = [S(max_events=3) for _ in range(3)]
     events = _events(17)
     prims = np.concatenate([p for _, p in events])
-    edep, led, steps, wall = multistream.run_event_parallel(sessions, prims, chunk_events=3)
+    log = []
+    edep, led, steps, wall = multistream.run_event_parallel(sessions, prims, chunk_events=3, chunk_log=log)
     assert sorted(edep) == sorted(e for e, _ in events)
+    assert len(log) == (len(events) + 2) // 3
+    assert {r["session"] for r in log} <= {0, 1, 2}
+    assert sum(r["steps"] for r in log) == steps
+    assert all(0.0 <= r["start"] <= r["end"] <= wall + 1e-6 for r in log)
     assert sum(len(s.released) for s in sessions) == len(events)
     assert steps == sum(s.steps for s in sessions)
     for e, v in edep.items():
