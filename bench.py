@@ -164,6 +164,8 @@ def parse():
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")
+    ap.add_argument("--fuse-along", type=int, default=1,
+                    help="one launch for the photon and field along-steps (with a field and one stream)")
     ap.add_argument("--roofline-kernel", default="along_field")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-events", type=int, default=10000, help="oracle sample (events); 0 = skip")
@@ -222,7 +224,7 @@ def new_session(w, args, precision, policy, init_partition, graph=None, drain=No
     reuse = args.reuse_parent_slot if reuse is None else reuse
     fuse = args.fuse_interactions if fuse is None else fuse
     s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse),
-                 fuse_interactions=bool(fuse))
+                 fuse_interactions=bool(fuse), fuse_along=bool(args.fuse_along))
     return s
 
 
@@ -304,6 +306,11 @@ def cpu_baseline(w, n_events):
                             "sample": f"first {n1} events ({steps1} track-steps, {dt1:.2f} s)"}}
 
 
+def fused_along(args, w):
+    """Whether the photon and field along-steps run as one launch."""
+    return bool(args.fuse_along) and args.streams == 1 and any(b != 0.0 for b in w.stack.B)
+
+
 def drain_for(args, n_slots):
     """The drain threshold for a session of n_slots slots: the configured one
     at 2^20 slots and above, scaled with the slots below (a fixed threshold
@@ -334,7 +341,7 @@ def event_parallel_rate(w, args, precision, k, repeats=2, details=False):
         # the same tuning as the mixed-event run, the drain threshold scaled
         # to the session's slots
         s.set_tuning(drain_threshold=drain_for(args, w.n_slots // k), drain_steps=args.drain_steps,
-                     fuse_interactions=bool(args.fuse_interactions))
+                     fuse_interactions=bool(args.fuse_interactions), fuse_along=bool(args.fuse_along))
         sessions.append(s)
     best = None
     log = []
@@ -708,17 +715,22 @@ def main():
         out["config"]["autotuned"]["phase_choice"] = r["tuned"].get("phase_table", {}).get("choice")
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
-        tracks = r["work_prof"][prof_kernel]
+        # with fuse_along the field role's launch (k_along_both) also steps
+        # the photons: its bytes and tracks are both along-steps'
+        both = prof_kernel == "along_field" and fused_along(args, w)
+        parts = ("along_field", "along_neutral") if both else (prof_kernel,)
+        tracks = sum(r["work_prof"][k] for k in parts)
         avg_s = ms / 1e3 / launches
-        per_launch = kernel_bytes(prof_kernel, r["work_prof"], precision) / launches
+        per_launch = sum(kernel_bytes(k, r["work_prof"], precision) for k in parts) / launches
         bpt = per_launch * launches / max(tracks, 1)
         achieved = per_launch / avg_s / 1e9
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
                "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot,
-               "fuse_interactions": args.fuse_interactions}
-        t = committed_traffic(prof_kernel, key)
-        out["roofline"] = {"bound": "hbm", "kernel": prof_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+               "fuse_interactions": args.fuse_interactions, "fuse_along": int(both)}
+        label = "along_both" if both else prof_kernel
+        t = committed_traffic(label, key)
+        out["roofline"] = {"bound": "hbm", "kernel": label, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "traffic": t["bytes_per_launch"] if t else None,
                            "traffic_unit": "bytes/launch (calibrated FETCH_SIZE + WRITE_SIZE)",

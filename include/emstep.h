@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 7u
+#define EMS_ABI_VERSION 8u
 
 typedef enum {
     EMS_OK = 0,
@@ -407,6 +407,14 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * of the interaction actions (each wave holds one action except at range
  * boundaries) instead of seven launches on the library's streams; kernel role
  * "interactions" in the block table.
+ *
+ * fuse_along (0/1): with a field and one stream, run the photon and field
+ * along-steps as one launch (kernel role "along_field" in the block table and
+ * the profile): each thread of the resident grid steps its field tracks, then
+ * its share of the photon tracks, dealt out first to the waves that had one
+ * field round fewer, so the photon steps fill the end of the field launch.
+ * Without a field, or with several streams, it has no effect.  On by default
+ * (ems_create); the other knobs default to 0 / off.
 
  * With ems_options.deterministic set, the queue policy and a drain threshold
  * above 0 are rejected (EMS_ERR_INVALID_ARG).
@@ -424,6 +432,7 @@ typedef struct {
     uint32_t reuse_parent_slot;
     uint32_t fuse_interactions;
     uint32_t phase_sort[2];
+    uint32_t fuse_along;
 } ems_tuning;
 ems_status ems_set_tuning(ems_ctx* ctx, const ems_tuning* t);
 ems_status ems_get_tuning(ems_ctx* ctx, ems_tuning* t);

@@ -147,7 +147,7 @@ def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
             t = db[key]
             session.set_tuning(sort_policy=t["sort_policy"], tail_threshold=t["tail_threshold"], block=t["block"],
                                fuse_interactions=t.get("fuse_interactions", False),
-                               drain_threshold=t.get("drain_threshold", 0),
+                               drain_threshold=t.get("drain_threshold", 0), fuse_along=t.get("fuse_along", True),
                                phase_sort=t.get("phase_sort", (ALL_BUCKETS, ALL_BUCKETS)))
             return t
     events = np.unique(sample["event"])
@@ -197,25 +197,33 @@ def autotune(session, sample, policies=("none", "partition", "radix", "queue"),
         phase_masks, phase_info = phase_table(session, sample, events)
         say("phase table", phase_info.get("choice"))
     session.set_tuning(phase_sort=phase_masks)
-    # 5. interaction kernels fused or not, then the drain threshold
+    # 5. interaction kernels fused or not, the along-steps fused or not, then
+    # the drain threshold
     fuse_t = {}
     for f in (False, True):
         session.set_tuning(fuse_interactions=f, drain_threshold=0)
         fuse_t[f] = min(_run(session, sample, events) for _ in range(repeats))
     best_fuse = min(fuse_t, key=fuse_t.get)
+    along_t = {}
+    for f in (False, True):
+        session.set_tuning(fuse_interactions=best_fuse, fuse_along=f, drain_threshold=0)
+        along_t[f] = min(_run(session, sample, events) for _ in range(repeats))
+    best_along = min(along_t, key=along_t.get)
     drain_t = {}
     for dth in drains:
-        session.set_tuning(fuse_interactions=best_fuse, drain_threshold=dth)
+        session.set_tuning(fuse_interactions=best_fuse, fuse_along=best_along, drain_threshold=dth)
         drain_t[dth] = min(_run(session, sample, events) for _ in range(repeats))
     best_drain = min(drain_t, key=drain_t.get)
-    say("fuse", fuse_t, "drain", drain_t)
+    say("fuse", fuse_t, "fuse along", along_t, "drain", drain_t)
     session.set_tuning(sort_policy=best_policy, tail_threshold=best_th, block=best_block,
-                       fuse_interactions=best_fuse, drain_threshold=best_drain, phase_sort=phase_masks)
+                       fuse_interactions=best_fuse, fuse_along=best_along, drain_threshold=best_drain,
+                       phase_sort=phase_masks)
     result = {"sort_policy": best_policy, "tail_threshold": int(best_th), "block": best_block,
-              "fuse_interactions": bool(best_fuse), "drain_threshold": int(best_drain),
+              "fuse_interactions": bool(best_fuse), "fuse_along": bool(best_along), "drain_threshold": int(best_drain),
               "phase_sort": [int(phase_masks[0]), int(phase_masks[1])], "phase_table": phase_info,
               "policy_seconds": pol_t, "threshold_seconds": {str(k): v for k, v in th_t.items()},
               "fuse_seconds": {str(k): v for k, v in fuse_t.items()},
+              "fuse_along_seconds": {str(k): v for k, v in along_t.items()},
               "drain_seconds": {str(k): v for k, v in drain_t.items()},
               "block_ms": {r: {str(b): v for b, v in d.items()} for r, d in per_role.items()}}
     if cache and key:

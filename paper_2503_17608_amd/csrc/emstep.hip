@@ -228,14 +228,15 @@ struct ems_ctx {
     int policy = 0;
     uint32_t tail_threshold = 0;
     // resident-grid cache of the field along-step, per precision (FP64, FP32)
-    int field_grid_bs[2] = {0, 0};
-    size_t field_grid_lds[2] = {0, 0};
-    uint32_t field_grid_resident[2] = {0, 0};
+    int field_grid_bs[4] = {0, 0, 0, 0};          // [FP64, FP32] x [field kernel, both along-steps]
+    size_t field_grid_lds[4] = {0, 0, 0, 0};
+    uint32_t field_grid_resident[4] = {0, 0, 0, 0};
     uint32_t phase_sort[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
     uint32_t reuse_parent = 0;        // parent-slot reuse for the first secondary
     uint32_t fuse_interactions = 0;   // one launch for the seven interaction kernels
+    uint32_t fuse_along = 1;          // one launch for the photon and field along-steps
     int block[16] = {0};
     // profiling
     uint32_t prof_mask = 0;
@@ -541,16 +542,17 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, int km)
 // one resident round 2.97e9 track-steps/s, two 2.90e9, the slot-covering
 // grid (one track per thread) 2.84e9.
 template <class R>
-uint32_t field_grid(ems_ctx* c, uint32_t g, int bs, size_t lds)
+uint32_t field_grid(ems_ctx* c, uint32_t g, int bs, size_t lds, bool both)
 {
-    const int k = sizeof(R) == 8 ? 0 : 1;
+    const int k = (sizeof(R) == 8 ? 0 : 1) + (both ? 2 : 0);
     if (c->field_grid_bs[k] != bs || c->field_grid_lds[k] != lds) {
         int nb = 0, cus = 0, dev = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_along_field<R>), bs,
-                                                         lds) != hipSuccess ||
+        const void* kern = both ? reinterpret_cast<const void*>(k_along_both<R>)
+                                : reinterpret_cast<const void*>(k_along_field<R>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, bs, lds) != hipSuccess ||
             nb < 1)
             nb = 1;
         c->field_grid_resident[k] = (uint32_t)(nb * cus);
@@ -613,21 +615,29 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
     // (the along-step kernels run the pre-step of their tracks)
     if (d.sorted == 1) launch_sort<R>(c, d, ln, 2);
-    // along-step: photons and leptons are independent branches
+    // along-step: photons and leptons are independent branches, or one
+    // launch for both in a field on one stream (tuning fuse_along)
     const int nw = c->n_streams - 1;
-    hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
-    if (nw > 0) fork(c, 0, 1);
-    ln.one(R_ALONG_NEUTRAL, k_along_straight<R, false>, dim3(G(R_ALONG_NEUTRAL)), dim3(B(R_ALONG_NEUTRAL)), lds,
-           s_neutral, d);
-    if (d.has_field)
-        ln.one(R_ALONG_FIELD, k_along_field<R>,
+    if (d.has_field && c->fuse_along && nw == 0) {
+        ln.one(R_ALONG_FIELD, k_along_both<R>,
                dim3(c->policy == EMS_SORT_NONE ? G(R_ALONG_FIELD)
-                                               : field_grid<R>(c, G(R_ALONG_FIELD), B(R_ALONG_FIELD), lds)),
+                                               : field_grid<R>(c, G(R_ALONG_FIELD), B(R_ALONG_FIELD), lds, true)),
                dim3(B(R_ALONG_FIELD)), lds, st, d);
-    else
-        ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)), lds,
-               st, d);
-    if (nw > 0) join(c, 0, 1);
+    } else {
+        hipStream_t s_neutral = nw > 0 ? c->workers[0] : st;
+        if (nw > 0) fork(c, 0, 1);
+        ln.one(R_ALONG_NEUTRAL, k_along_straight<R, false>, dim3(G(R_ALONG_NEUTRAL)), dim3(B(R_ALONG_NEUTRAL)), lds,
+               s_neutral, d);
+        if (d.has_field)
+            ln.one(R_ALONG_FIELD, k_along_field<R>,
+                   dim3(c->policy == EMS_SORT_NONE ? G(R_ALONG_FIELD)
+                                                   : field_grid<R>(c, G(R_ALONG_FIELD), B(R_ALONG_FIELD), lds, false)),
+                   dim3(B(R_ALONG_FIELD)), lds, st, d);
+        else
+            ln.one(R_ALONG_CHARGED, k_along_straight<R, true>, dim3(G(R_ALONG_CHARGED)), dim3(B(R_ALONG_CHARGED)),
+                   lds, st, d);
+        if (nw > 0) join(c, 0, 1);
+    }
     if (d.sorted2 == 1) launch_sort<R>(c, d, ln, 0);
     if (d.det) launch_interactions<R, true>(c, d, ln, nw);
     else launch_interactions<R, false>(c, d, ln, nw);
@@ -1638,6 +1648,7 @@ ems_status ems_set_tuning(ems_ctx* c, const ems_tuning* t)
     c->drain_steps = t->drain_steps;
     c->reuse_parent = t->reuse_parent_slot ? 1u : 0u;
     c->fuse_interactions = t->fuse_interactions ? 1u : 0u;
+    c->fuse_along = t->fuse_along ? 1u : 0u;
     for (int i = 0; i < 16; ++i) c->block[i] = t->block[i];
     return drop_graph(c);
 }
@@ -1651,6 +1662,7 @@ ems_status ems_get_tuning(ems_ctx* c, ems_tuning* t)
     t->drain_steps = c->drain_steps;
     t->reuse_parent_slot = c->reuse_parent;
     t->fuse_interactions = c->fuse_interactions;
+    t->fuse_along = c->fuse_along;
     t->phase_sort[0] = c->phase_sort[0];
     t->phase_sort[1] = c->phase_sort[1];
     for (int i = 0; i < 16; ++i) t->block[i] = c->block[i];

@@ -1207,67 +1207,142 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
 // position, direction, path length and search state saved, and resumes in the
 // next iteration (paper, "Reducing load imbalance").  Momentum is fixed during
 // the step, so a paused step ends exactly as an uninterrupted one.
+// Per-thread counts of the along-step kernels, flushed once per block.
+struct AlongAcc {
+    unsigned long long field = 0, photon = 0, ret_field = 0, ret_photon = 0, sub = 0, pause = 0, pre = 0;
+};
+
+// The field tracks of a sorted iteration, positions [0, n) of the
+// permutation from `off`: each thread walks its positions at the grid
+// stride and loads the next track's fields (and the slot after it) before
+// stepping the current one, so those loads are in flight during the step.
+template <class R>
+__device__ __forceinline__ void field_tracks_sorted(const Dev<R>& d, const Tables<R>& tb, uint32_t n, uint32_t off,
+                                                    AlongAcc& acc)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t s = i < n ? d.perm[off + i] : 0u;
+    FieldIn<R> cur;
+    if (i < n) load_field_in(d, s, cur);
+    uint32_t s_next = i + stride < n ? d.perm[off + i + stride] : 0u;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const bool act = i < n;
+        const uint32_t i1 = i + stride, i2 = i + 2 * stride;
+        FieldIn<R> nxt;
+        if (i1 < n) load_field_in(d, s_next, nxt);
+        const uint32_t s_after = i2 < n ? d.perm[off + i2] : 0u;
+        uint32_t row = 0;
+        uint8_t next = A_NONE;
+        uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
+        if (act) along_field_track<R>(d, tb, s, cur, d.max_substeps, row, next, retired, att, paused_n, pre_n);
+        acc.field += act ? 1u : 0u;
+        acc.pre += pre_n;
+        leave_event(d, retired != 0, row);
+        acc.ret_field += retired;
+        acc.sub += att;
+        acc.pause += paused_n;
+        if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u))
+            append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+        i = i1;
+        s = s_next;
+        cur = nxt;
+        s_next = s_after;
+    }
+}
+
+// One track's along-step by its along action (masked iterations).
+template <class R>
+__device__ __forceinline__ void along_any_track(const Dev<R>& d, const Tables<R>& tb, uint32_t s, uint8_t a,
+                                                AlongAcc& acc)
+{
+    uint32_t row = 0;
+    uint8_t next = A_NONE;
+    uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
+    if (a == A_FIELD) {
+        along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n, pre_n);
+        ++acc.field;
+        acc.ret_field += retired;
+    } else if (a == A_NEUTRAL) {
+        along_straight_track<R, false>(d, tb, s, row, next, retired);
+        pre_n = 1;
+        ++acc.photon;
+        acc.ret_photon += retired;
+    }
+    acc.pre += pre_n;
+    acc.sub += att;
+    acc.pause += paused_n;
+    leave_event(d, retired != 0, row);
+    if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u)) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+}
+
 template <class R>
 __global__ void __launch_bounds__(kStepMaxBlock) k_along_field(Dev<R> d)
 {
     extern __shared__ __align__(16) unsigned char ems_lds[];
     EMS_TRACK_RANGE(d, A_FIELD)
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
-    unsigned long long ret_acc = 0, sub_acc = 0, pause_acc = 0, pre_acc = 0;
+    AlongAcc acc;
     if (_mode == 1) {
-        // sorted: the field tracks are one index range.  Each thread walks
-        // its tracks at the grid stride and loads the next one's fields (and
-        // the slot after it) before stepping the current one, so those loads
-        // are in flight during the step.
-        const uint32_t stride = gridDim.x * blockDim.x;
-        uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-        uint32_t s = i < _n ? d.perm[_off + i] : 0u;
-        FieldIn<R> cur;
-        if (i < _n) load_field_in(d, s, cur);
-        uint32_t s_next = i + stride < _n ? d.perm[_off + i + stride] : 0u;
-        for (uint32_t base = blockIdx.x * blockDim.x; base < _n; base += stride) {
-            const bool act = i < _n;
-            const uint32_t i1 = i + stride, i2 = i + 2 * stride;
-            FieldIn<R> nxt;
-            if (i1 < _n) load_field_in(d, s_next, nxt);
-            const uint32_t s_after = i2 < _n ? d.perm[_off + i2] : 0u;
-            uint32_t row = 0;
-            uint8_t next = A_NONE;
-            uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
-            if (act) along_field_track<R>(d, tb, s, cur, d.max_substeps, row, next, retired, att, paused_n, pre_n);
-            _work += act ? 1u : 0u;
-            pre_acc += pre_n;
-            leave_event(d, retired != 0, row);
-            ret_acc += retired;
-            sub_acc += att;
-            pause_acc += paused_n;
-            if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u))
-                append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
-            i = i1;
-            s = s_next;
-            cur = nxt;
-            s_next = s_after;
-        }
+        field_tracks_sorted(d, tb, _n, _off, acc);
     } else {
         EMS_FOR_TRACKS(d, A_FIELD, s, act, W_FIELD)
-        uint32_t row = 0;
-        uint8_t next = A_NONE;
-        uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
-        if (act) along_field_track<R>(d, tb, s, d.max_substeps, row, next, retired, att, paused_n, pre_n);
-        pre_acc += pre_n;
-        leave_event(d, retired != 0, row);
-        ret_acc += retired;
-        sub_acc += att;
-        pause_acc += paused_n;
-        if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u))
-            append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+        along_any_track(d, tb, s, act ? (uint8_t)A_FIELD : (uint8_t)A_NONE, acc);
         EMS_END_TRACKS
+        (void)_work;                 // the same count as acc.field
     }
-    flush_count(d, W_FIELD, _work);
-    flush_count(d, kStepsSlot + W_FIELD, ret_acc);
-    flush_count(d, W_SUBSTEPS, sub_acc);
-    flush_count(d, W_PAUSED, pause_acc);
-    flush_count_shared(d, W_PRE, pre_acc);
+    flush_count(d, W_FIELD, acc.field);
+    flush_count(d, kStepsSlot + W_FIELD, acc.ret_field);
+    flush_count(d, W_SUBSTEPS, acc.sub);
+    flush_count(d, W_PAUSED, acc.pause);
+    flush_count_shared(d, W_PRE, acc.pre);
+}
+
+// Both along-steps of a field iteration in one launch (tuning `fuse_along`):
+// sorted, each thread first steps its field tracks as k_along_field does,
+// then its share of the photon range, which is dealt out starting at the
+// waves that had one field round fewer, so that the photon steps fill the
+// end of the field launch instead of paying for a launch of their own.
+// Masked, each slot takes the along-step of its type.
+template <class R>
+__global__ void __launch_bounds__(kStepMaxBlock) k_along_both(Dev<R> d)
+{
+    extern __shared__ __align__(16) unsigned char ems_lds[];
+    const int mode = (d.ctr->phase_sorted & 1u) ? d.sorted : 0;
+    const uint32_t nf = mode == 1 ? d.ctr->range_cnt[A_FIELD] : d.n_slots;
+    const uint32_t np = mode == 1 ? d.ctr->range_cnt[A_NEUTRAL] : 0u;
+    // sorted, every wave of the grid may be dealt photon chunks: no early exit
+    if (mode != 1 && blockIdx.x * blockDim.x >= nf) return;          // block-uniform
+    const Tables<R> tb = block_tables(d, (R*)ems_lds);
+    AlongAcc acc;
+    if (mode == 1) {
+        field_tracks_sorted(d, tb, nf, d.ctr->range_off[A_FIELD], acc);
+        // photon chunks of 64 positions: chunk c goes to wave (r + c) mod W,
+        // r = the number of waves that took one field round more
+        const uint32_t waves = gridDim.x * blockDim.x / 64;
+        const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+        const uint32_t r = (nf / 64 + (nf % 64 != 0)) % waves;
+        const uint32_t first = (w + waves - r) % waves;
+        const uint32_t offp = d.ctr->range_off[A_NEUTRAL];
+        for (uint32_t c = first; (size_t)c * 64 < np; c += waves) {
+            const uint32_t j = c * 64 + lane_id();
+            const bool act = j < np;
+            along_any_track(d, tb, act ? d.perm[offp + j] : 0u, act ? (uint8_t)A_NEUTRAL : (uint8_t)A_NONE, acc);
+        }
+    } else {
+        for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += gridDim.x * blockDim.x) {
+            const uint32_t s = base + threadIdx.x;
+            const uint8_t a = s < nf ? along_action(d, s) : A_NONE;
+            along_any_track(d, tb, s, a, acc);
+        }
+    }
+    flush_count(d, W_FIELD, acc.field);
+    flush_count(d, W_NEUTRAL, acc.photon);
+    flush_count(d, kStepsSlot + W_FIELD, acc.ret_field);
+    flush_count(d, kStepsSlot + W_NEUTRAL, acc.ret_photon);
+    flush_count(d, W_SUBSTEPS, acc.sub);
+    flush_count(d, W_PAUSED, acc.pause);
+    flush_count_shared(d, W_PRE, acc.pre);
 }
 
 // Discrete interaction PROC of one track at the end of its along-step.

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 7
+ABI_VERSION = 8
 FP64, MIXED = 0, 1
 SORT_NONE, SORT_PARTITION, SORT_RADIX, SORT_QUEUE = 0, 1, 2, 3
 SORT_POLICIES = {"none": SORT_NONE, "partition": SORT_PARTITION, "radix": SORT_RADIX, "queue": SORT_QUEUE}
@@ -52,7 +52,7 @@ class Material(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("sort_policy", C.c_int32), ("tail_threshold", C.c_uint32), ("block", C.c_int32 * 16),
                 ("drain_threshold", C.c_uint32), ("drain_steps", C.c_uint32), ("reuse_parent_slot", C.c_uint32),
-                ("fuse_interactions", C.c_uint32), ("phase_sort", C.c_uint32 * 2)]
+                ("fuse_interactions", C.c_uint32), ("phase_sort", C.c_uint32 * 2), ("fuse_along", C.c_uint32)]
 
 
 class Counters(C.Structure):
@@ -341,11 +341,11 @@ class Session:
         return {"sort_policy": t.sort_policy, "tail_threshold": t.tail_threshold,
                 "drain_threshold": t.drain_threshold, "drain_steps": t.drain_steps,
                 "reuse_parent_slot": bool(t.reuse_parent_slot), "fuse_interactions": bool(t.fuse_interactions),
-                "phase_sort": (int(t.phase_sort[0]), int(t.phase_sort[1])),
+                "phase_sort": (int(t.phase_sort[0]), int(t.phase_sort[1])), "fuse_along": bool(t.fuse_along),
                 "block": {KERNEL_ROLES[i]: t.block[i] for i in range(len(KERNEL_ROLES)) if t.block[i]}}
 
     def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, drain_threshold=None, drain_steps=None,
-                   reuse_parent_slot=None, fuse_interactions=None, phase_sort=None):
+                   reuse_parent_slot=None, fuse_interactions=None, phase_sort=None, fuse_along=None):
         """Change knobs that affect speed only; block maps kernel role names to
         block sizes; phase_sort is a pair of 32-bit masks over occupancy
         buckets floor(log2 live tracks): bit b of mask p set = sort point p
@@ -364,6 +364,8 @@ class Session:
             cur.reuse_parent_slot = 1 if reuse_parent_slot else 0
         if fuse_interactions is not None:
             cur.fuse_interactions = 1 if fuse_interactions else 0
+        if fuse_along is not None:
+            cur.fuse_along = 1 if fuse_along else 0
         if block is not None:
             for name, b in block.items():
                 cur.block[KERNEL_ROLES.index(name)] = int(b)

@@ -35,7 +35,7 @@ pytestmark = pytest.mark.gpu
 ME = 0.51099895
 BENCH = dict(sort_policy="partition", init_partition=True, graph_iterations=8, lds_tables=1, streams=1,
              max_substeps=10)
-BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True)
+BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True, fuse_along=True)
 
 
 def _run(w, events=None, tuning=None, **kw):

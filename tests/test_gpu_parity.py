@@ -16,8 +16,8 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_helpers import (assert_events_match, layer_sums, ledger_int_mismatch, random_states, session_for,
-                               to_lib_tracks)
+from tests.gpu_helpers import (assert_events_match, event_energy, layer_sums, ledger_int_mismatch, random_states,
+                               session_for, to_lib_tracks)
 
 pytestmark = pytest.mark.gpu
 
@@ -324,7 +324,10 @@ def test_tuning_does_not_change_results():
                    dict(sort_policy="queue", tail_threshold=0, block={"along_field": 64}),
                    dict(sort_policy="queue", fuse_interactions=True, drain_threshold=0),
                    dict(sort_policy="none", fuse_interactions=True, block={"interactions": 128}),
-                   dict(sort_policy="radix", tail_threshold=2000, fuse_interactions=True, reuse_parent_slot=True)]:
+                   dict(sort_policy="radix", tail_threshold=2000, fuse_interactions=True, reuse_parent_slot=True),
+                   dict(sort_policy="partition", fuse_along=False, fuse_interactions=True),
+                   dict(sort_policy="none", fuse_along=False, block={"along_field": 128}),
+                   dict(sort_policy="partition", fuse_along=True, block={"along_field": 512}, tail_threshold=0)]:
         s.set_tuning(**tuning)
         s.push(w.primaries)
         c = s.run()
@@ -334,6 +337,40 @@ def test_tuning_does_not_change_results():
         assert _ledger_equal_int(led, l_ref) is None, tuning
         assert np.abs(edep - e_ref).max() <= 1e-9 * 1000.0, tuning
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_fused_along_steps_match_separate_launches_and_oracle(precision):
+    """Photon and field along-steps in one launch (tuning fuse_along, one
+    stream): the same per-track code as the two separate kernels, so the
+    results equal theirs (integer ledgers exactly, deposits to 1e-12 of the
+    event energy) and, in FP64, the oracle's, for every sort policy; masked
+    (policy none) each slot takes the along-step of its type.  Few slots
+    (2^12) keep both ranges longer than the grid, so threads take several
+    field rounds and photon chunks."""
+    w = workloads.electron_showers_1gev_field(40, n_slots=1 << 12)
+    e0 = event_energy(w)
+    if precision == "f64":
+        e_ref, l_ref, steps = _run_oracle(w)
+    for policy in ("partition", "none", "radix"):
+        res = {}
+        for fused in (True, False):
+            s = session_for(w, precision=precision, sort_policy=policy, init_partition=True, graph_iterations=4,
+                            streams=1)
+            s.set_tuning(fuse_interactions=True, fuse_along=fused)
+            s.push(w.primaries)
+            c = s.run(max_iterations=1_000_000)
+            res[fused] = (c, *s.tallies_by_event(np.arange(w.n_events)))
+            s.close()
+        (c1, e1, l1), (c0, ea, la) = res[True], res[False]
+        assert c1["steps"] == c0["steps"] and c1["overflow"] == 0, policy
+        assert _ledger_equal_int(l1, la) is None, policy
+        assert np.all(np.abs(e1 - ea).max(1) <= 1e-12 * e0), policy
+        assert c1["work"]["along_neutral"] == c0["work"]["along_neutral"] > 0, policy
+        if precision == "f64":
+            assert c1["steps"] == steps
+            assert _ledger_equal_int(l1, l_ref) is None, policy
+            assert np.all(np.abs(e1 - e_ref).max(1) <= 1e-9 * e0), policy
 
 
 @pytest.mark.parametrize("precision", ["f64", "mixed"])

@@ -160,11 +160,13 @@ class TuneSession(FakeSession):
 
     def __init__(self):
         super().__init__(max_events=10 ** 6)
-        self.t = {"sort_policy": "none", "tail_threshold": 0, "block": {}, "fuse": False, "drain": 0}
+        self.t = {"sort_policy": "none", "tail_threshold": 0, "block": {}, "fuse": False, "drain": 0, "along": False}
         self.prof_on = 0
 
     def set_tuning(self, sort_policy=None, tail_threshold=None, block=None, fuse_interactions=None,
-                   drain_threshold=None, **kw):
+                   drain_threshold=None, fuse_along=None, **kw):
+        if fuse_along is not None:
+            self.t["along"] = fuse_along
         if sort_policy is not None:
             self.t["sort_policy"] = sort_policy
         if tail_threshold is not None:
@@ -194,6 +196,7 @@ class TuneSession(FakeSession):
         cost += 0.001 * abs(self.t["tail_threshold"] - 2048) / 2048
         cost -= 0.2 if self.t["fuse"] else 0.0
         cost -= 0.1 if self.t["drain"] == 16384 else 0.0
+        cost -= 0.15 if self.t["along"] else 0.0
         time.sleep(0.002 * cost)
         self.pending.clear()
         return self.counters()
@@ -211,6 +214,7 @@ def test_autotune_finds_the_cost_model_optimum(monkeypatch):
     assert res["sort_policy"] == "partition"
     assert res["tail_threshold"] == 2048
     assert res["fuse_interactions"] is True and res["drain_threshold"] == 16384
+    assert res["fuse_along"] is True
     assert res["block"]["along_field"] == 256 and res["block"]["along_neutral"] == 128
 
 
