@@ -705,6 +705,7 @@ def main():
                    "lds_tables": args.lds_tables, "streams": args.streams,
                    "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
                    "reuse_parent_slot": args.reuse_parent_slot, "fuse_interactions": args.fuse_interactions,
+                   "fuse_along": int(fused_along(args, w)),
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
