@@ -164,6 +164,12 @@ def parse():
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")
+    ap.add_argument("--phase-sort", type=lambda x: int(x, 0), nargs=2, default=[0x0007FFFF, 0xFFFFFFFF],
+                    metavar=("MASK1", "MASK2"),
+                    help="reorder at sort point 1 / 2 in the occupancy buckets floor(log2 live tracks) whose bits "
+                         "are set; default: sort point 1 below 2^19 live tracks (above it the partitioned fill "
+                         "keeps photons and charged tracks apart and the along-step launch runs masked), sort "
+                         "point 2 always")
     ap.add_argument("--fuse-along", type=int, default=1,
                     help="one launch for the photon and field along-steps (with a field and one stream)")
     ap.add_argument("--roofline-kernel", default="along_field")
@@ -224,7 +230,8 @@ def new_session(w, args, precision, policy, init_partition, graph=None, drain=No
     reuse = args.reuse_parent_slot if reuse is None else reuse
     fuse = args.fuse_interactions if fuse is None else fuse
     s.set_tuning(drain_threshold=drain, drain_steps=args.drain_steps, reuse_parent_slot=bool(reuse),
-                 fuse_interactions=bool(fuse), fuse_along=bool(args.fuse_along))
+                 fuse_interactions=bool(fuse), fuse_along=bool(args.fuse_along),
+                 phase_sort=tuple(args.phase_sort) if args.phase_sort else None)
     return s
 
 
@@ -706,6 +713,7 @@ def main():
                    "drain_threshold": args.drain_threshold, "drain_steps": args.drain_steps,
                    "reuse_parent_slot": args.reuse_parent_slot, "fuse_interactions": args.fuse_interactions,
                    "fuse_along": int(fused_along(args, w)),
+                   "phase_sort": ["0x%08X" % m for m in args.phase_sort],
                    "track_steps_per_step": r["steps"] // args.steps,
                    "iterations_per_step": r["iterations"] // args.steps},
         "work_per_step": {k: v // args.steps for k, v in r["work"].items()},
@@ -728,7 +736,8 @@ def main():
         key = {"workload": w.name, "precision": precision, "n_slots": w.n_slots, "sort_policy": args.policy,
                "init_partition": args.init_partition, "max_substeps": args.max_substeps,
                "drain_threshold": args.drain_threshold, "reuse_parent_slot": args.reuse_parent_slot,
-               "fuse_interactions": args.fuse_interactions, "fuse_along": int(both)}
+               "fuse_interactions": args.fuse_interactions, "fuse_along": int(both),
+               "phase_sort": ["0x%08X" % m for m in args.phase_sort]}
         label = "along_both" if both else prof_kernel
         t = committed_traffic(label, key)
         out["roofline"] = {"bound": "hbm", "kernel": label, "achieved": achieved, "peak": HBM_PEAK_GBS,
