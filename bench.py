@@ -164,12 +164,12 @@ def parse():
     ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")
-    ap.add_argument("--phase-sort", type=lambda x: int(x, 0), nargs=2, default=[0x0007FFFF, 0xFFFFFFFF],
+    ap.add_argument("--phase-sort", type=lambda x: int(x, 0), nargs=2, default=[0x0, 0xFFFFFFFF],
                     metavar=("MASK1", "MASK2"),
                     help="reorder at sort point 1 / 2 in the occupancy buckets floor(log2 live tracks) whose bits "
-                         "are set; default: sort point 1 below 2^19 live tracks (above it the partitioned fill "
-                         "keeps photons and charged tracks apart and the along-step launch runs masked), sort "
-                         "point 2 always")
+                         "are set (an empty mask: that point's kernels are not launched); default: no sort point 1 "
+                         "(the partitioned fill keeps photons and charged tracks apart and the along-step launch "
+                         "runs masked), sort point 2 always")
     ap.add_argument("--fuse-along", type=int, default=1,
                     help="one launch for the photon and field along-steps (with a field and one stream)")
     ap.add_argument("--roofline-kernel", default="along_field")

@@ -381,8 +381,8 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * bucket: an iteration with n live tracks (n >= tail_threshold) reorders at
  * sort point p when bit floor(log2 n) of phase_sort[p] is set, and runs that
  * point's kernels masked otherwise (all bits set: reorder at every
- * occupancy).  The sort policy itself (partition, radix, queue) is one per
- * context.
+ * occupancy; none set: that point's kernels are not launched at all).  The
+ * sort policy itself (partition, radix, queue) is one per context.
  *
  * Drain (ems_run only; 0 = off): once the latest counter snapshot shows fewer
  * than drain_threshold tracks alive, queued or pending, and no more than the

@@ -614,7 +614,9 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     }
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
     // (the along-step kernels run the pre-step of their tracks)
-    if (d.sorted == 1) launch_sort<R>(c, d, ln, 2);
+    // a sort point whose phase mask is empty never reorders: its kernels are
+    // not launched at all (not even to return at once)
+    if (d.sorted == 1 && c->phase_sort[0] != 0u) launch_sort<R>(c, d, ln, 2);
     // along-step: photons and leptons are independent branches, or one
     // launch for both in a field on one stream (tuning fuse_along)
     const int nw = c->n_streams - 1;
@@ -638,7 +640,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
                    lds, st, d);
         if (nw > 0) join(c, 0, 1);
     }
-    if (d.sorted2 == 1) launch_sort<R>(c, d, ln, 0);
+    if (d.sorted2 == 1 && c->phase_sort[1] != 0u) launch_sort<R>(c, d, ln, 0);
     if (d.det) launch_interactions<R, true>(c, d, ln, nw);
     else launch_interactions<R, false>(c, d, ln, nw);
     if (d.det) {

@@ -1212,6 +1212,24 @@ struct AlongAcc {
     unsigned long long field = 0, photon = 0, ret_field = 0, ret_photon = 0, sub = 0, pause = 0, pre = 0;
 };
 
+// One field track's along-step from its loaded inputs, with the counts.
+template <class R>
+__device__ __forceinline__ void field_step_loaded(const Dev<R>& d, const Tables<R>& tb, uint32_t s,
+                                                  const FieldIn<R>& in, bool act, AlongAcc& acc)
+{
+    uint32_t row = 0;
+    uint8_t next = A_NONE;
+    uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
+    if (act) along_field_track<R>(d, tb, s, in, d.max_substeps, row, next, retired, att, paused_n, pre_n);
+    acc.field += act ? 1u : 0u;
+    acc.pre += pre_n;
+    leave_event(d, retired != 0, row);
+    acc.ret_field += retired;
+    acc.sub += att;
+    acc.pause += paused_n;
+    if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u)) append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+}
+
 // The field tracks of a sorted iteration, positions [0, n) of the
 // permutation from `off`: each thread walks its positions at the grid
 // stride and loads the next track's fields (and the slot after it) before
@@ -1232,18 +1250,7 @@ __device__ __forceinline__ void field_tracks_sorted(const Dev<R>& d, const Table
         FieldIn<R> nxt;
         if (i1 < n) load_field_in(d, s_next, nxt);
         const uint32_t s_after = i2 < n ? d.perm[off + i2] : 0u;
-        uint32_t row = 0;
-        uint8_t next = A_NONE;
-        uint32_t retired = 0, att = 0, paused_n = 0, pre_n = 0;
-        if (act) along_field_track<R>(d, tb, s, cur, d.max_substeps, row, next, retired, att, paused_n, pre_n);
-        acc.field += act ? 1u : 0u;
-        acc.pre += pre_n;
-        leave_event(d, retired != 0, row);
-        acc.ret_field += retired;
-        acc.sub += att;
-        acc.pause += paused_n;
-        if (d.sorted2 == 2 && (d.ctr->phase_sorted & 2u))
-            append_to_list(d, next >= A_PROC0 && next < A_NUM, next, s);
+        field_step_loaded(d, tb, s, cur, act, acc);
         i = i1;
         s = s_next;
         cur = nxt;
@@ -1330,10 +1337,26 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_both(Dev<R> d)
             along_any_track(d, tb, act ? d.perm[offp + j] : 0u, act ? (uint8_t)A_NEUTRAL : (uint8_t)A_NONE, acc);
         }
     } else {
-        for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += gridDim.x * blockDim.x) {
-            const uint32_t s = base + threadIdx.x;
-            const uint8_t a = s < nf ? along_action(d, s) : A_NONE;
-            along_any_track(d, tb, s, a, acc);
+        // masked: each thread walks the slots at the grid stride; the along
+        // action of the slot after next and the inputs of the next slot, if
+        // it holds a field track, are loaded before the current slot steps
+        const uint32_t stride = gridDim.x * blockDim.x;
+        uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+        uint8_t a = s < nf ? along_action(d, s) : A_NONE;
+        uint8_t a1 = s + stride < nf ? along_action(d, s + stride) : A_NONE;
+        FieldIn<R> cur;
+        if (a == A_FIELD) load_field_in(d, s, cur);
+        for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
+            const uint32_t s1 = s + stride, s2 = s + 2 * stride;
+            FieldIn<R> nxt;
+            if (a1 == A_FIELD) load_field_in(d, s1, nxt);
+            const uint8_t a2 = s2 < nf ? along_action(d, s2) : A_NONE;
+            if (a == A_FIELD) field_step_loaded(d, tb, s, cur, true, acc);
+            else along_any_track(d, tb, s, a, acc);
+            s = s1;
+            a = a1;
+            a1 = a2;
+            cur = nxt;
         }
     }
     flush_count(d, W_FIELD, acc.field);

@@ -1,9 +1,9 @@
 """GPU parity at the benchmark workloads' full sizes, in the launch
 configuration the benchmark times (partition policy, charged / neutral
 partitioned fill, 8-iteration graph batches, LDS-staged tables, one stream,
-substep cap 10, photon and field along-steps in one launch, masked above
-2^19 live tracks and sorted below, fused interaction kernel, drain below
-65536 tracks), plus degenerate and rejected inputs.
+substep cap 10, photon and field along-steps in one launch, masked (no
+sort point before them), fused interaction kernel, drain below 65536
+tracks), plus degenerate and rejected inputs.
 
 * 10^4 electrons of 1 GeV in the 1 T stack at 2^20 slots: every event of the
   benchmark's configuration against the FP64 oracle (integer ledger equal,
@@ -37,7 +37,7 @@ ME = 0.51099895
 BENCH = dict(sort_policy="partition", init_partition=True, graph_iterations=8, lds_tables=1, streams=1,
              max_substeps=10)
 BENCH_TUNING = dict(drain_threshold=65536, drain_steps=4096, fuse_interactions=True, fuse_along=True,
-                    phase_sort=(0x0007FFFF, 0xFFFFFFFF))
+                    phase_sort=(0x0, 0xFFFFFFFF))
 
 
 def _run(w, events=None, tuning=None, **kw):

@@ -327,7 +327,10 @@ def test_tuning_does_not_change_results():
                    dict(sort_policy="radix", tail_threshold=2000, fuse_interactions=True, reuse_parent_slot=True),
                    dict(sort_policy="partition", fuse_along=False, fuse_interactions=True),
                    dict(sort_policy="none", fuse_along=False, block={"along_field": 128}),
-                   dict(sort_policy="partition", fuse_along=True, block={"along_field": 512}, tail_threshold=0)]:
+                   dict(sort_policy="partition", fuse_along=True, block={"along_field": 512}, tail_threshold=0),
+                   dict(sort_policy="partition", phase_sort=(0, 0xFFFFFFFF)),
+                   dict(sort_policy="radix", phase_sort=(0xFFFFFFFF, 0)),
+                   dict(sort_policy="partition", phase_sort=(0x0007FFFF, 0xFFFFFFFF))]:
         s.set_tuning(**tuning)
         s.push(w.primaries)
         c = s.run()
