@@ -111,6 +111,8 @@ struct Counters {
     unsigned int done_count;           // events completed so far (entries written to the ring)
     unsigned int phase_sorted;         // reordering this iteration: bit 0 sort point 1, bit 1 sort point 2
     unsigned long long sec_base;       // deterministic appends: buffer size before this iteration's appends
+    unsigned int n_take_lo;            // taken initializers that went to the lowest vacancies (the rest to
+                                       // the highest): the charged ones with the partitioned fill, else all
 };
 
 // work counter indices

@@ -69,6 +69,7 @@ struct Layout {
     uint32_t n_rep_e;                      // copies of the deposit tallies
     uint64_t edep_rs, edep_out;            // doubles per copy; summed tallies for readers
     uint64_t sec_cnt, sec_blk, sec_rec;    // deterministic appends (staging; 0 when off)
+    uint64_t along_list;                   // occupied slots before the fill (masked one-launch along-steps)
     uint32_t part_stride;
     uint32_t drain_threads;   // capacity of the drain kernel (threads; 8 stack records each)
     uint64_t total;
@@ -113,6 +114,7 @@ Layout make_layout(const ems_options& o)
     L.vac_cnt = take(4 * nvb);
     L.init_cnt = take(4 * nvb);
     L.perm = take(4 * n);
+    L.along_list = take(4 * n);
     L.lists = take(4ull * A_NUM * n);
     L.n_tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
     L.sort_cnt = take(4ull * 128 * L.n_tiles);
@@ -248,6 +250,13 @@ struct ems_ctx {
 
 namespace {
 
+// The photon and field along-steps run as one launch: a field, one stream
+// and the tuning's fuse_along.
+bool fused_along(const ems_ctx* c)
+{
+    return c->fuse_along && c->n_streams == 1 && (c->B[0] != 0.0 || c->B[1] != 0.0 || c->B[2] != 0.0);
+}
+
 template <class R>
 Dev<R> make_dev(const ems_ctx* c)
 {
@@ -323,6 +332,9 @@ Dev<R> make_dev(const ems_ctx* c)
     d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.msc = c->opt.msc ? 1 : 0;
     d.det = c->opt.deterministic ? 1 : 0;
+    d.along_list = (uint32_t*)(b + L.along_list);
+    // the walk over listed slots is a reordering: not with the policy none
+    d.compact_along = (c->policy != EMS_SORT_NONE && fused_along(c)) ? 1 : 0;
     d.sec_cnt = c->opt.deterministic ? (uint8_t*)(b + L.sec_cnt) : nullptr;
     d.sec_blk = c->opt.deterministic ? (uint32_t*)(b + L.sec_blk) : nullptr;
     d.sec_rec = c->opt.deterministic ? (Initializer*)(b + L.sec_rec) : nullptr;
@@ -603,7 +615,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     hipStream_t st = c->stream;
     ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
     ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1,
-         (uint32_t*)nullptr);
+         d.compact_along ? d.along_list : (uint32_t*)nullptr);
     if (!no_init) {
         if (c->opt.init_partition) {
             ln.k(R_INIT, true, false, k_init_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
@@ -620,7 +632,7 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     // along-step: photons and leptons are independent branches, or one
     // launch for both in a field on one stream (tuning fuse_along)
     const int nw = c->n_streams - 1;
-    if (d.has_field && c->fuse_along && nw == 0) {
+    if (fused_along(c)) {
         ln.one(R_ALONG_FIELD, k_along_both<R>,
                dim3(c->policy == EMS_SORT_NONE ? G(R_ALONG_FIELD)
                                                : field_grid<R>(c, G(R_ALONG_FIELD), B(R_ALONG_FIELD), lds, true)),

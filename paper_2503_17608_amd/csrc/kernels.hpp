@@ -81,6 +81,11 @@ struct Dev {
     // point 1 (before the along-steps) / 2 (before the interactions)
     // reorders in an iteration of that bucket, else its kernels run masked
     unsigned int phase_sort1, phase_sort2;
+    // masked iterations of the one-launch along-steps walk the slots occupied
+    // before the fill (listed by the vacancy pass) and the filled vacancies,
+    // not every slot
+    int compact_along;
+    uint32_t* along_list;   // [n_slots] occupied slots before the fill, in slot order
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
@@ -282,6 +287,7 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
         }
         c->n_take_q = (uint32_t)tq;
         c->n_take_p = (uint32_t)tp;
+        c->n_take_lo = (uint32_t)(tq + tp);          // the partitioned fill sets its charged count
         c->q_base = q - tq;
         c->p_base = c->prim_next;
         c->queue_size = q - tq;
@@ -432,6 +438,12 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
         for (int k = 0; k < w; ++k) off += wcnt[k];
         uint32_t cidx = off + rank_below(m);          // charged initializers before i
         if (act) slot = ch ? d.vac[cidx] : d.vac[c->n_vac - 1 - (i - cidx)];
+        // the last block knows how many charged initializers there are
+        if (threadIdx.x == 0 && (blockIdx.x + 1) * kVacBlock >= n) {
+            uint32_t tot = prefix;
+            for (int k = 0; k < kVacBlock / 64; ++k) tot += wcnt[k];
+            d.ctr->n_take_lo = tot;
+        }
     } else {
         if (act) slot = d.vac[i];
     }
@@ -1319,6 +1331,7 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_both(Dev<R> d)
     const uint32_t nf = mode == 1 ? d.ctr->range_cnt[A_FIELD] : d.n_slots;
     const uint32_t np = mode == 1 ? d.ctr->range_cnt[A_NEUTRAL] : 0u;
     // sorted, every wave of the grid may be dealt photon chunks: no early exit
+    // (masked, the grid never exceeds the slots)
     if (mode != 1 && blockIdx.x * blockDim.x >= nf) return;          // block-uniform
     const Tables<R> tb = block_tables(d, (R*)ems_lds);
     AlongAcc acc;
@@ -1337,23 +1350,43 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_both(Dev<R> d)
             along_any_track(d, tb, act ? d.perm[offp + j] : 0u, act ? (uint8_t)A_NEUTRAL : (uint8_t)A_NONE, acc);
         }
     } else {
-        // masked: each thread walks the slots at the grid stride; the along
-        // action of the slot after next and the inputs of the next slot, if
-        // it holds a field track, are loaded before the current slot steps
+        // masked: each thread walks its positions at the grid stride -- the
+        // slots, or with compact_along the slots occupied before the fill
+        // (in slot order) followed by the vacancies the fill used (the
+        // lowest n_take_lo, then the highest) -- and steps each slot's own
+        // type; the along action of the position after next and the inputs
+        // of the next one, if it holds a field track, are loaded before the
+        // current one steps
+        const Counters* c = d.ctr;
+        const bool cl = d.compact_along != 0;
+        const uint32_t n_old = c->alive_before, n_take = c->n_take_q + c->n_take_p;
+        const uint32_t n_lo = c->n_take_lo, n_vac = c->n_vac;
+        const uint32_t np_all = cl ? n_old + n_take : nf;
+        auto slot_at = [&](uint32_t p) -> uint32_t {
+            if (!cl) return p;
+            if (p < n_old) return d.along_list[p];
+            const uint32_t q = p - n_old;
+            return q < n_lo ? d.vac[q] : d.vac[n_vac - n_take + q];
+        };
         const uint32_t stride = gridDim.x * blockDim.x;
-        uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-        uint8_t a = s < nf ? along_action(d, s) : A_NONE;
-        uint8_t a1 = s + stride < nf ? along_action(d, s + stride) : A_NONE;
+        uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+        uint32_t s = p < np_all ? slot_at(p) : 0u;
+        uint32_t s1 = p + stride < np_all ? slot_at(p + stride) : 0u;
+        uint8_t a = p < np_all ? along_action(d, s) : A_NONE;
+        uint8_t a1 = p + stride < np_all ? along_action(d, s1) : A_NONE;
         FieldIn<R> cur;
         if (a == A_FIELD) load_field_in(d, s, cur);
-        for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
-            const uint32_t s1 = s + stride, s2 = s + 2 * stride;
+        for (uint32_t base = blockIdx.x * blockDim.x; base < np_all; base += stride) {
+            const uint32_t p2 = p + 2 * stride;
             FieldIn<R> nxt;
             if (a1 == A_FIELD) load_field_in(d, s1, nxt);
-            const uint8_t a2 = s2 < nf ? along_action(d, s2) : A_NONE;
+            const uint32_t s2 = p2 < np_all ? slot_at(p2) : 0u;
+            const uint8_t a2 = p2 < np_all ? along_action(d, s2) : A_NONE;
             if (a == A_FIELD) field_step_loaded(d, tb, s, cur, true, acc);
             else along_any_track(d, tb, s, a, acc);
+            p += stride;
             s = s1;
+            s1 = s2;
             a = a1;
             a1 = a2;
             cur = nxt;
