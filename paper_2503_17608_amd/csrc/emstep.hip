@@ -230,9 +230,11 @@ struct ems_ctx {
     int policy = 0;
     uint32_t tail_threshold = 0;
     // resident-grid cache of the field along-step, per precision (FP64, FP32)
-    int field_grid_bs[4] = {0, 0, 0, 0};          // [FP64, FP32] x [field kernel, both along-steps]
-    size_t field_grid_lds[4] = {0, 0, 0, 0};
-    uint32_t field_grid_resident[4] = {0, 0, 0, 0};
+    // resident grids by kernel: [FP64, FP32] x [field along-step, both along-steps, fused interactions,
+    // fused interactions with deterministic appends]
+    int grid_bs[8] = {0};
+    size_t grid_lds[8] = {0};
+    uint32_t grid_resident[8] = {0};
     uint32_t phase_sort[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};
     uint32_t drain_threshold = 0;   // ems_run drains below this many live + queued + pending tracks
     uint32_t drain_steps = kDrainStepsDefault;
@@ -548,30 +550,35 @@ void launch_sort(ems_ctx* c, const Dev<R>& d, Launcher& ln, int km)
     }
 }
 
-// Grid of the field along-step with a sort policy: the blocks the device holds
-// at once (each thread then walks its tracks at the grid stride with the
-// next track's loads in flight), at most the slot-covering grid.  Measured:
-// one resident round 2.97e9 track-steps/s, two 2.90e9, the slot-covering
-// grid (one track per thread) 2.84e9.
-template <class R>
-uint32_t field_grid(ems_ctx* c, uint32_t g, int bs, size_t lds, bool both)
+// The blocks of `kern` the device holds at once (cached per kernel slot k
+// and launch shape), at most g.
+uint32_t resident_grid(ems_ctx* c, const void* kern, int k, uint32_t g, int bs, size_t lds)
 {
-    const int k = (sizeof(R) == 8 ? 0 : 1) + (both ? 2 : 0);
-    if (c->field_grid_bs[k] != bs || c->field_grid_lds[k] != lds) {
+    if (c->grid_bs[k] != bs || c->grid_lds[k] != lds) {
         int nb = 0, cus = 0, dev = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
-        const void* kern = both ? reinterpret_cast<const void*>(k_along_both<R>)
-                                : reinterpret_cast<const void*>(k_along_field<R>);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, bs, lds) != hipSuccess ||
-            nb < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, bs, lds) != hipSuccess || nb < 1)
             nb = 1;
-        c->field_grid_resident[k] = (uint32_t)(nb * cus);
-        c->field_grid_bs[k] = bs;
-        c->field_grid_lds[k] = lds;
+        c->grid_resident[k] = (uint32_t)(nb * cus);
+        c->grid_bs[k] = bs;
+        c->grid_lds[k] = lds;
     }
-    return c->field_grid_resident[k] < g ? c->field_grid_resident[k] : g;
+    return c->grid_resident[k] < g ? c->grid_resident[k] : g;
+}
+
+// Grid of the field (or both) along-steps with a sort policy: one resident
+// round (each thread then walks its tracks at the grid stride with the next
+// track's loads in flight), at most the slot-covering grid.  Measured: one
+// resident round 2.97e9 track-steps/s, two 2.90e9, the slot-covering grid
+// (one track per thread) 2.84e9.
+template <class R>
+uint32_t field_grid(ems_ctx* c, uint32_t g, int bs, size_t lds, bool both)
+{
+    const void* kern = both ? reinterpret_cast<const void*>(k_along_both<R>)
+                            : reinterpret_cast<const void*>(k_along_field<R>);
+    return resident_grid(c, kern, (sizeof(R) == 8 ? 0 : 1) + (both ? 2 : 0), g, bs, lds);
 }
 
 // The interaction kernels of an iteration: one fused launch, or seven on
@@ -586,7 +593,12 @@ void launch_interactions(ems_ctx* c, const Dev<R>& d, Launcher& ln, int nw)
     hipStream_t st = c->stream;
     if (c->fuse_interactions) {
         // all seven actions in one launch over the combined index range
-        ln.one(R_INTERACT_ALL, k_interact_all<R, DET>, dim3(G(R_INTERACT_ALL)), dim3(B(R_INTERACT_ALL)), 0, st, d);
+        // one resident round of blocks walks the combined range (the slot
+        // covering grid would launch thousands of blocks that find nothing)
+        const uint32_t g = resident_grid(c, reinterpret_cast<const void*>(k_interact_all<R, DET>),
+                                         4 + (sizeof(R) == 8 ? 0 : 1) + (DET ? 2 : 0), G(R_INTERACT_ALL),
+                                         B(R_INTERACT_ALL), 0);
+        ln.one(R_INTERACT_ALL, k_interact_all<R, DET>, dim3(g), dim3(B(R_INTERACT_ALL)), 0, st, d);
         return;
     }
     // seven independent branches spread over the streams
