@@ -1358,8 +1358,11 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_along_both(Dev<R> d)
         // of the next one, if it holds a field track, are loaded before the
         // current one steps
         const Counters* c = d.ctr;
-        const bool cl = d.compact_along != 0;
         const uint32_t n_old = c->alive_before, n_take = c->n_take_q + c->n_take_p;
+        // the listed walk pays when most slots are empty; when most are
+        // occupied the plain walk reads each line once, where the listed one
+        // reaches a line from both lists
+        const bool cl = d.compact_along != 0 && 2 * (n_old + n_take) < nf;
         const uint32_t n_lo = c->n_take_lo, n_vac = c->n_vac;
         const uint32_t np_all = cl ? n_old + n_take : nf;
         auto slot_at = [&](uint32_t p) -> uint32_t {
