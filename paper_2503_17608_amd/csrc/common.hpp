@@ -113,6 +113,7 @@ struct Counters {
     unsigned long long sec_base;       // deterministic appends: buffer size before this iteration's appends
     unsigned int n_take_lo;            // taken initializers that went to the lowest vacancies (the rest to
                                        // the highest): the charged ones with the partitioned fill, else all
+    unsigned int n_take_hi;            // partitioned fill by block reservations: neutral ones placed so far
 };
 
 // work counter indices

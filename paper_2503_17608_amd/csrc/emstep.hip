@@ -333,6 +333,8 @@ Dev<R> make_dev(const ems_ctx* c)
     d.stage_tables = c->opt.lds_tables ? 1 : 0;
     d.reuse_parent = c->reuse_parent ? 1 : 0;
     d.msc = c->opt.msc ? 1 : 0;
+    // deterministic appends keep the counted (ordered) partitioned fill
+    d.fill_reserve = (c->opt.init_partition && !c->opt.deterministic) ? 1 : 0;
     d.det = c->opt.deterministic ? 1 : 0;
     d.along_list = (uint32_t*)(b + L.along_list);
     // the walk over listed slots is a reordering: not with the policy none
@@ -629,7 +631,9 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1,
          d.compact_along ? d.along_list : (uint32_t*)nullptr);
     if (!no_init) {
-        if (c->opt.init_partition) {
+        if (d.fill_reserve) {
+            ln.one(R_INIT, k_init_reserve<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
+        } else if (c->opt.init_partition) {
             ln.k(R_INIT, true, false, k_init_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
             ln.k(R_INIT, false, true, k_init<R, true>, dim3(nvb), dim3(kVacBlock), 0, st, d);
         } else {

@@ -89,6 +89,7 @@ struct Dev {
     int stage_tables;       // copy the tables into LDS at block start
     int reuse_parent;       // a track that ends hands its slot to its first secondary
     int msc;                // multiple-scattering deflection after charged along-steps
+    int fill_reserve;       // partitioned fill by per-block reservations (k_init_reserve), no count pass
     // deterministic appends: secondaries staged per position of the
     // interaction order (up to 3 records each), appended in that order
     int det;
@@ -287,7 +288,9 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fi
         }
         c->n_take_q = (uint32_t)tq;
         c->n_take_p = (uint32_t)tp;
-        c->n_take_lo = (uint32_t)(tq + tp);          // the partitioned fill sets its charged count
+        // the partitioned fill sets its charged count (by reservations: from 0)
+        c->n_take_lo = d.fill_reserve ? 0u : (uint32_t)(tq + tp);
+        c->n_take_hi = 0u;
         c->q_base = q - tq;
         c->p_base = c->prim_next;
         c->queue_size = q - tq;
@@ -447,6 +450,56 @@ __global__ void __launch_bounds__(kVacBlock) k_init(Dev<R> d)
     } else {
         if (act) slot = d.vac[i];
     }
+    flush_count(d, W_INIT, act ? 1ull : 0ull);
+    if (!act) return;
+    init_slot(d, slot, rec);
+}
+
+// Partitioned fill without a count pass: each block reserves room for its
+// charged initializers from the low end of the vacancies and for its neutral
+// ones from the high end with one atomic each, then places them in lane
+// order.  The set of slots filled is the one k_init<R, true> fills; which
+// charged initializer lands in which of them follows the order in which the
+// blocks reserve (the physics does not depend on it: random numbers are
+// keyed by track).  n_take_lo ends as the number of charged initializers.
+template <class R>
+__global__ void __launch_bounds__(kVacBlock) k_init_reserve(Dev<R> d)
+{
+    __shared__ uint32_t wch[kVacBlock / 64], wne[kVacBlock / 64];
+    __shared__ uint32_t base_lo, base_hi;
+    Counters* c = d.ctr;
+    const uint32_t n = c->n_take_q + c->n_take_p;
+    if (blockIdx.x * kVacBlock >= n) return;          // block-uniform
+    const uint32_t i = blockIdx.x * kVacBlock + threadIdx.x;
+    const bool act = i < n;
+    Initializer rec;
+    if (act) rec = *taken(d, i);
+    const bool ch = act && rec.type != kGamma, ne = act && !ch;
+    const uint64_t mc = __ballot(ch), mn = __ballot(ne);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        wch[w] = (uint32_t)__popcll(mc);
+        wne[w] = (uint32_t)__popcll(mn);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tc = 0, tn = 0;
+        for (int k = 0; k < kVacBlock / 64; ++k) {
+            tc += wch[k];
+            tn += wne[k];
+        }
+        base_lo = tc ? atomicAdd(&c->n_take_lo, tc) : 0u;
+        base_hi = tn ? atomicAdd(&c->n_take_hi, tn) : 0u;
+    }
+    __syncthreads();
+    uint32_t oc = base_lo, on = base_hi;
+    for (int k = 0; k < w; ++k) {
+        oc += wch[k];
+        on += wne[k];
+    }
+    uint32_t slot = 0;
+    if (ch) slot = d.vac[oc + rank_below(mc)];
+    if (ne) slot = d.vac[c->n_vac - 1 - (on + rank_below(mn))];
     flush_count(d, W_INIT, act ? 1ull : 0ull);
     if (!act) return;
     init_slot(d, slot, rec);
