@@ -61,7 +61,7 @@ struct RowReg {
 
 // Workspace layout: every region 256-byte aligned, offsets from the base.
 struct Layout {
-    uint64_t type, action, flags, nsearch, slab, row, step, key, T, nl, xs, sphys, sdone, htry, x, y, z, ux, uy, uz;
+    uint64_t type, action, flags, nsearch, slab, row, step, trk, nl, xs, sphys, sdone, htry;
     uint64_t queue, prims, vac, vac_cnt, init_cnt, perm, lists, sort_cnt, bin_off, ctr;
     uint64_t tables64, tables32, mats, zp, smat, row_event, edep, ledger, live, done_ring, row_gen, row_state, part, incr;
     uint64_t drain_stack, regs, x0, rowsum, ledger_out;
@@ -94,19 +94,12 @@ Layout make_layout(const ems_options& o)
     L.slab = take(2 * n);
     L.row = take(4 * n);
     L.step = take(4 * n);
-    L.key = take(8 * n);
-    L.T = take(rb * n);
+    L.trk = take(kTrackRec * n);
     L.nl = take(rb * n);
     L.xs = take(rb * n);
     L.sphys = take(8 * n);
     L.sdone = take(8 * n);
     L.htry = take(8 * n);
-    L.x = take(8 * n);
-    L.y = take(8 * n);
-    L.z = take(8 * n);
-    L.ux = take(rb * n);
-    L.uy = take(rb * n);
-    L.uz = take(rb * n);
     L.queue = take(sizeof(Initializer) * o.n_initializers);
     L.prims = take(sizeof(Initializer) * o.n_primaries);
     L.vac = take(4 * n);
@@ -272,19 +265,15 @@ Dev<R> make_dev(const ems_ctx* c)
     d.slab = (uint16_t*)(b + L.slab);
     d.row = (uint32_t*)(b + L.row);
     d.step = (uint32_t*)(b + L.step);
-    d.key = (uint64_t*)(b + L.key);
-    d.T = (R*)(b + L.T);
+    // the 64-byte track records (x, y, z, key, then ux, uy, uz, T)
+    char* rec = b + L.trk;
+    d.x.base = d.y.base = d.z.base = d.key.base = rec;
+    d.ux.base = d.uy.base = d.uz.base = d.T.base = rec;
     d.nl = (R*)(b + L.nl);
     d.xs = (R*)(b + L.xs);
     d.sphys = (double*)(b + L.sphys);
     d.sdone = (double*)(b + L.sdone);
     d.htry = (double*)(b + L.htry);
-    d.x = (double*)(b + L.x);
-    d.y = (double*)(b + L.y);
-    d.z = (double*)(b + L.z);
-    d.ux = (R*)(b + L.ux);
-    d.uy = (R*)(b + L.uy);
-    d.uz = (R*)(b + L.uz);
     d.n_slots = (uint32_t)c->opt.n_slots;
     d.queue = (Initializer*)(b + L.queue);
     d.queue_cap = c->opt.n_initializers;

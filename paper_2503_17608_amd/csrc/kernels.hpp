@@ -1,5 +1,6 @@
 // Step-iteration kernels (paper, "Stepping algorithm"): one kernel per
-// stepping action over the struct-of-arrays track state.
+// stepping action over the track state (an array per field, with the fields
+// read together on every step in one record per slot).
 //
 // Every kernel visits its tracks either masked over all slots (the paper's
 // default: each kernel runs on all tracks and masks by next action) or through
@@ -12,6 +13,28 @@
 
 namespace ems {
 
+// The fields that both the along-steps and the interactions read and write
+// for every track they touch -- position, direction, kinetic energy and the
+// random-number key -- sit together in one 64-byte record per slot instead
+// of arrays of their own: a kernel that reaches a few scattered slots (the
+// interactions after the sort, the fill) then brings in one half line per
+// track rather than a line of each array.  Record of slot s at
+// base + 64 s: x, y, z (double) at 0, 8, 16; key at 24; ux, uy, uz and T
+// (precision R) from 32.
+constexpr uint32_t kTrackRec = 64;
+
+template <class T, uint32_t OFF>
+struct RecField {
+    char* base;   // the record of slot 0 (aligned to the record size)
+    __device__ __forceinline__ T& operator[](size_t i) const
+    {
+        // the alignment lets the compiler merge neighbouring fields of one
+        // record into 16-byte accesses
+        char* rec = static_cast<char*>(__builtin_assume_aligned(base + i * kTrackRec, kTrackRec));
+        return *reinterpret_cast<T*>(rec + OFF);
+    }
+};
+
 template <class R>
 struct Dev {
     // track state (struct of arrays over n_slots)
@@ -22,19 +45,19 @@ struct Dev {
     uint16_t* slab;
     uint32_t* row;
     uint32_t* step;
-    uint64_t* key;
-    R* T;
+    RecField<uint64_t, 24> key;
+    RecField<R, 32 + 3 * sizeof(R)> T;
     R* nl;
     R* xs;
     double* sphys;
     double* sdone;
     double* htry;
-    double* x;
-    double* y;
-    double* z;
-    R* ux;
-    R* uy;
-    R* uz;
+    RecField<double, 0> x;
+    RecField<double, 8> y;
+    RecField<double, 16> z;
+    RecField<R, 32> ux;
+    RecField<R, 32 + sizeof(R)> uy;
+    RecField<R, 32 + 2 * sizeof(R)> uz;
     uint32_t n_slots;
     // buffers
     Initializer* queue;
@@ -99,6 +122,23 @@ struct Dev {
     const double* x0;       // radiation length per material [cm]
     int n_tab;              // table values (n_materials * 8 * 181)
 };
+
+// A whole track record, read with 16-byte loads (the hot paths read every
+// field of it).
+template <class R>
+struct alignas(16) TrackRec {
+    double r[3];
+    uint64_t key;
+    R u[3];
+    R T;
+};
+static_assert(sizeof(TrackRec<double>) == kTrackRec, "track record layout");
+
+template <class R>
+__device__ __forceinline__ TrackRec<R> load_track(const Dev<R>& d, uint32_t s)
+{
+    return *reinterpret_cast<const TrackRec<R>*>(d.x.base + (size_t)s * kTrackRec);
+}
 
 // Tables used by a block: staged into LDS (one copy per block, read by every
 // lookup of the block's tracks) or read through the caches.
@@ -936,12 +976,13 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
     row = d.row[s];
     uint16_t slab = d.slab[s];
     const uint16_t slab0 = slab;
-    R T = d.T[s];
-    R u[3] = {d.ux[s], d.uy[s], d.uz[s]};
-    double r[3] = {d.x[s], d.y[s], d.z[s]};
+    const TrackRec<R> tr = load_track(d, s);
+    R T = tr.T;
+    R u[3] = {tr.u[0], tr.u[1], tr.u[2]};
+    double r[3] = {tr.r[0], tr.r[1], tr.r[2]};
     R nl = d.nl[s];
     uint32_t step = d.step[s];
-    const uint64_t key = d.key[s];
+    const uint64_t key = tr.key;
     const uint64_t event = d.row_event[row];
     const int mat = d.smat[slab];
     R sig;
@@ -1097,11 +1138,12 @@ __device__ __forceinline__ void load_field_in(const Dev<R>& d, uint32_t s, Field
     f.slab = d.slab[s];
     f.row = d.row[s];
     f.step = d.step[s];
-    f.key = d.key[s];
-    f.T = d.T[s];
+    const TrackRec<R> tr = load_track(d, s);
+    f.key = tr.key;
+    f.T = tr.T;
     f.nl = d.nl[s];
-    f.u[0] = d.ux[s]; f.u[1] = d.uy[s]; f.u[2] = d.uz[s];
-    f.r[0] = d.x[s]; f.r[1] = d.y[s]; f.r[2] = d.z[s];
+    f.u[0] = tr.u[0]; f.u[1] = tr.u[1]; f.u[2] = tr.u[2];
+    f.r[0] = tr.r[0]; f.r[1] = tr.r[1]; f.r[2] = tr.r[2];
 }
 
 template <class R>
@@ -1465,11 +1507,12 @@ __device__ __forceinline__ void interact_track(const Dev<R>& d, uint32_t s, SecB
 {
     row = d.row[s];
     slab = d.slab[s];
-    r[0] = d.x[s]; r[1] = d.y[s]; r[2] = d.z[s];
+    const TrackRec<R> tr = load_track(d, s);
+    r[0] = tr.r[0]; r[1] = tr.r[1]; r[2] = tr.r[2];
     Prim<R> p;
-    p.T = d.T[s];
-    p.u[0] = d.ux[s]; p.u[1] = d.uy[s]; p.u[2] = d.uz[s];
-    p.key = d.key[s];
+    p.T = tr.T;
+    p.u[0] = tr.u[0]; p.u[1] = tr.u[1]; p.u[2] = tr.u[2];
+    p.key = tr.key;
     p.step = d.step[s];
     p.type = d.type[s];
     p.alive = true;
