@@ -123,8 +123,8 @@ struct Dev {
     int n_tab;              // table values (n_materials * 8 * 181)
 };
 
-// A whole track record, read with 16-byte loads (the hot paths read every
-// field of it).
+// A whole track record, read and written with 16-byte accesses (the hot
+// paths read every field of it, a new track writes every field).
 template <class R>
 struct alignas(16) TrackRec {
     double r[3];
@@ -138,6 +138,12 @@ template <class R>
 __device__ __forceinline__ TrackRec<R> load_track(const Dev<R>& d, uint32_t s)
 {
     return *reinterpret_cast<const TrackRec<R>*>(d.x.base + (size_t)s * kTrackRec);
+}
+
+template <class R>
+__device__ __forceinline__ void store_track(const Dev<R>& d, uint32_t s, const TrackRec<R>& tr)
+{
+    *reinterpret_cast<TrackRec<R>*>(d.x.base + (size_t)s * kTrackRec) = tr;
 }
 
 // Tables used by a block: staged into LDS (one copy per block, read by every
@@ -430,15 +436,17 @@ __device__ __forceinline__ void init_slot(const Dev<R>& d, uint32_t slot, const 
     d.slab[slot] = rec.slab;
     d.row[slot] = rec.row;
     d.step[slot] = 0;
-    d.key[slot] = rec.key;
-    d.T[slot] = (R)rec.T;
     d.nl[slot] = R(-1);
-    d.x[slot] = rec.r[0];
-    d.y[slot] = rec.r[1];
-    d.z[slot] = rec.r[2];
-    d.ux[slot] = (R)rec.u[0];
-    d.uy[slot] = (R)rec.u[1];
-    d.uz[slot] = (R)rec.u[2];
+    TrackRec<R> tr;
+    tr.r[0] = rec.r[0];
+    tr.r[1] = rec.r[1];
+    tr.r[2] = rec.r[2];
+    tr.key = rec.key;
+    tr.u[0] = (R)rec.u[0];
+    tr.u[1] = (R)rec.u[1];
+    tr.u[2] = (R)rec.u[2];
+    tr.T = (R)rec.T;
+    store_track(d, slot, tr);
 }
 
 // per-block count of charged initializers among the taken ones (partitioned fill)
@@ -1009,12 +1017,24 @@ __device__ __forceinline__ void along_straight_track(const Dev<R>& d, const Tabl
                              true, w_sel);
     record_tally(d, row, slab0, tl);
     if (alive) {
-        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+        // the whole record is written (whole 32-byte sectors, no partial
+        // writes), the direction unchanged unless deflected
+        TrackRec<R> out;
+        out.r[0] = r[0];
+        out.r[1] = r[1];
+        out.r[2] = r[2];
+        out.key = key;
+        out.u[0] = u[0];
+        out.u[1] = u[1];
+        out.u[2] = u[2];
         if (CHARGED && d.msc && na != A_ANNIH) {
             msc_deflect(d.seed, event, key, k0, T_pre, st, d.x0[mat], ud);
-            d.ux[s] = (R)ud[0]; d.uy[s] = (R)ud[1]; d.uz[s] = (R)ud[2];
+            out.u[0] = (R)ud[0];
+            out.u[1] = (R)ud[1];
+            out.u[2] = (R)ud[2];
         }
-        d.T[s] = T;
+        out.T = T;
+        store_track(d, s, out);
         d.nl[s] = nl;
         if (slab != slab0) d.slab[s] = slab;
         if (step != k0) d.step[s] = step;
@@ -1257,8 +1277,17 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
     }
     paused_n = paused ? 1u : 0u;
     if (paused) {
-        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-        d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
+        // the kinetic energy changes only at the end of the step
+        TrackRec<R> out;
+        out.r[0] = r[0];
+        out.r[1] = r[1];
+        out.r[2] = r[2];
+        out.key = key;
+        out.u[0] = (R)u[0];
+        out.u[1] = (R)u[1];
+        out.u[2] = (R)u[2];
+        out.T = in.T;
+        store_track(d, s, out);
         d.sdone[s] = s_done;
         d.htry[s] = h_try;
         d.nsearch[s] = (uint8_t)n_search;
@@ -1283,9 +1312,16 @@ __device__ __forceinline__ void along_field_track(const Dev<R>& d, const Tables<
     record_tally(d, row, slab0, tl);
     if (alive) {
         if (d.msc && na != A_ANNIH) msc_deflect(d.seed, event, key, k0, Td, s_done, d.x0[mat], u);
-        d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-        d.ux[s] = (R)u[0]; d.uy[s] = (R)u[1]; d.uz[s] = (R)u[2];
-        d.T[s] = T;
+        TrackRec<R> tr;
+        tr.r[0] = r[0];
+        tr.r[1] = r[1];
+        tr.r[2] = r[2];
+        tr.key = key;
+        tr.u[0] = (R)u[0];
+        tr.u[1] = (R)u[1];
+        tr.u[2] = (R)u[2];
+        tr.T = T;
+        store_track(d, s, tr);
         d.nl[s] = nl;
         if (slab != slab0) d.slab[s] = slab;
         if (step != k0) d.step[s] = step;
@@ -1545,8 +1581,16 @@ __device__ __forceinline__ void interact_track(const Dev<R>& d, uint32_t s, SecB
     }
     record_tally(d, row, slab, tl);
     if (p.alive) {
-        d.T[s] = p.T;
-        d.ux[s] = p.u[0]; d.uy[s] = p.u[1]; d.uz[s] = p.u[2];
+        TrackRec<R> out;
+        out.r[0] = r[0];
+        out.r[1] = r[1];
+        out.r[2] = r[2];
+        out.key = p.key;
+        out.u[0] = p.u[0];
+        out.u[1] = p.u[1];
+        out.u[2] = p.u[2];
+        out.T = p.T;
+        store_track(d, s, out);
         d.nl[s] = R(-1);
         d.action[s] = A_IDLE;
     } else {
