@@ -390,8 +390,9 @@ ems_status ems_sort_keys_noalloc(ems_ctx* ctx, const uint8_t* keys, uint64_t n, 
  * with few tracks: the first snapshot never starts it; 0xFFFFFFFF drains from
  * the first iteration on), each further
  * iteration fills the vacant slots and then runs one kernel in which every
- * block steps its own tracks in rounds, for up to drain_steps rounds (> 0):
- * half of a block's threads own occupied slots and half vacant ones,
+ * block steps its own tracks in rounds, for up to drain_steps rounds (> 0)
+ * of up to 4 steps per track: half of a block's threads own occupied slots
+ * and half vacant ones,
  * secondaries go onto the block's stack of 2048 records and threads with a
  * vacant slot take them (the rest go back to the initializer buffer).  It
  * removes the per-iteration launch latency of the last, nearly empty

@@ -134,6 +134,7 @@ constexpr uint32_t kDrainThreadsMax = 1u << 16;   // drain kernel threads (8 sta
 constexpr int kDrainDepth = 8;                     // private secondary stack depth per drain thread
 constexpr uint32_t kDrainStepsDefault = 4096;      // steps per drain thread and launch
 constexpr int kDrainSubsteps = 1024;               // field substeps per drain trip before a pause
+constexpr int kDrainBurst = 4;                     // steps per track and drain round
 
 // Host-visible snapshot copied to pinned memory after each batch
 struct Snapshot {

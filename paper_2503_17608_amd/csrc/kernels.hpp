@@ -1716,11 +1716,16 @@ __global__ void __launch_bounds__(kStepMaxBlock) k_interact_all(Dev<R> d)
 // latency, not by work.  A drain launch steps them without further launches:
 // each block runs its own small step loop in rounds.  Half of a block's
 // threads own occupied slots, half own vacant ones; in every round each
-// thread with a track takes one step -- pre-step, along-step and interaction,
-// through the same per-track functions as the action kernels -- and the
-// secondaries go onto the block's stack (LIFO); at the start of the next round
-// the threads whose slot is vacant take the newest entries.  A sub-shower so
-// spreads over the block's threads instead of one thread stepping it alone.
+// thread with a track takes up to kDrainBurst steps -- pre-step, along-step
+// and interaction, through the same per-track functions as the action
+// kernels -- and the secondaries go onto the block's stack (LIFO); at the
+// start of the next round the threads whose slot is vacant take the newest
+// entries.  A sub-shower so spreads over the block's threads instead of one
+// thread stepping it alone.  A thread knows from its own steps whether its
+// slot holds a track (a step that retires the track says so), so a round
+// reads no slot state beyond what the steps read; several steps per round
+// spread the round's barriers over them, which matters at the end, when a
+// few long-lived tracks are left.
 // After `max_steps` rounds, or when a block has neither tracks nor entries,
 // the block stops; its stack entries (and any that did not fit) go to the
 // initializer buffer for the step loop.  Random numbers are keyed by track
@@ -1826,24 +1831,31 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
         if (owns) s = d.vac[n_take + j];
     }
     unsigned long long ret_acc = 0, work = 0;
+    bool has = owns && d.type[s] != kDead;     // the thread's slot holds a track
     if (threadIdx.x == 0) top = 0;
     __syncthreads();
     for (uint32_t k = 0; k < max_steps; ++k) {
         // threads with a vacant slot take the newest entries of the stack
-        const bool idle = owns && d.type[s] == kDead;
+        const bool idle = owns && !has;
         uint32_t n_idle = 0;
         const uint32_t rank = block_rank(idle, wcnt, n_idle);
         const int avail = top;
-        if (idle && (int)rank < avail) init_slot(d, s, bstack[avail - 1 - (int)rank]);
+        if (idle && (int)rank < avail) {
+            init_slot(d, s, bstack[avail - 1 - (int)rank]);
+            has = true;
+        }
         __syncthreads();
         if (threadIdx.x == 0) top = avail - ((int)n_idle < avail ? (int)n_idle : avail);
         // no track left in the block: then its stack is empty too
-        const bool live = owns && d.type[s] != kDead;
-        if (!__syncthreads_or(live)) break;
-        if (live) {
+        if (!__syncthreads_or(has)) break;
+        for (int burst = 0; burst < kDrainBurst && has; ++burst) {
             // the along-step functions run the pre-step (a paused step is a
             // field step and resumes without one)
             const uint8_t a = along_action(d, s);
+            if (a == A_NONE) {      // (every retirement is reported; kept as a guard)
+                has = false;
+                break;
+            }
             uint32_t row = 0, retired = 0;
             uint8_t next = A_NONE;
             if (a == A_NEUTRAL) {
@@ -1851,7 +1863,7 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
             } else if (a == A_CHARGED) {
                 along_straight_track<R, true>(d, tb, s, row, next, retired);
             } else {
-                // a paused step resumes in the next round (pausing does not change the result)
+                // a paused step resumes at the thread's next step (pausing does not change the result)
                 uint32_t att = 0, paused_n = 0, pre_n = 0;
                 along_field_track<R>(d, tb, s, kDrainSubsteps, row, next, retired, att, paused_n, pre_n);
             }
@@ -1867,6 +1879,7 @@ __global__ void __launch_bounds__(256) k_drain(Dev<R> d, const uint32_t* live_li
             }
             ret_acc += retired;
             ++work;
+            has = retired == 0;     // a retired track has left its slot
         }
         __syncthreads();
         if (threadIdx.x == 0 && top > cap) top = cap;     // the excess went to the initializer buffer
