@@ -161,7 +161,8 @@ def parse():
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--drain-threshold", type=int, default=65536,
                     help="drain the last tracks in block-local loops below this many live+queued+pending (0 = off)")
-    ap.add_argument("--drain-steps", type=int, default=4096, help="steps per drain thread and launch")
+    ap.add_argument("--drain-steps", type=int, default=4096,
+                    help="drain rounds per launch (each of up to 4 steps per track)")
     ap.add_argument("--reuse-parent-slot", type=int, default=0, help="a finished track hands its slot to a secondary")
     ap.add_argument("--fuse-interactions", type=int, default=1, help="one launch for the seven interaction kernels")
     ap.add_argument("--phase-sort", type=lambda x: int(x, 0), nargs=2, default=[0x0, 0xFFFFFFFF],
