@@ -8,7 +8,8 @@
  *   - a step-based transport loop ("Stepping algorithm"): the host runs a
  *     loop of step iterations; each iteration is a sequence of kernels, one
  *     per stepping action, over a fixed array of track slots stored as a
- *     struct of arrays;
+ *     struct of arrays (here with position, direction, energy and key in
+ *     one 64-byte record per slot, since every step reads them together);
  *   - secondaries are pushed to a buffer of lightweight track initializers
  *     and vacant slots are filled from it at the start of every iteration;
  *     only the interaction kernels create them (a positron that stops in its

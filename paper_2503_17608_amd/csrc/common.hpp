@@ -2,8 +2,11 @@
 // action codes, counters and small device helpers.
 //
 // Track state is a struct of arrays over n_slots (paper, "Stepping
-// algorithm"): every per-track quantity is its own array so that a kernel
-// reading one field streams it contiguously from HBM.
+// algorithm"): a per-track quantity is its own array so that a kernel
+// reading one field over many slots streams it contiguously from HBM.  The
+// exception is the group that every step and every interaction reads and
+// writes together (position, direction, kinetic energy, random-number key):
+// it shares one 64-byte record per slot.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

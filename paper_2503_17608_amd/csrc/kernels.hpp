@@ -37,7 +37,8 @@ struct RecField {
 
 template <class R>
 struct Dev {
-    // track state (struct of arrays over n_slots)
+    // track state over n_slots: an array per field, except the RecField
+    // members (key, T, x, y, z, ux, uy, uz), which live in the 64-byte records
     uint8_t* type;
     uint8_t* action;
     uint8_t* flags;
