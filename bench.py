@@ -721,7 +721,8 @@ def main():
     }
     if r["tuned"] is not None:
         out["config"]["autotuned"] = {k: r["tuned"][k] for k in ("sort_policy", "tail_threshold", "block",
-                                                                 "fuse_interactions", "drain_threshold", "phase_sort")}
+                                                                 "fuse_interactions", "fuse_along", "drain_threshold",
+                                                                 "phase_sort")}
         out["config"]["autotuned"]["phase_choice"] = r["tuned"].get("phase_table", {}).get("choice")
     if prof_kernel and r["prof"].get(prof_kernel, (0, 0))[1] > 0:
         ms, launches = r["prof"][prof_kernel]
