@@ -613,11 +613,12 @@ void launch_iteration(ems_ctx* c, bool no_init, bool prof)
     const int bs_def = c->opt.block_size > 0 ? c->opt.block_size : 256;
     const uint32_t n = d.n_slots;
     const uint32_t nvb = (n + kVacBlock - 1) / kVacBlock;
+    const uint32_t nvs = (n + kVacSpan - 1) / kVacSpan;      // vacancy blocks
     auto B = [&](int role) { return c->block[role] > 0 ? c->block[role] : bs_def; };
     auto G = [&](int role) { return grid_for(n, B(role)); };
     hipStream_t st = c->stream;
-    ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
-    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1,
+    ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvs), dim3(kVacBlock), 0, st, d);
+    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvs), dim3(kVacBlock), 0, st, d, no_init ? 0 : 1,
          d.compact_along ? d.along_list : (uint32_t*)nullptr);
     if (!no_init) {
         if (d.fill_reserve) {
@@ -683,10 +684,11 @@ void launch_drain(ems_ctx* c, uint32_t threads)
     Launcher ln{c, c->prof_mask != 0};
     const uint32_t n = d.n_slots;
     const uint32_t nvb = (n + kVacBlock - 1) / kVacBlock;
+    const uint32_t nvs = (n + kVacSpan - 1) / kVacSpan;      // vacancy blocks
     hipStream_t st = c->stream;
     uint32_t* live_list = (uint32_t*)(c->ws + c->L.perm);
-    ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvb), dim3(kVacBlock), 0, st, d);
-    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvb), dim3(kVacBlock), 0, st, d, 1, live_list);
+    ln.k(R_VAC, true, false, k_vac_count<R>, dim3(nvs), dim3(kVacBlock), 0, st, d);
+    ln.k(R_VAC, false, true, k_vac_scatter<R>, dim3(nvs), dim3(kVacBlock), 0, st, d, 1, live_list);
     ln.one(R_INIT, k_init<R, false>, dim3(nvb), dim3(kVacBlock), 0, st, d);
     const size_t lds = d.stage_tables ? (size_t)d.n_tab * sizeof(R) : 0;
     ln.one(R_DRAIN, k_drain<R>, dim3((threads + 255) / 256), dim3(256), lds, st, d, (const uint32_t*)live_list,

@@ -276,12 +276,39 @@ __device__ uint32_t block_prefix(const uint32_t* cnt, uint32_t b, uint32_t* scra
 }
 
 // ---- vacancy compaction (ordered by slot index) ---------------------------------
+// Each thread of the two vacancy kernels covers kVacPer consecutive slots
+// (one 4-byte load of their type bytes), so a block covers kVacSpan slots and
+// the per-block counts that every block of the scatter adds up stay few
+// (256 at 2^20 slots, 2048 at 2^23).
+constexpr int kVacPer = 4;
+constexpr uint32_t kVacSpan = (uint32_t)kVacBlock * kVacPer;
+
+// Vacancy bits of the kVacPer slots from s0 (bit j: slot s0 + j), and how
+// many of those slots exist (fewer than kVacPer only at the end of the array).
+template <class R>
+__device__ __forceinline__ uint32_t vacant_bits(const Dev<R>& d, uint32_t s0, uint32_t& valid)
+{
+    static_assert(kVacPer == 4, "one 4-byte load per thread");
+    uint32_t m = 0;
+    if (s0 + kVacPer <= d.n_slots) {
+        // s0 is a multiple of 4 and the type array starts 256-byte aligned
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(d.type + s0);
+        for (int j = 0; j < kVacPer; ++j) m |= (uint32_t)(((w >> (8 * j)) & 0xFFu) == kDead) << j;
+        valid = kVacPer;
+    } else {
+        valid = s0 < d.n_slots ? d.n_slots - s0 : 0u;
+        for (uint32_t j = 0; j < valid; ++j) m |= (uint32_t)(d.type[s0 + j] == kDead) << j;
+    }
+    return m;
+}
+
 template <class R>
 __global__ void __launch_bounds__(kVacBlock) k_vac_count(Dev<R> d)
 {
-    uint32_t s = blockIdx.x * kVacBlock + threadIdx.x;
-    int v = (s < d.n_slots) && d.type[s] == kDead;
-    int c = __syncthreads_count(v);
+    const uint32_t s0 = (blockIdx.x * kVacBlock + threadIdx.x) * kVacPer;
+    uint32_t valid = 0;
+    const uint32_t m = vacant_bits(d, s0, valid);
+    const unsigned long long c = block_sum((unsigned long long)__popc(m));
     if (threadIdx.x == 0) d.vac_cnt[blockIdx.x] = (uint32_t)c;
 }
 
@@ -290,31 +317,37 @@ __global__ void __launch_bounds__(kVacBlock) k_vac_count(Dev<R> d)
 // then from the pending primaries.
 //
 // With live_out set, the occupied slots are also listed there in slot order
-// (n_slots - n_vac of them), for the drain kernel.
+// (n_slots - n_vac of them), for the drain kernel and the listed walk of the
+// along-steps.
 template <class R>
 __global__ void __launch_bounds__(kVacBlock) k_vac_scatter(Dev<R> d, int plan_fill, uint32_t* live_out)
 {
     __shared__ uint32_t red[kVacBlock / 64];
     __shared__ uint32_t wcnt[kVacBlock / 64];
-    __shared__ uint32_t wlive[kVacBlock / 64];
-    uint32_t prefix = block_prefix(d.vac_cnt, blockIdx.x, red);
-    uint32_t s = blockIdx.x * kVacBlock + threadIdx.x;
-    bool v = (s < d.n_slots) && d.type[s] == kDead;
-    uint64_t m = __ballot(v);
-    int w = threadIdx.x >> 6;
-    if (lane_id() == 0) wcnt[w] = (uint32_t)__popcll(m);
+    const uint32_t prefix = block_prefix(d.vac_cnt, blockIdx.x, red);
+    const uint32_t s0 = (blockIdx.x * kVacBlock + threadIdx.x) * kVacPer;
+    uint32_t valid = 0;
+    const uint32_t m = vacant_bits(d, s0, valid);
+    const uint32_t nv = (uint32_t)__popc(m);
+    // vacancies of the block's earlier threads: a wave scan, then the waves
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = nv;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wcnt[w] = x;
     __syncthreads();
-    uint32_t off = prefix;
-    for (int i = 0; i < w; ++i) off += wcnt[i];
-    if (v) d.vac[off + rank_below(m)] = s;
-    if (live_out) {                                   // block-uniform
-        bool l = (s < d.n_slots) && !v;
-        uint64_t ml = __ballot(l);
-        if (lane_id() == 0) wlive[w] = (uint32_t)__popcll(ml);
-        __syncthreads();
-        uint32_t lo = blockIdx.x * kVacBlock - prefix;   // occupied slots in earlier (full) blocks
-        for (int i = 0; i < w; ++i) lo += wlive[i];
-        if (l) live_out[lo + rank_below(ml)] = s;
+    uint32_t before = 0;
+    for (int i = 0; i < w; ++i) before += wcnt[i];
+    uint32_t off = prefix + before + x - nv;           // vacancies before slot s0
+    for (int j = 0; j < kVacPer; ++j)
+        if ((m >> j) & 1u) d.vac[off++] = s0 + (uint32_t)j;
+    if (live_out) {
+        // every slot before s0 exists, so the occupied ones number s0 - vacancies
+        uint32_t lo = s0 - (prefix + before + x - nv);
+        for (uint32_t j = 0; j < valid; ++j)
+            if (!((m >> j) & 1u)) live_out[lo++] = s0 + j;
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         uint32_t blk = 0;
