@@ -23,13 +23,15 @@ namespace ems {
 // (precision R) from 32.
 constexpr uint32_t kTrackRec = 64;
 
+// One field of the records, indexed by slot like an array.  Single-field
+// accesses go through it; the hot paths read and write whole records with
+// load_track / store_track (four 16-byte accesses), which the compiler does
+// not form from separate field accesses.
 template <class T, uint32_t OFF>
 struct RecField {
     char* base;   // the record of slot 0 (aligned to the record size)
     __device__ __forceinline__ T& operator[](size_t i) const
     {
-        // the alignment lets the compiler merge neighbouring fields of one
-        // record into 16-byte accesses
         char* rec = static_cast<char*>(__builtin_assume_aligned(base + i * kTrackRec, kTrackRec));
         return *reinterpret_cast<T*>(rec + OFF);
     }
@@ -133,7 +135,10 @@ struct alignas(16) TrackRec {
     R u[3];
     R T;
 };
-static_assert(sizeof(TrackRec<double>) == kTrackRec, "track record layout");
+static_assert(sizeof(TrackRec<double>) == kTrackRec && sizeof(TrackRec<float>) <= kTrackRec, "track record size");
+static_assert(offsetof(TrackRec<double>, key) == 24 && offsetof(TrackRec<double>, u) == 32 &&
+                  offsetof(TrackRec<double>, T) == 56 && offsetof(TrackRec<float>, T) == 44,
+              "track record layout (the RecField offsets of Dev)");
 
 template <class R>
 __device__ __forceinline__ TrackRec<R> load_track(const Dev<R>& d, uint32_t s)
